@@ -1,0 +1,232 @@
+/*
+ * fe.h -- C ABI of the MI355X (gfx950) finite element cell-kernel and
+ * assembly library.
+ *
+ * The library computes, for every simplex cell K of an affine mesh, the
+ * local element matrix of the mass or Poisson (stiffness) form with an
+ * optional coefficient z in the same Lagrange space,
+ *
+ *     A_K = sum_{s,t} B_s C_st B_t^T,   C_st = diag_q(w_q z(X_q) G_st)
+ *
+ * (Croci & Wells, Section 3.1, eq. triple_products; Algorithm 1 in
+ * Section 3.2), and assembles the global matrix A^g = L D L^T into CSR
+ * (Section 3.3).  B holds reference basis values (mass) or gradients
+ * (Poisson) at the quadrature points; G = |det J| (mass) or
+ * G = |det J| J^{-1} J^{-T} (Poisson) is the geometry tensor (Section 4.2).
+ *
+ * Conventions shared by every call:
+ *   - Every function returns an fe_status (0 = success).  Argument errors are
+ *     detected on the host before anything is enqueued; outputs are then
+ *     left untouched.  No C++ exception crosses this boundary.
+ *   - The caller owns all memory.  Device buffers are allocated by the
+ *     caller (for instance through PyTorch) and passed as plain pointers;
+ *     sizes of library-internal buffers are obtained by a size query
+ *     (NULL buffer, non-NULL size pointer).  The library never allocates or
+ *     frees device memory.
+ *   - Device work is enqueued on the caller's stream (hipStream_t passed as
+ *     void*; NULL = default stream).  Calls do not synchronise unless stated.
+ *   - Calls hold no global state and may be issued from several host threads
+ *     on distinct buffers.
+ *   - Floating-point results of the reduced/mixed precision modes are
+ *     deterministic for a given GPU, input and build: the numeric assembly
+ *     sums every CSR entry in a fixed order.
+ *
+ * Cell geometry is affine: J, det J and G are constant on a cell, computed
+ * once per cell in FP64 (the geometry precision u_g of List 1 is double).
+ */
+#ifndef FE_MI355X_FE_H
+#define FE_MI355X_FE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fe_status;
+
+enum {
+  FE_OK = 0,
+  FE_EINVAL = -1,       /* bad argument: NULL pointer, size, range, dof index */
+  FE_EUNSUPPORTED = -2, /* valid but not implemented: cell, degree, precision */
+  FE_EOVERFLOW = -3,    /* an index would not fit its integer type */
+  FE_EHIP = -4,         /* a HIP runtime call failed */
+  FE_EDEGENERATE = -5,  /* a cell has det J == 0 or non-finite geometry */
+  FE_ESIZE = -6         /* a caller buffer is smaller than the queried size */
+};
+
+/* Reference cells (Section 5.1): the triangle / tetrahedron with vertices
+ * 0, e_1, ..., e_d.  The value equals the dimension d. */
+enum { FE_TRIANGLE = 2, FE_TETRAHEDRON = 3 };
+
+/* Forms of Section 3.1. */
+enum { FE_MASS = 0, FE_STIFFNESS = 1 };
+
+/* Arithmetic of the contraction A = B^T H (List 1, Section 4.5):
+ *   FE_FP64            everything in double (u_s = u_q = u_g = FP64)
+ *   FE_FP32            B and H in single, single accumulation
+ *   FE_FP16_ACC32      B and H stored in half (u_s = FP16), products and
+ *                      accumulation in single on the matrix cores (u_q)
+ *   FE_BF16_ACC32      as above with bfloat16 storage
+ *   FE_SPLITFP16_ACC32 B and H each stored as a pair hi + 2^-11 lo of halves;
+ *                      three products hi*hi + 2^-11 (hi*lo + lo*hi), single
+ *                      accumulation.
+ * In all modes geometry is FP64 and H is formed in single (double for
+ * FE_FP64) from FP64 geometry and rounded once to the storage format. */
+enum {
+  FE_FP64 = 0,
+  FE_FP32 = 1,
+  FE_FP16_ACC32 = 2,
+  FE_BF16_ACC32 = 3,
+  FE_SPLITFP16_ACC32 = 4
+};
+
+/* Geometry precision u_g.  Only FP64 is implemented. */
+enum { FE_GEOM_FP64 = 0 };
+
+/* Phases of fe_assemble_csr. */
+enum { FE_SYMBOLIC_COUNT = 0, FE_SYMBOLIC_FILL = 1, FE_NUMERIC = 2 };
+
+typedef struct fe_form_desc {
+  int32_t cell;           /* FE_TRIANGLE or FE_TETRAHEDRON                     */
+  int32_t degree;         /* Lagrange degree p, 1 <= p <= 8                     */
+  int32_t quad_degree;    /* q >= 0: floor(q/2)+1 collapsed Gauss-Jacobi points
+                             per direction, at most 9 (q <= 17)                 */
+  int32_t form;           /* FE_MASS or FE_STIFFNESS                            */
+  int32_t has_coeff;      /* 1: multiply by z(X_q) = sum_k z_k phi_k(X_q)      */
+  int32_t precision;      /* FE_FP64 ... FE_SPLITFP16_ACC32                     */
+  int32_t geom_precision; /* FE_GEOM_FP64                                       */
+} fe_form_desc;
+
+typedef struct fe_mesh_view {
+  int64_t n_cells;
+  const double *cell_coords; /* device [n_cells][d+1][d] FP64; vertex k <-> e_k */
+  const int32_t *dofmap;     /* device [n_cells][n_phi], entries in [0, n_dofs) */
+  int64_t n_dofs;
+  const double *coeff;       /* device [n_dofs] nodal values z, or NULL         */
+} fe_mesh_view;
+
+typedef struct fe_csr {
+  int64_t n_rows;   /* = n_dofs                                               */
+  int64_t nnz;      /* written by FE_SYMBOLIC_COUNT                            */
+  int64_t *row_ptr; /* device [n_rows+1]                                       */
+  int32_t *col_idx; /* device [nnz], ascending and unique per row              */
+  void *values;     /* device [nnz], double for FE_FP64 else float             */
+} fe_csr;
+
+/* ------------------------------------------------------------------------
+ * fe_tabulate -- reference quadrature and basis tabulation (host, FP64).
+ *
+ * Algorithm 1 step 1; the tables B of Section 3.1 (B_skq = d_s phi_k(X_q) or
+ * phi_k(X_q)).  Quadrature: m = floor(q/2)+1 Gauss-Jacobi points per
+ * direction on [0,1] with weights (1-t)^0, (1-t)^1, (1-t)^2, collapsed onto
+ * the simplex (X = a(1-b)(1-c), Y = b(1-c), Z = c), a fastest.  Basis:
+ * equispaced-lattice Lagrange functions in product form (Appendix A),
+ * local order alpha_d outermost, alpha_1 innermost.
+ *   n_phi, n_q : out, always written on success
+ *   points     : out [n_q][d] or NULL
+ *   weights    : out [n_q] or NULL
+ *   table      : out [1 + d*nderiv][n_q][n_phi] or NULL: slab 0 = values,
+ *                slab 1+s = d/dX_s (nderiv = 1)
+ * Call with NULL buffers to query sizes.  Errors: FE_EINVAL (bad cell, p<1,
+ * q<0, nderiv not 0/1, NULL size pointers), FE_EUNSUPPORTED (p > 8,
+ * q > 17).  Synchronous; touches no device.
+ * ------------------------------------------------------------------------ */
+fe_status fe_tabulate(int32_t cell, int32_t degree, int32_t quad_degree, int32_t nderiv,
+                      int32_t *n_phi, int32_t *n_q, double *points, double *weights,
+                      double *table);
+
+/* ------------------------------------------------------------------------
+ * fe_form_prepare -- device copy of the tabulation in operand layout.
+ *
+ * Algorithm 1 step 1, device side: B rounded once from FP64 to the operand
+ * format of f->precision (hi/lo pair for the split mode) and packed in the
+ * lane order of the matrix-core instructions, the weighted table w_q B used
+ * to form H = C B^T in single (double for FE_FP64), and, with a
+ * coefficient, the value table used to evaluate z at the quadrature points.
+ * The buffer also holds a device status word (see fe_get_device_status).
+ *   form_buf   : device buffer of *form_bytes bytes, or NULL for a size query
+ *   form_bytes : in/out; on a query receives the required size; on a real
+ *                call must be >= that size (else FE_ESIZE)
+ * Synchronous with respect to the host (the upload is complete on return).
+ * Errors: FE_EINVAL, FE_EUNSUPPORTED, FE_ESIZE, FE_EHIP.
+ * ------------------------------------------------------------------------ */
+fe_status fe_form_prepare(const fe_form_desc *f, void *form_buf, size_t *form_bytes,
+                          void *stream);
+
+/* ------------------------------------------------------------------------
+ * fe_cell_kernels -- local element matrices of every cell (unassembled).
+ *
+ * Algorithm 1 steps 2-4 for all cells: FP64 geometry (J, det J, J^{-1},
+ * G; Section 4.2), the coefficient at the quadrature points when
+ * f->has_coeff (Lemma on FE function evaluation), H = C B^T formed on chip
+ * and the contraction A = B^T H on the matrix cores, cells batched 16 at a
+ * time along the N dimension (the cell batching of Section 3.1).
+ *   form_buf : prepared by fe_form_prepare for the same *f
+ *   A_local  : device [n_cells][n_phi][n_phi], row-major, row = first basis
+ *              index; double for FE_FP64, float otherwise
+ * Asynchronous.  A degenerate cell (det J == 0 or non-finite geometry)
+ * yields NaN entries for that cell and sets FE_EDEGENERATE in the status
+ * word of form_buf.  Errors: FE_EINVAL (NULL pointers, n_cells < 0, coeff
+ * missing while f->has_coeff), FE_EUNSUPPORTED, FE_EHIP.
+ * ------------------------------------------------------------------------ */
+fe_status fe_cell_kernels(const fe_form_desc *f, const void *form_buf, const fe_mesh_view *m,
+                          void *A_local, void *stream);
+
+/* ------------------------------------------------------------------------
+ * fe_assemble_csr -- global assembly A^g = L D L^T into CSR (Section 3.3).
+ *
+ * The CSR pattern is the set of pairs (dof(K,i), dof(K,j)) over all cells,
+ * rows in dof order, columns ascending and unique, explicit zeros kept.  It
+ * depends only on the dof map, so n_forms forms (for instance mass and
+ * stiffness) sharing one mesh share one pattern and one plan.
+ *
+ *   forms[n_forms], form_bufs[n_forms] : 1 <= n_forms <= 4; every form must
+ *       have the same cell and degree and all forms the same value type
+ *       (all FE_FP64 or none)
+ *   mats[n_forms] : output matrices; row_ptr/col_idx may be shared
+ *   plan / plan_bytes : device scratch owned by the caller, sized by a query
+ *       with plan == NULL; holds the dof-to-cell adjacency and the
+ *       position of every local entry inside its CSR row.  Its size depends
+ *       only on the mesh (n_cells, n_phi, n_dofs).
+ *   workspace / ws_bytes : device scratch for the numeric phase (local
+ *       matrices of all forms), sized by a query with workspace == NULL.
+ *
+ * Phases:
+ *   FE_SYMBOLIC_COUNT : fills mats[0].row_ptr and writes nnz into every
+ *       mats[f].nnz.  SYNCHRONISES the stream (nnz is read back).
+ *   FE_SYMBOLIC_FILL  : fills mats[0].col_idx (sorted) and the plan.
+ *       Asynchronous.  Errors: FE_EOVERFLOW when a row holds 65536 or more
+ *       entries (checked on the host after COUNT).
+ *   FE_NUMERIC : for every form, runs the cell kernels and sums every
+ *       CSR entry's contributions in the fixed order (cell ascending, then
+ *       local row), writing every value exactly once (no separate
+ *       zero-fill).  Asynchronous, never synchronises, bitwise repeatable.
+ * Errors: FE_EINVAL (NULL pointers, dof entries out of range are reported
+ * through the status word of the plan), FE_ESIZE, FE_EUNSUPPORTED, FE_EHIP.
+ * ------------------------------------------------------------------------ */
+fe_status fe_assemble_csr(const fe_form_desc *forms, const void *const *form_bufs,
+                          int32_t n_forms, const fe_mesh_view *m, int32_t phase,
+                          fe_csr *mats, void *plan, size_t *plan_bytes, void *workspace,
+                          size_t *ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * fe_get_device_status -- read and clear the status word of a form buffer
+ * or plan after the work that could set it.  Synchronises the stream.
+ * Returns FE_OK, FE_EDEGENERATE (a degenerate cell was met) or FE_EINVAL
+ * (a dof index was out of range), or FE_EHIP on a runtime failure.
+ * ------------------------------------------------------------------------ */
+fe_status fe_get_device_status(const void *form_buf_or_plan, void *stream);
+
+/* Static English description of a status code. */
+const char *fe_status_string(fe_status s);
+
+/* Library version, for diagnostics: "fe-mi355x <major>.<minor>". */
+const char *fe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FE_MI355X_FE_H */

@@ -1,0 +1,113 @@
+"""ctypes declarations of the C ABI in ``include/fe.h``.
+
+Loading fails loudly (``FeLibraryError``) when ``libfe.so`` has not been
+built: there is no fallback implementation of any step.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfe.so")
+
+# status codes
+FE_OK = 0
+FE_EINVAL = -1
+FE_EUNSUPPORTED = -2
+FE_EOVERFLOW = -3
+FE_EHIP = -4
+FE_EDEGENERATE = -5
+FE_ESIZE = -6
+
+FE_TRIANGLE = 2
+FE_TETRAHEDRON = 3
+FE_MASS = 0
+FE_STIFFNESS = 1
+FE_FP64 = 0
+FE_FP32 = 1
+FE_FP16_ACC32 = 2
+FE_BF16_ACC32 = 3
+FE_SPLITFP16_ACC32 = 4
+FE_GEOM_FP64 = 0
+FE_SYMBOLIC_COUNT = 0
+FE_SYMBOLIC_FILL = 1
+FE_NUMERIC = 2
+
+# every symbol declared in include/fe.h
+EXPORTS = (
+    "fe_tabulate",
+    "fe_form_prepare",
+    "fe_cell_kernels",
+    "fe_assemble_csr",
+    "fe_get_device_status",
+    "fe_status_string",
+    "fe_version",
+)
+
+
+class FeLibraryError(RuntimeError):
+    pass
+
+
+class fe_form_desc(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("cell", "degree", "quad_degree", "form", "has_coeff", "precision", "geom_precision")]
+
+
+class fe_mesh_view(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int64), ("cell_coords", ctypes.c_void_p),
+                ("dofmap", ctypes.c_void_p), ("n_dofs", ctypes.c_int64),
+                ("coeff", ctypes.c_void_p)]
+
+
+class fe_csr(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("values", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FeLibraryError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2410_12614_amd.build` "
+            "(there is no fallback path)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32 = ctypes.c_int32
+    lib.fe_tabulate.argtypes = [i32, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), P, P, P]
+    lib.fe_tabulate.restype = i32
+    lib.fe_form_prepare.argtypes = [ctypes.POINTER(fe_form_desc), P, ctypes.POINTER(ctypes.c_size_t), P]
+    lib.fe_form_prepare.restype = i32
+    lib.fe_cell_kernels.argtypes = [ctypes.POINTER(fe_form_desc), P, ctypes.POINTER(fe_mesh_view), P, P]
+    lib.fe_cell_kernels.restype = i32
+    lib.fe_assemble_csr.argtypes = [ctypes.POINTER(fe_form_desc), ctypes.POINTER(P), i32,
+                                    ctypes.POINTER(fe_mesh_view), i32, ctypes.POINTER(fe_csr), P,
+                                    ctypes.POINTER(ctypes.c_size_t), P,
+                                    ctypes.POINTER(ctypes.c_size_t), P]
+    lib.fe_assemble_csr.restype = i32
+    lib.fe_get_device_status.argtypes = [P, P]
+    lib.fe_get_device_status.restype = i32
+    lib.fe_status_string.argtypes = [i32]
+    lib.fe_status_string.restype = ctypes.c_char_p
+    lib.fe_version.argtypes = []
+    lib.fe_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+class FeError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = load().fe_status_string(status).decode()
+        super().__init__(f"{where}: {msg} (status {status})")
+        self.status = status
+
+
+def check(status: int, where: str) -> None:
+    if status != FE_OK:
+        raise FeError(status, where)

@@ -1,0 +1,170 @@
+"""Thin Python binding of the C ABI (argument marshalling only).
+
+Every function here forwards to ``libfe.so`` with the same name.  PyTorch
+provides device memory and the HIP stream; no step of the computation runs
+in Python.  ``Assembly`` is a convenience that allocates the caller-owned
+buffers the ABI asks for and issues the phases in order.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import check
+
+PRECISIONS = {
+    "fp64": L.FE_FP64,
+    "fp32": L.FE_FP32,
+    "fp16": L.FE_FP16_ACC32,
+    "bf16": L.FE_BF16_ACC32,
+    "split": L.FE_SPLITFP16_ACC32,
+}
+FORMS = {"mass": L.FE_MASS, "stiffness": L.FE_STIFFNESS}
+
+
+def form_desc(d: int, degree: int, quad_degree: int, form: str, precision: str = "fp64",
+              has_coeff: bool = False) -> L.fe_form_desc:
+    return L.fe_form_desc(cell=d, degree=degree, quad_degree=quad_degree, form=FORMS[form],
+                          has_coeff=int(bool(has_coeff)), precision=PRECISIONS[precision],
+                          geom_precision=L.FE_GEOM_FP64)
+
+
+def _stream(stream: Optional[torch.cuda.Stream]) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[ctypes.c_void_p]:
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def fe_tabulate(d: int, degree: int, quad_degree: int, nderiv: int = 1):
+    """(points [n_q][d], weights [n_q], table [1 + d*nderiv][n_q][n_phi]) in FP64 (host)."""
+    lib = L.load()
+    n_phi, n_q = ctypes.c_int32(0), ctypes.c_int32(0)
+    check(lib.fe_tabulate(d, degree, quad_degree, nderiv, ctypes.byref(n_phi), ctypes.byref(n_q),
+                          None, None, None), "fe_tabulate")
+    pts = np.zeros((n_q.value, d))
+    w = np.zeros(n_q.value)
+    tab = np.zeros((1 + d * nderiv, n_q.value, n_phi.value))
+    check(lib.fe_tabulate(d, degree, quad_degree, nderiv, ctypes.byref(n_phi), ctypes.byref(n_q),
+                          pts.ctypes.data_as(ctypes.c_void_p), w.ctypes.data_as(ctypes.c_void_p),
+                          tab.ctypes.data_as(ctypes.c_void_p)), "fe_tabulate")
+    return pts, w, tab
+
+
+def fe_form_prepare(desc: L.fe_form_desc, device="cuda", stream=None) -> torch.Tensor:
+    lib = L.load()
+    size = ctypes.c_size_t(0)
+    check(lib.fe_form_prepare(ctypes.byref(desc), None, ctypes.byref(size), None), "fe_form_prepare")
+    buf = torch.empty(size.value, dtype=torch.uint8, device=device)
+    check(lib.fe_form_prepare(ctypes.byref(desc), _ptr(buf), ctypes.byref(size), _stream(stream)),
+          "fe_form_prepare")
+    return buf
+
+
+@dataclass
+class MeshView:
+    """Device views of a mesh: coords [n_cells][d+1][d] f64, dofmap [n_cells][n_phi] i32."""
+
+    coords: torch.Tensor
+    dofmap: torch.Tensor
+    n_dofs: int
+    coeff: Optional[torch.Tensor] = None
+
+    @classmethod
+    def from_numpy(cls, coords, dofmap, n_dofs, coeff=None, device="cuda") -> "MeshView":
+        c = torch.from_numpy(np.ascontiguousarray(coords, dtype=np.float64)).to(device)
+        m = torch.from_numpy(np.ascontiguousarray(dofmap, dtype=np.int32)).to(device)
+        z = None if coeff is None else torch.from_numpy(np.ascontiguousarray(coeff, dtype=np.float64)).to(device)
+        return cls(c, m, int(n_dofs), z)
+
+    def struct(self) -> L.fe_mesh_view:
+        for t, dt in ((self.coords, torch.float64), (self.dofmap, torch.int32)):
+            if t.dtype != dt or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError("mesh tensors must be contiguous device tensors (f64 coords, i32 dofmap)")
+        if self.coeff is not None and (self.coeff.dtype != torch.float64 or not self.coeff.is_contiguous()):
+            raise ValueError("coeff must be a contiguous f64 device tensor")
+        return L.fe_mesh_view(n_cells=self.coords.shape[0], cell_coords=self.coords.data_ptr(),
+                              dofmap=self.dofmap.data_ptr(), n_dofs=self.n_dofs,
+                              coeff=None if self.coeff is None else self.coeff.data_ptr())
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.coords.shape[0])
+
+
+def fe_cell_kernels(desc: L.fe_form_desc, form_buf: torch.Tensor, mesh: MeshView,
+                    A_local: torch.Tensor, stream=None) -> None:
+    mv = mesh.struct()
+    check(L.load().fe_cell_kernels(ctypes.byref(desc), _ptr(form_buf), ctypes.byref(mv),
+                                   _ptr(A_local), _stream(stream)), "fe_cell_kernels")
+
+
+def fe_get_device_status(buf: torch.Tensor, stream=None) -> int:
+    return int(L.load().fe_get_device_status(_ptr(buf), _stream(stream)))
+
+
+def fe_assemble_csr(descs: Sequence[L.fe_form_desc], form_bufs: Sequence[Optional[torch.Tensor]],
+                    mesh: MeshView, phase: int, mats: "ctypes.Array", plan: Optional[torch.Tensor],
+                    workspace: Optional[torch.Tensor], stream=None,
+                    plan_bytes: Optional[ctypes.c_size_t] = None,
+                    ws_bytes: Optional[ctypes.c_size_t] = None) -> int:
+    n = len(descs)
+    darr = (L.fe_form_desc * n)(*descs)
+    barr = (ctypes.c_void_p * n)(*[None if b is None else b.data_ptr() for b in form_bufs])
+    mv = mesh.struct()
+    pb = plan_bytes if plan_bytes is not None else ctypes.c_size_t(0 if plan is None else plan.numel())
+    wb = ws_bytes if ws_bytes is not None else ctypes.c_size_t(0 if workspace is None else workspace.numel())
+    st = L.load().fe_assemble_csr(darr, barr, n, ctypes.byref(mv), phase, mats, _ptr(plan),
+                                  ctypes.byref(pb), _ptr(workspace), ctypes.byref(wb), _stream(stream))
+    return st
+
+
+class Assembly:
+    """Caller-side orchestration: sizes and allocates the buffers of the ABI
+    (form buffers, plan, CSR arrays, workspace) with torch, then runs the
+    symbolic phases once and the numeric phase on demand."""
+
+    def __init__(self, mesh: MeshView, descs: Sequence[L.fe_form_desc], stream=None):
+        self.mesh = mesh
+        self.descs = list(descs)
+        self.stream = stream
+        dev = mesh.coords.device
+        self.form_bufs = [fe_form_prepare(d, dev, stream) for d in self.descs]
+        n = len(self.descs)
+        self.mats = (L.fe_csr * n)()
+        pb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        check(fe_assemble_csr(self.descs, [None] * n, mesh, L.FE_NUMERIC, self.mats, None, None,
+                              stream, pb, wb), "fe_assemble_csr(size query)")
+        self.plan = torch.empty(pb.value, dtype=torch.uint8, device=dev)
+        self.workspace = torch.empty(wb.value, dtype=torch.uint8, device=dev)
+        self.row_ptr = torch.empty(mesh.n_dofs + 1, dtype=torch.int64, device=dev)
+        for k in range(n):
+            self.mats[k].n_rows = mesh.n_dofs
+            self.mats[k].row_ptr = self.row_ptr.data_ptr()
+        check(fe_assemble_csr(self.descs, self.form_bufs, mesh, L.FE_SYMBOLIC_COUNT, self.mats,
+                              self.plan, None, stream), "fe_assemble_csr(COUNT)")
+        self.nnz = int(self.mats[0].nnz)
+        self.col_idx = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
+        vdt = torch.float64 if self.descs[0].precision == L.FE_FP64 else torch.float32
+        self.values = [torch.empty(max(self.nnz, 1), dtype=vdt, device=dev) for _ in range(n)]
+        for k in range(n):
+            self.mats[k].col_idx = self.col_idx.data_ptr()
+            self.mats[k].values = self.values[k].data_ptr()
+        check(fe_assemble_csr(self.descs, self.form_bufs, mesh, L.FE_SYMBOLIC_FILL, self.mats,
+                              self.plan, None, stream), "fe_assemble_csr(FILL)")
+
+    def numeric(self) -> list:
+        check(fe_assemble_csr(self.descs, self.form_bufs, self.mesh, L.FE_NUMERIC, self.mats,
+                              self.plan, self.workspace, self.stream), "fe_assemble_csr(NUMERIC)")
+        return self.values
+
+    def status(self) -> list:
+        return [fe_get_device_status(b, self.stream) for b in self.form_bufs] + \
+               [fe_get_device_status(self.plan, self.stream)]

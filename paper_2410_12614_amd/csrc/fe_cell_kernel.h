@@ -1,0 +1,458 @@
+// Cell kernel: local element matrices A_K = B^T H_K on the gfx950 matrix cores.
+//
+// Algorithm 1 (Section 3.2) with the one-H-per-s variant of the remark that
+// follows it, read as H_s = sum_t C_st B_t^T, so that A = sum_s B_s H_s is a
+// single contraction over K = (s, q), s < n_d.  Cells are batched 16 at a
+// time (cell batching, Section 3.1) and laid along the N dimension of
+// 16 x 16 x KSTEP matrix-core tiles:
+//
+//     [A_c(i, j)]_{i, c} = sum_k  B^T(i, k) * H_c(k, j)     for one column j,
+//
+// so the left operand B^T (rows i, shared by all cells) is read from the
+// prepared form buffer in lane order, and the right operand (16 cells x
+// KSTEP values of H for one j) is formed in registers:
+//
+//     H_c((s, q), j) = sigma_c z_c(X_q) sum_t G_c(s, t) (w_q B_t(q, j)),
+//
+// from FP64 geometry (J, det J, adj J; Section 4.2) rounded once to the
+// operand format.  sigma_c = 2^e_c is an exact per-cell power of two that
+// keeps H inside the FP16 range (the paper notes FP16 underflow of geometry
+// terms and leaves scaling open); it is undone exactly on the FP32
+// accumulator.  The left operand B^T carries its own exact power-of-two
+// scale (stored in the form header) for the same reason: the matrix cores
+// flush FP16 subnormal inputs.  The coefficient z at the quadrature points is the FE
+// function evaluation z_q = sum_k z_k phi_k(X_q) with u_p = u^2 relative
+// to the storage format: single for FP16/BF16, double for FP32, the split
+// pair and FP64 (the list of precisions and the mixed-precision strategy of
+// Section 4.5).
+//
+// Workgroup: 256 threads = 4 waves.  Lane l of a wave owns cell c = l % 16
+// and K-slot kb = l / 16; wave w handles columns j in [pass*4*JC + w*JC, +JC).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "fe_internal.h"
+
+namespace fe {
+
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+// ---- precision policies -------------------------------------------------
+// A/B operand layout of every 16x16 instruction used here: lane l holds
+// rows/cols (l % 16) and K entries (l / 16) * KPL + e.  Output: lane l holds
+// column l % 16 and rows row(l / 16, r), r < 4 (checked on gfx950).
+
+struct PolF16 {
+  static constexpr int KSTEP = 32, KPL = 8, REGMUL = 1;
+  static constexpr bool SPLIT = false, SCALED = true;
+  typedef float real;
+  typedef float zreal;  // coefficient evaluation: u_p = u^2 for FP16 storage
+  typedef f32x4_t acc;
+  typedef half8_t frag;
+  static __device__ __forceinline__ frag load(const unsigned char *base, size_t idx) {
+    return *(const frag *)(base + idx * 16);
+  }
+  static __device__ __forceinline__ frag pack(const float *h) {
+    frag f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) f[e] = (_Float16)h[e];
+    return f;
+  }
+  static __device__ __forceinline__ acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kb, int r) { return 4 * kb + r; }
+};
+
+struct PolBF16 {
+  static constexpr int KSTEP = 32, KPL = 8, REGMUL = 1;
+  static constexpr bool SPLIT = false, SCALED = true;
+  typedef float real;
+  typedef float zreal;
+  typedef f32x4_t acc;
+  typedef bf16x8_t frag;
+  static __device__ __forceinline__ frag load(const unsigned char *base, size_t idx) {
+    return *(const frag *)(base + idx * 16);
+  }
+  static __device__ __forceinline__ frag pack(const float *h) {
+    frag f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) f[e] = (__bf16)h[e];
+    return f;
+  }
+  static __device__ __forceinline__ acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kb, int r) { return 4 * kb + r; }
+};
+
+// hi + 2^-11 lo pairs of halves; products hi*hi into one accumulator and
+// hi*lo + lo*hi into another, combined once at the end.
+struct PolSplit {
+  static constexpr int KSTEP = 32, KPL = 8, REGMUL = 2;
+  static constexpr bool SPLIT = true, SCALED = true;
+  typedef float real;
+  typedef double zreal;  // the pair carries ~22 bits: u^2 calls for double
+  typedef f32x4_t acc;
+  typedef half8_t frag;
+  static __device__ __forceinline__ frag load(const unsigned char *base, size_t idx) {
+    return *(const frag *)(base + idx * 16);
+  }
+  static __device__ __forceinline__ void pack2(const float *h, frag &hi, frag &lo) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      _Float16 x = (_Float16)h[e];
+      hi[e] = x;
+      lo[e] = (_Float16)((h[e] - (float)x) * 2048.0f);
+    }
+  }
+  static __device__ __forceinline__ acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kb, int r) { return 4 * kb + r; }
+};
+
+struct PolF32 {
+  static constexpr int KSTEP = 4, KPL = 1, REGMUL = 1;
+  static constexpr bool SPLIT = false, SCALED = true;
+  typedef float real;
+  typedef double zreal;
+  typedef f32x4_t acc;
+  typedef float frag;
+  static __device__ __forceinline__ frag load(const unsigned char *base, size_t idx) {
+    return ((const float *)base)[idx];
+  }
+  static __device__ __forceinline__ frag pack(const float *h) { return h[0]; }
+  static __device__ __forceinline__ acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kb, int r) { return 4 * kb + r; }
+};
+
+struct PolF64 {
+  static constexpr int KSTEP = 4, KPL = 1, REGMUL = 2;
+  static constexpr bool SPLIT = false, SCALED = false;
+  typedef double real;
+  typedef double zreal;
+  typedef f64x4_t acc;
+  typedef double frag;
+  static __device__ __forceinline__ frag load(const unsigned char *base, size_t idx) {
+    return ((const double *)base)[idx];
+  }
+  static __device__ __forceinline__ frag pack(const double *h) { return h[0]; }
+  static __device__ __forceinline__ acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // the FP64 instruction interleaves its output rows
+  static __device__ __forceinline__ int row(int kb, int r) { return kb + 4 * r; }
+};
+
+// ---- kernel arguments -----------------------------------------------------
+struct KArgs {
+  const unsigned char *afrag;     // B^T fragments (hi for split)
+  const unsigned char *afrag_lo;  // split mode
+  const void *wtab;               // [NDT][n_phi][n_q_pad], float or double
+  const void *vtab;               // [n_q][n_phi], zreal
+  const FormHeader *hdr;
+  int32_t *status;
+  const double *coords;
+  const int32_t *dofmap;
+  const double *coeff;
+  void *A;
+  int64_t n_cells, n_dofs;
+  int d, nd, n_phi, n_q, n_q_pad, nks;
+};
+
+// FP64 geometry of one affine simplex: G = |det J| J^{-1} J^{-T} computed as
+// adj(J) adj(J)^T / |det J| (cofactor inverse; any inverse meeting the
+// paper's inverse assumption may be used).  Returns false when det J == 0 or
+// a value is not finite.
+__device__ __forceinline__ bool cell_geometry(int d, const double *x, double G[3][3],
+                                              double &adet) {
+  double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) J[i][j] = x[(j + 1) * d + i] - x[i];
+  double adj[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  double det;
+  if (d == 3) {
+    adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
+  } else {
+    adj[0][0] = J[1][1];
+    adj[0][1] = -J[0][1];
+    adj[1][0] = -J[1][0];
+    adj[1][1] = J[0][0];
+    det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  }
+  adet = fabs(det);
+  const double r = 1.0 / adet;
+  bool ok = (det != 0.0) && isfinite(det);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += adj[i][k] * adj[j][k];
+      G[i][j] = s * r;
+      ok = ok && isfinite(G[i][j]);
+    }
+  return ok;
+}
+
+template <class P, int MT, int JC, int NDT, bool COEFF>
+__global__ __launch_bounds__(256) void cell_kernel(KArgs a) {
+  typedef typename P::real T;
+  typedef typename P::zreal Z;
+  typedef typename P::acc ACC;
+  typedef typename P::frag FRAG;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int c = lane & 15, kb = lane >> 4;
+  const int64_t cell0 = (int64_t)blockIdx.x * 16;
+  const int64_t cell = cell0 + c;
+  const bool valid = cell < a.n_cells;
+  const int d = a.d, nphi = a.n_phi, n_q_pad = a.n_q_pad;
+
+  // ---- geometry (Section 4.2), one lane per cell, FP64 ----
+  double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  double adet = 0.0;
+  bool ok = true;
+  if (valid) ok = cell_geometry(d, a.coords + cell * (d + 1) * d, G, adet);
+
+  // ---- coefficient at the quadrature points (FE function evaluation) ----
+  Z *zq = (Z *)smem;                                            // [n_q_pad][16]
+  double *zloc = (double *)(smem + (size_t)16 * n_q_pad * sizeof(Z));  // [16][n_phi]
+  double zmax = 1.0;
+  if constexpr (COEFF) {
+    for (int idx = tid; idx < 16 * nphi; idx += 256) {
+      const int cc = idx / nphi, k = idx - cc * nphi;
+      const int64_t ce = cell0 + cc;
+      double z = 0.0;
+      if (ce < a.n_cells) {
+        const int32_t g = a.dofmap[ce * nphi + k];
+        if (g >= 0 && g < a.n_dofs) z = a.coeff[g];
+        else atomicOr(a.status, STATUS_BAD_DOF);
+      }
+      zloc[idx] = z;
+    }
+    __syncthreads();
+    const Z *vt = (const Z *)a.vtab;
+    double zpart = 0.0;   // this thread's |z_q| maximum for cell tid % 16
+    for (int idx = tid; idx < 16 * n_q_pad; idx += 256) {
+      const int q = idx >> 4, cc = idx & 15;
+      Z z = 0;
+      if (q < a.n_q)
+        for (int k = 0; k < nphi; ++k) z += (Z)zloc[cc * nphi + k] * vt[q * nphi + k];
+      zq[idx] = z;
+      zpart = fmax(zpart, fabs((double)z));
+    }
+    __shared__ double zred[256];
+    zred[tid] = zpart;
+    __syncthreads();
+    // max_q |z_q| of this lane's cell (threads tid and tid + 16 r share tid % 16)
+    double m = 0.0;
+    for (int r = 0; r < 16; ++r) m = fmax(m, zred[c + 16 * r]);
+    zmax = m;
+  }
+
+  // ---- per-cell exact power-of-two scale ----
+  double gabs = adet;
+  if (a.nd > 1) {
+    gabs = 0.0;
+    for (int s = 0; s < 3; ++s) gabs = fmax(gabs, fabs(G[s][0]) + fabs(G[s][1]) + fabs(G[s][2]));
+  }
+  double sK = 1.0;
+  if constexpr (P::SCALED) {
+    // |H| <= sK * max|w B| * max_s sum_t |G_st| * max_q |z_q| < 2^15 <= FP16 max
+    const double bound = a.hdr->max_wb * gabs * zmax;
+    if (bound > 0.0 && isfinite(bound)) sK = ldexp(1.0, 14 - ilogb(bound));
+  }
+  if (valid && !ok) {
+    if (lane < 16 && wave == 0) atomicOr(a.status, STATUS_DEGENERATE);
+  }
+  T Gp[3][3];
+  for (int s = 0; s < 3; ++s)
+    for (int t = 0; t < 3; ++t) {
+      double v = (a.nd == 1) ? (s == 0 && t == 0 ? adet : 0.0) : G[s][t];
+      if (!valid) v = 0.0;
+      else if (!ok) v = NAN;
+      Gp[s][t] = (T)(v * sK);
+    }
+  const T inv = (T)(1.0 / (sK * a.hdr->b_scale));
+
+  const T *wt = (const T *)a.wtab;
+  const int npass = (nphi + 4 * JC - 1) / (4 * JC);
+  for (int pass = 0; pass < npass; ++pass) {
+    const int jb = pass * 4 * JC + wave * JC;
+    if (jb >= nphi) continue;
+    ACC acc[MT][JC];
+    ACC acc2[P::SPLIT ? MT : 1][P::SPLIT ? JC : 1];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int jj = 0; jj < JC; ++jj) {
+        acc[mt][jj] = ACC{0, 0, 0, 0};
+        if constexpr (P::SPLIT) acc2[mt][jj] = ACC{0, 0, 0, 0};
+      }
+    for (int ks = 0; ks < a.nks; ++ks) {
+      const int k0 = ks * P::KSTEP;
+      const int s = k0 / n_q_pad;
+      const int qb = k0 - s * n_q_pad + kb * P::KPL;
+      FRAG afr[MT];
+      FRAG afl[P::SPLIT ? MT : 1];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const size_t fi = ((size_t)mt * a.nks + ks) * 64 + lane;
+        afr[mt] = P::load(a.afrag, fi);
+        if constexpr (P::SPLIT) afl[mt] = P::load(a.afrag_lo, fi);
+      }
+      T g[NDT];
+#pragma unroll
+      for (int t = 0; t < NDT; ++t) g[t] = (s == 0) ? Gp[0][t] : ((s == 1) ? Gp[1][t] : Gp[2][t]);
+      T zf[P::KPL];
+      if constexpr (COEFF) {
+#pragma unroll
+        for (int e = 0; e < P::KPL; ++e) zf[e] = (T)zq[(qb + e) * 16 + c];
+      }
+#pragma unroll
+      for (int jj = 0; jj < JC; ++jj) {
+        const int jl = min(jb + jj, nphi - 1);
+        T h[P::KPL];
+#pragma unroll
+        for (int e = 0; e < P::KPL; ++e) h[e] = 0;
+#pragma unroll
+        for (int t = 0; t < NDT; ++t) {
+          const T *w = wt + ((size_t)t * nphi + jl) * n_q_pad + qb;
+          T wv[P::KPL];
+          if constexpr (P::KPL == 8) {
+            const float4 w0 = ((const float4 *)w)[0], w1 = ((const float4 *)w)[1];
+            wv[0] = w0.x; wv[1] = w0.y; wv[2] = w0.z; wv[3] = w0.w;
+            wv[4] = w1.x; wv[5] = w1.y; wv[6] = w1.z; wv[7] = w1.w;
+          } else {
+            wv[0] = w[0];
+          }
+#pragma unroll
+          for (int e = 0; e < P::KPL; ++e) h[e] += g[t] * wv[e];
+        }
+        if constexpr (COEFF) {
+#pragma unroll
+          for (int e = 0; e < P::KPL; ++e) h[e] *= zf[e];
+        }
+        if constexpr (P::SPLIT) {
+          FRAG hh, hl;
+          P::pack2(h, hh, hl);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            acc[mt][jj] = P::mma(afr[mt], hh, acc[mt][jj]);
+            acc2[mt][jj] = P::mma(afr[mt], hl, acc2[mt][jj]);
+            acc2[mt][jj] = P::mma(afl[mt], hh, acc2[mt][jj]);
+          }
+        } else {
+          const FRAG hf = P::pack(h);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) acc[mt][jj] = P::mma(afr[mt], hf, acc[mt][jj]);
+        }
+      }
+    }
+    if (valid) {
+      T *A = (T *)a.A + (size_t)cell * nphi * nphi;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int jj = 0; jj < JC; ++jj) {
+          const int j = jb + jj;
+          if (j < nphi) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int i = mt * 16 + P::row(kb, r);
+              if (i < nphi) {
+                T v = acc[mt][jj][r];
+                if constexpr (P::SPLIT) v += acc2[mt][jj][r] * (T)(1.0 / 2048.0);
+                A[(size_t)i * nphi + j] = v * inv;
+              }
+            }
+          }
+        }
+    }
+  }
+}
+
+template <class P, int MT, int JC, int NDT, bool COEFF>
+static fe_status launch_one(const KArgs &k, int64_t n_cells, size_t smem, hipStream_t s) {
+  auto kern = cell_kernel<P, MT, JC, NDT, COEFF>;
+  if (smem > 65536) {
+    if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)smem) != hipSuccess)
+      return FE_EHIP;
+  }
+  const int64_t blocks = (n_cells + 15) / 16;
+  if (blocks > INT32_MAX) return FE_EOVERFLOW;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), smem, s, k);
+  return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
+}
+
+template <class P, int MT, int JC>
+static fe_status launch_mt(const KArgs &k, int64_t n_cells, size_t smem, hipStream_t s, int ndt,
+                           bool coeff) {
+  if (ndt == 1)
+    return coeff ? launch_one<P, MT, JC, 1, true>(k, n_cells, smem, s)
+                 : launch_one<P, MT, JC, 1, false>(k, n_cells, smem, s);
+  return coeff ? launch_one<P, MT, JC, 3, true>(k, n_cells, smem, s)
+               : launch_one<P, MT, JC, 3, false>(k, n_cells, smem, s);
+}
+
+template <class P>
+fe_status launch_cell_impl(const CellLaunch &a) {
+  const FormLayout &L = *a.L;
+  int mt, jc;
+  tile_choice(L.n_phi, P::REGMUL, &mt, &jc);
+  KArgs k;
+  k.afrag = a.form_buf + L.off_afrag;
+  k.afrag_lo = a.form_buf + L.off_afrag_lo;
+  k.wtab = a.form_buf + L.off_wtab;
+  k.vtab = a.form_buf + L.off_vtab;
+  k.hdr = (const FormHeader *)a.form_buf;
+  k.status = a.status;
+  k.coords = a.coords;
+  k.dofmap = a.dofmap;
+  k.coeff = a.coeff;
+  k.A = a.A_local;
+  k.n_cells = a.n_cells;
+  k.n_dofs = a.n_dofs;
+  k.d = L.d;
+  k.nd = L.nd;
+  k.n_phi = L.n_phi;
+  k.n_q = L.n_q;
+  k.n_q_pad = L.n_q_pad;
+  k.nks = L.nks;
+  const bool coeff = L.has_coeff != 0;
+  const size_t smem =
+      coeff ? (size_t)16 * L.n_q_pad * sizeof(typename P::zreal) + (size_t)16 * L.n_phi * 8 : 0;
+  hipStream_t s = (hipStream_t)a.stream;
+  const int ndt = L.ndt;
+#define FE_CASE(M, J) \
+  if (mt == M && jc == J) return launch_mt<P, M, J>(k, a.n_cells, smem, s, ndt, coeff);
+  if constexpr (P::REGMUL == 1) {
+    FE_CASE(1, 4) FE_CASE(2, 8) FE_CASE(3, 9) FE_CASE(4, 7) FE_CASE(6, 7) FE_CASE(8, 6)
+    FE_CASE(11, 3)
+  } else {
+    FE_CASE(1, 4) FE_CASE(2, 8) FE_CASE(3, 9) FE_CASE(4, 7) FE_CASE(6, 3) FE_CASE(8, 3)
+    FE_CASE(11, 2)
+  }
+#undef FE_CASE
+  return FE_EUNSUPPORTED;
+}
+
+}  // namespace fe

@@ -1,0 +1,6 @@
+// Cell-kernel instantiations for one precision (see fe_cell_kernel.h).
+#include "fe_cell_kernel.h"
+
+namespace fe {
+fe_status launch_cell_split(const CellLaunch &a) { return launch_cell_impl<PolSplit>(a); }
+}  // namespace fe

@@ -1,0 +1,505 @@
+// Global assembly A^g = L D L^T into CSR (Section 3.3).
+//
+// Symbolic phases (once per dof map):
+//   COUNT: dof -> (cell, local index) adjacency by counting sort, every
+//          adjacency list sorted so the order is deterministic; per row, the
+//          dofs of all incident cells are sorted (bitonic, in LDS) and
+//          de-duplicated to give the row length; an inclusive scan gives
+//          row_ptr.
+//   FILL:  the same per-row sort writes col_idx; then every local entry
+//          (K, i, j) gets its position inside CSR row dof(K, i) as a 16-bit
+//          rank (binary search of dof(K, j) in that row).
+// Numeric phase (every call):
+//   the cell kernels write the local matrices of all forms to the
+//   workspace; one wave per CSR row then sums, in the fixed order of the
+//   sorted adjacency list (cell ascending, then local row), the local rows
+//   A_K(i, :) of the incident cells into an LDS window at their ranks and
+//   writes the row once, coalesced.  No atomics touch values, so the result
+//   is bitwise repeatable.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "fe_internal.h"
+
+namespace fe {
+namespace {
+
+struct PlanHeader {
+  int32_t status;
+  int32_t magic;
+  int64_t n_cells, n_dofs;
+  int32_t n_phi, pad;
+  int64_t nnz, max_deg, max_len;
+};
+constexpr int32_t PLAN_MAGIC = 0x46455043;  // "FEPC"
+
+struct PlanLayout {
+  size_t off_adj_ptr, off_cursor, off_adj, off_rank, off_scan, total;
+  size_t scan_blocks;
+};
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+constexpr int SCAN_TILE = 2048;  // elements per scan block (256 threads x 8)
+
+PlanLayout plan_layout(int64_t n_cells, int n_phi, int64_t n_dofs) {
+  PlanLayout P;
+  size_t off = 256;
+  P.off_adj_ptr = off;
+  off = a256(off + sizeof(int64_t) * (n_dofs + 1));
+  P.off_cursor = off;
+  off = a256(off + sizeof(int64_t) * n_dofs);
+  P.off_adj = off;
+  off = a256(off + sizeof(int64_t) * (size_t)n_cells * n_phi);
+  P.off_rank = off;
+  off = a256(off + sizeof(uint16_t) * (size_t)n_cells * n_phi * n_phi);
+  P.scan_blocks = (size_t)(n_dofs + 1 + SCAN_TILE - 1) / SCAN_TILE;
+  P.off_scan = off;
+  off = a256(off + sizeof(int64_t) * (P.scan_blocks + 1));
+  P.total = off;
+  return P;
+}
+
+// ---------------------------------------------------------------- kernels
+__global__ void k_fill_i64(int64_t *x, int64_t n, int64_t v) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    x[t] = v;
+}
+
+__global__ void k_degree(const int32_t *dofmap, int64_t n_entries, int64_t n_dofs,
+                         int64_t *deg /* [n_dofs+1], counts at g+1 */, int32_t *status) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_entries;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t g = dofmap[e];
+    if (g < 0 || g >= n_dofs) {
+      atomicOr(status, STATUS_BAD_DOF);
+      continue;
+    }
+    atomicAdd((unsigned long long *)&deg[g + 1], 1ull);
+  }
+}
+
+// Inclusive scan of x[0..n) in tiles of SCAN_TILE: per-tile scan + tile totals.
+__global__ void k_scan_tiles(int64_t *x, int64_t n, int64_t *tile_sum) {
+  __shared__ int64_t part[256];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * 8;
+  int64_t v[8], run = 0;
+  for (int e = 0; e < 8; ++e) {
+    const int64_t idx = base + e;
+    v[e] = idx < n ? x[idx] : 0;
+    run += v[e];
+    v[e] = run;
+  }
+  part[threadIdx.x] = run;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    int64_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  const int64_t prefix = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0;
+  for (int e = 0; e < 8; ++e) {
+    const int64_t idx = base + e;
+    if (idx < n) x[idx] = v[e] + prefix;
+  }
+  if (threadIdx.x == 255) tile_sum[blockIdx.x] = part[255];
+}
+
+__global__ void k_scan_totals(int64_t *tile_sum, int64_t nt) {
+  // single block: exclusive scan of tile totals, serial per chunk
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+      int64_t v = tile_sum[t];
+      tile_sum[t] = run;
+      run += v;
+    }
+  }
+}
+
+__global__ void k_scan_add(int64_t *x, int64_t n, const int64_t *tile_off) {
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  const int64_t add = tile_off[blockIdx.x];
+  for (int e = threadIdx.x; e < SCAN_TILE; e += blockDim.x) {
+    const int64_t idx = base + e;
+    if (idx < n) x[idx] += add;
+  }
+}
+
+__global__ void k_fill_adj(const int32_t *dofmap, int64_t n_cells, int n_phi, int64_t n_dofs,
+                           const int64_t *adj_ptr, int64_t *cursor, int64_t *adj) {
+  const int64_t n = n_cells * n_phi;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t g = dofmap[e];
+    if (g < 0 || g >= n_dofs) continue;
+    const int64_t K = e / n_phi, i = e - K * n_phi;
+    const unsigned long long p = atomicAdd((unsigned long long *)&cursor[g], 1ull);
+    adj[adj_ptr[g] + (int64_t)p] = K * 256 + i;
+  }
+}
+
+// Insertion sort of every adjacency list (lists are short: cells around a dof).
+__global__ void k_sort_adj(const int64_t *adj_ptr, int64_t *adj, int64_t n_dofs,
+                           int64_t *max_deg) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_dofs) return;
+  const int64_t a0 = adj_ptr[g], a1 = adj_ptr[g + 1];
+  for (int64_t a = a0 + 1; a < a1; ++a) {
+    const int64_t v = adj[a];
+    int64_t b = a - 1;
+    while (b >= a0 && adj[b] > v) {
+      adj[b + 1] = adj[b];
+      --b;
+    }
+    adj[b + 1] = v;
+  }
+  atomicMax((unsigned long long *)max_deg, (unsigned long long)(a1 - a0));
+}
+
+// One workgroup per row: gather the dofs of every incident cell, bitonic sort
+// in LDS, de-duplicate.  count mode: row length into rowlen[g+1]; fill mode:
+// unique columns into col_idx[row_ptr[g] ...].
+__global__ __launch_bounds__(256) void k_rows(const int32_t *dofmap, int n_phi,
+                                              const int64_t *adj_ptr, const int64_t *adj,
+                                              int64_t row0, int64_t n_rows, int64_t *rowlen,
+                                              const int64_t *row_ptr, int32_t *col_idx,
+                                              int64_t *max_len) {
+  extern __shared__ int32_t buf[];
+  __shared__ int32_t cnt[256];
+  const int64_t g = row0 + blockIdx.x;
+  if (g >= n_rows) return;
+  const int64_t a0 = adj_ptr[g], a1 = adj_ptr[g + 1];
+  const int n = (int)((a1 - a0) * n_phi);
+  int npow = 1;
+  while (npow < n) npow <<= 1;
+  for (int t = threadIdx.x; t < npow; t += 256) {
+    int32_t v = INT32_MAX;
+    if (t < n) {
+      const int64_t ent = adj[a0 + t / n_phi];
+      v = dofmap[(ent >> 8) * n_phi + (t % n_phi)];
+    }
+    buf[t] = v;
+  }
+  __syncthreads();
+  for (int k = 2; k <= npow; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < npow; t += 256) {
+        const int ixj = t ^ j;
+        if (ixj > t) {
+          const int32_t a = buf[t], b = buf[ixj];
+          const bool up = (t & k) == 0;
+          if ((a > b) == up) {
+            buf[t] = b;
+            buf[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  // per-thread contiguous chunk of the sorted array
+  const int chunk = (npow + 255) / 256;
+  const int s0 = threadIdx.x * chunk;
+  int local = 0;
+  for (int t = s0; t < min(s0 + chunk, n); ++t)
+    if (t == 0 || buf[t] != buf[t - 1]) ++local;
+  cnt[threadIdx.x] = local;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    int add = threadIdx.x >= off ? cnt[threadIdx.x - off] : 0;
+    __syncthreads();
+    cnt[threadIdx.x] += add;
+    __syncthreads();
+  }
+  if (rowlen) {
+    if (threadIdx.x == 0) {
+      rowlen[g + 1] = cnt[255];
+      atomicMax((unsigned long long *)max_len, (unsigned long long)cnt[255]);
+    }
+    return;
+  }
+  int pos = threadIdx.x > 0 ? cnt[threadIdx.x - 1] : 0;
+  int32_t *out = col_idx + row_ptr[g];
+  for (int t = s0; t < min(s0 + chunk, n); ++t)
+    if (t == 0 || buf[t] != buf[t - 1]) out[pos++] = buf[t];
+}
+
+// One wave per local row (K, i): rank of every dof(K, j) inside CSR row dof(K, i).
+__global__ __launch_bounds__(256) void k_ranks(const int32_t *dofmap, int64_t n_cells, int n_phi,
+                                               const int64_t *row_ptr, const int32_t *col_idx,
+                                               uint16_t *rank) {
+  const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (e >= n_cells * n_phi) return;
+  const int64_t K = e / n_phi;
+  const int32_t g = dofmap[e];
+  const int64_t r0 = row_ptr[g];
+  const int64_t len = row_ptr[g + 1] - r0;
+  const int32_t *row = col_idx + r0;
+  for (int j = lane; j < n_phi; j += 64) {
+    const int32_t h = dofmap[K * n_phi + j];
+    int64_t lo = 0, hi = len;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (row[mid] < h) lo = mid + 1;
+      else hi = mid;
+    }
+    rank[e * n_phi + j] = (uint16_t)lo;
+  }
+}
+
+// Numeric gather: one wave per CSR row, NF forms, LDS window of W entries.
+template <class T, int NF>
+__global__ __launch_bounds__(256) void k_gather(const int64_t *adj_ptr, const int64_t *adj,
+                                                const uint16_t *rank, const int64_t *row_ptr,
+                                                int64_t n_rows, int n_phi, int W,
+                                                const T *A0, const T *A1, const T *A2,
+                                                const T *A3, T *V0, T *V1, T *V2, T *V3) {
+  extern __shared__ __align__(16) unsigned char gsm[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * 4 + wave;
+  if (g >= n_rows) return;
+  T *buf = (T *)gsm + (size_t)wave * NF * W;
+  const T *A[4] = {A0, A1, A2, A3};
+  T *V[4] = {V0, V1, V2, V3};
+  const int64_t r0 = row_ptr[g];
+  const int len = (int)(row_ptr[g + 1] - r0);
+  const int64_t a0 = adj_ptr[g], a1 = adj_ptr[g + 1];
+  for (int w0 = 0; w0 < len; w0 += W) {
+    const int wl = min(W, len - w0);
+    for (int r = lane; r < wl; r += 64)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) buf[f * W + r] = 0;
+    for (int64_t a = a0; a < a1; ++a) {
+      const int64_t ent = adj[a];
+      const size_t base = ((size_t)(ent >> 8) * n_phi + (ent & 255)) * n_phi;
+      for (int j = lane; j < n_phi; j += 64) {
+        const int r = (int)rank[base + j] - w0;
+        if (r >= 0 && r < wl) {
+#pragma unroll
+          for (int f = 0; f < NF; ++f) buf[f * W + r] += A[f][base + j];
+        }
+      }
+    }
+    for (int r = lane; r < wl; r += 64)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) V[f][r0 + w0 + r] = buf[f * W + r];
+  }
+}
+
+template <class T, int NF>
+fe_status launch_gather(const int64_t *adj_ptr, const int64_t *adj, const uint16_t *rank,
+                        const int64_t *row_ptr, int64_t n_rows, int n_phi, void *const *A,
+                        void *const *V, hipStream_t s) {
+  const int W = (int)(16384 / (NF * sizeof(T)));  // 16 KiB of LDS per wave
+  const size_t smem = (size_t)4 * NF * W * sizeof(T);
+  const int64_t blocks = (n_rows + 3) / 4;
+  auto kern = k_gather<T, NF>;
+  if (smem > 65536 && hipFuncSetAttribute((const void *)kern,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)smem) != hipSuccess)
+    return FE_EHIP;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), smem, s, adj_ptr, adj, rank, row_ptr,
+                     n_rows, n_phi, W, (const T *)A[0], (const T *)A[1], (const T *)A[2],
+                     (const T *)A[3], (T *)V[0], (T *)V[1], (T *)V[2], (T *)V[3]);
+  return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
+}
+
+unsigned grid_for(int64_t n, int block) {
+  int64_t b = (n + block - 1) / block;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 65536 * 4));
+}
+
+fe_status scan_inclusive(int64_t *x, int64_t n, int64_t *scratch, size_t tiles, hipStream_t s) {
+  if (n <= 0) return FE_OK;
+  const int64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+  if ((size_t)nt > tiles) return FE_EINVAL;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(256), 0, s, x, n, scratch);
+  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(64), 0, s, scratch, nt);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nt), dim3(256), 0, s, x, n, scratch);
+  return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
+}
+
+bool sync_ok(hipStream_t s) { return hipStreamSynchronize(s) == hipSuccess; }
+
+}  // namespace
+}  // namespace fe
+
+using namespace fe;
+
+extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *const *form_bufs,
+                                     int32_t n_forms, const fe_mesh_view *m, int32_t phase,
+                                     fe_csr *mats, void *plan, size_t *plan_bytes,
+                                     void *workspace, size_t *ws_bytes, void *stream) {
+  if (!forms || n_forms < 1 || n_forms > 4 || !m) return FE_EINVAL;
+  FormLayout L[4];
+  for (int f = 0; f < n_forms; ++f) {
+    fe_status st = compute_layout(&forms[f], &L[f]);
+    if (st != FE_OK) return st;
+    if (forms[f].cell != forms[0].cell || forms[f].degree != forms[0].degree) return FE_EINVAL;
+    if ((forms[f].precision == FE_FP64) != (forms[0].precision == FE_FP64)) return FE_EINVAL;
+  }
+  if (m->n_cells < 0 || m->n_dofs < 1) return FE_EINVAL;
+  if (m->n_dofs >= INT32_MAX) return FE_EOVERFLOW;
+  const int n_phi = L[0].n_phi;
+  const int64_t n_cells = m->n_cells, n_dofs = m->n_dofs;
+  const size_t elt = (forms[0].precision == FE_FP64) ? 8 : 4;
+  const PlanLayout P = plan_layout(n_cells, n_phi, n_dofs);
+  const size_t ws_need = std::max<size_t>(256, (size_t)n_forms * n_cells * n_phi * n_phi * elt);
+  if (!plan || (phase == FE_NUMERIC && !workspace)) {
+    if (!plan_bytes && !ws_bytes) return FE_EINVAL;
+    if (plan_bytes) *plan_bytes = P.total;
+    if (ws_bytes) *ws_bytes = ws_need;
+    return FE_OK;
+  }
+  if (plan_bytes && *plan_bytes < P.total) return FE_ESIZE;
+  if (!mats || !mats[0].row_ptr) return FE_EINVAL;
+  if (n_cells > 0 && (!m->dofmap || !m->cell_coords)) return FE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned char *pb = (unsigned char *)plan;
+  PlanHeader *hdr_d = (PlanHeader *)pb;
+  int64_t *adj_ptr = (int64_t *)(pb + P.off_adj_ptr);
+  int64_t *cursor = (int64_t *)(pb + P.off_cursor);
+  int64_t *adj = (int64_t *)(pb + P.off_adj);
+  uint16_t *rank = (uint16_t *)(pb + P.off_rank);
+  int64_t *scan = (int64_t *)(pb + P.off_scan);
+  int64_t *row_ptr = mats[0].row_ptr;
+
+  if (phase == FE_SYMBOLIC_COUNT) {
+    PlanHeader h;
+    std::memset(&h, 0, sizeof(h));
+    h.magic = PLAN_MAGIC;
+    h.n_cells = n_cells;
+    h.n_dofs = n_dofs;
+    h.n_phi = n_phi;
+    if (hipMemcpyAsync(hdr_d, &h, sizeof(h), hipMemcpyHostToDevice, s) != hipSuccess) return FE_EHIP;
+    hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n_dofs + 1, 256)), dim3(256), 0, s, adj_ptr,
+                       n_dofs + 1, (int64_t)0);
+    hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n_dofs, 256)), dim3(256), 0, s, cursor, n_dofs,
+                       (int64_t)0);
+    hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n_dofs + 1, 256)), dim3(256), 0, s, row_ptr,
+                       n_dofs + 1, (int64_t)0);
+    if (n_cells > 0) {
+      hipLaunchKernelGGL(k_degree, dim3(grid_for(n_cells * n_phi, 256)), dim3(256), 0, s, m->dofmap,
+                         n_cells * n_phi, n_dofs, adj_ptr, &hdr_d->status);
+      fe_status st = scan_inclusive(adj_ptr + 1, n_dofs, scan, P.scan_blocks, s);
+      if (st != FE_OK) return st;
+      hipLaunchKernelGGL(k_fill_adj, dim3(grid_for(n_cells * n_phi, 256)), dim3(256), 0, s,
+                         m->dofmap, n_cells, n_phi, n_dofs, adj_ptr, cursor, adj);
+      hipLaunchKernelGGL(k_sort_adj, dim3((unsigned)((n_dofs + 255) / 256)), dim3(256), 0, s,
+                         adj_ptr, adj, n_dofs, &hdr_d->max_deg);
+    }
+    if (!sync_ok(s)) return FE_EHIP;
+    if (hipMemcpy(&h, hdr_d, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return FE_EHIP;
+    if (h.status & STATUS_BAD_DOF) return FE_EINVAL;
+    const int64_t ncand = h.max_deg * n_phi;
+    int64_t cap = 1;
+    while (cap < ncand) cap <<= 1;
+    if (cap > 32768) return FE_EUNSUPPORTED;
+    const size_t smem = sizeof(int32_t) * (size_t)std::max<int64_t>(cap, 1);
+    if (smem > 65536 && hipFuncSetAttribute((const void *)k_rows,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)smem) != hipSuccess)
+      return FE_EHIP;
+    for (int64_t r0 = 0; r0 < n_dofs; r0 += (int64_t)1 << 30)
+      hipLaunchKernelGGL(k_rows, dim3((unsigned)std::min<int64_t>(n_dofs - r0, (int64_t)1 << 30)),
+                         dim3(256), smem, s, m->dofmap, n_phi, adj_ptr, adj, r0, n_dofs, row_ptr,
+                         (const int64_t *)nullptr, (int32_t *)nullptr, &hdr_d->max_len);
+    fe_status st = scan_inclusive(row_ptr + 1, n_dofs, scan, P.scan_blocks, s);
+    if (st != FE_OK) return st;
+    if (!sync_ok(s)) return FE_EHIP;
+    int64_t nnz = 0;
+    if (hipMemcpy(&nnz, row_ptr + n_dofs, sizeof(nnz), hipMemcpyDeviceToHost) != hipSuccess)
+      return FE_EHIP;
+    if (hipMemcpy(&h, hdr_d, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return FE_EHIP;
+    h.nnz = nnz;
+    if (hipMemcpy(hdr_d, &h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess) return FE_EHIP;
+    for (int f = 0; f < n_forms; ++f) {
+      mats[f].n_rows = n_dofs;
+      mats[f].nnz = nnz;
+    }
+    if (h.max_len >= 65536) return FE_EOVERFLOW;
+    return FE_OK;
+  }
+
+  PlanHeader h;
+  if (phase == FE_SYMBOLIC_FILL) {
+    if (!mats[0].col_idx) return FE_EINVAL;
+    if (!sync_ok(s)) return FE_EHIP;
+    if (hipMemcpy(&h, hdr_d, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return FE_EHIP;
+    if (h.magic != PLAN_MAGIC || h.n_cells != n_cells || h.n_dofs != n_dofs || h.n_phi != n_phi)
+      return FE_EINVAL;
+    if (h.max_len >= 65536) return FE_EOVERFLOW;
+    const int64_t ncand = h.max_deg * n_phi;
+    int64_t cap = 1;
+    while (cap < ncand) cap <<= 1;
+    const size_t smem = sizeof(int32_t) * (size_t)std::max<int64_t>(cap, 1);
+    if (smem > 65536 && hipFuncSetAttribute((const void *)k_rows,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)smem) != hipSuccess)
+      return FE_EHIP;
+    for (int64_t r0 = 0; r0 < n_dofs; r0 += (int64_t)1 << 30)
+      hipLaunchKernelGGL(k_rows, dim3((unsigned)std::min<int64_t>(n_dofs - r0, (int64_t)1 << 30)),
+                         dim3(256), smem, s, m->dofmap, n_phi, adj_ptr, adj, r0, n_dofs,
+                         (int64_t *)nullptr, (const int64_t *)row_ptr, mats[0].col_idx,
+                         &hdr_d->max_len);
+    if (n_cells > 0) {
+      const int64_t ne = n_cells * n_phi;
+      hipLaunchKernelGGL(k_ranks, dim3((unsigned)((ne + 3) / 4)), dim3(256), 0, s, m->dofmap,
+                         n_cells, n_phi, (const int64_t *)row_ptr, mats[0].col_idx, rank);
+    }
+    if (hipGetLastError() != hipSuccess) return FE_EHIP;
+    if (!sync_ok(s)) return FE_EHIP;
+    return FE_OK;
+  }
+
+  if (phase != FE_NUMERIC) return FE_EINVAL;
+  if (ws_bytes && *ws_bytes < ws_need) return FE_ESIZE;
+  if (!mats[0].col_idx) return FE_EINVAL;
+  for (int f = 0; f < n_forms; ++f)
+    if (!form_bufs || !form_bufs[f] || !mats[f].values) return FE_EINVAL;
+  if (n_cells == 0) return FE_OK;  // values of an empty pattern: nothing to write
+  void *Aloc[4] = {nullptr, nullptr, nullptr, nullptr};
+  void *V[4] = {nullptr, nullptr, nullptr, nullptr};
+  const size_t stride = (size_t)n_cells * n_phi * n_phi * elt;
+  for (int f = 0; f < n_forms; ++f) {
+    Aloc[f] = (unsigned char *)workspace + f * stride;
+    V[f] = mats[f].values;
+    fe_mesh_view mv = *m;
+    CellLaunch a;
+    a.L = &L[f];
+    a.form_buf = (const unsigned char *)form_bufs[f];
+    a.status = (int32_t *)form_bufs[f];
+    a.n_cells = n_cells;
+    a.coords = mv.cell_coords;
+    a.dofmap = mv.dofmap;
+    a.n_dofs = n_dofs;
+    a.coeff = forms[f].has_coeff ? mv.coeff : nullptr;
+    if (forms[f].has_coeff && !mv.coeff) return FE_EINVAL;
+    a.A_local = Aloc[f];
+    a.stream = stream;
+    fe_status st = launch_cell(a);
+    if (st != FE_OK) return st;
+  }
+  fe_status st = FE_EINVAL;
+  if (elt == 8) {
+    switch (n_forms) {
+      case 1: st = launch_gather<double, 1>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
+      case 2: st = launch_gather<double, 2>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
+      case 3: st = launch_gather<double, 3>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
+      case 4: st = launch_gather<double, 4>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
+    }
+  } else {
+    switch (n_forms) {
+      case 1: st = launch_gather<float, 1>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
+      case 2: st = launch_gather<float, 2>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
+      case 3: st = launch_gather<float, 3>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
+      case 4: st = launch_gather<float, 4>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
+    }
+  }
+  return st;
+}

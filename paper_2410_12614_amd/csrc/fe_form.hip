@@ -1,0 +1,244 @@
+// Form preparation (device operand tables), cell-kernel entry point and
+// device status readback.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "fe_internal.h"
+
+namespace fe {
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+fe_status check_form(const fe_form_desc *f) {
+  if (!f) return FE_EINVAL;
+  if (f->cell != FE_TRIANGLE && f->cell != FE_TETRAHEDRON) return FE_EINVAL;
+  if (f->degree < 1 || f->quad_degree < 0) return FE_EINVAL;
+  if (f->form != FE_MASS && f->form != FE_STIFFNESS) return FE_EINVAL;
+  if (f->has_coeff != 0 && f->has_coeff != 1) return FE_EINVAL;
+  if (f->precision < FE_FP64 || f->precision > FE_SPLITFP16_ACC32) return FE_EINVAL;
+  if (f->geom_precision != FE_GEOM_FP64) return FE_EUNSUPPORTED;
+  if (f->degree > FE_MAX_DEGREE || f->quad_degree > FE_MAX_QUAD_DEGREE) return FE_EUNSUPPORTED;
+  return FE_OK;
+}
+
+void tile_choice(int n_phi, int regmul, int *mt, int *jc) {
+  const int m = (n_phi + 15) / 16;
+  static const int jc1[12] = {0, 4, 8, 9, 7, 0, 7, 0, 6, 0, 0, 3};
+  static const int jc2[12] = {0, 4, 8, 9, 7, 0, 3, 0, 3, 0, 0, 2};
+  *mt = m;
+  *jc = (m >= 1 && m <= 11) ? (regmul == 1 ? jc1[m] : jc2[m]) : 0;
+}
+
+fe_status compute_layout(const fe_form_desc *f, FormLayout *L) {
+  fe_status st = check_form(f);
+  if (st != FE_OK) return st;
+  std::memset(L, 0, sizeof(*L));
+  L->d = f->cell;
+  L->form = f->form;
+  L->nd = (f->form == FE_MASS) ? 1 : L->d;
+  L->ndt = (f->form == FE_MASS) ? 1 : 3;
+  L->n_phi = simplex_dim(L->d, f->degree);
+  const int m = f->quad_degree / 2 + 1;
+  L->n_q = (L->d == 2) ? m * m : m * m * m;
+  L->prec = f->precision;
+  L->has_coeff = f->has_coeff;
+  const bool mfma16 = (f->precision == FE_FP16_ACC32 || f->precision == FE_BF16_ACC32 ||
+                       f->precision == FE_SPLITFP16_ACC32);
+  L->kstep = mfma16 ? 32 : 4;
+  L->kpl = mfma16 ? 8 : 1;
+  L->n_q_pad = (L->n_q + L->kstep - 1) / L->kstep * L->kstep;
+  L->k_pad = L->nd * L->n_q_pad;
+  L->nks = L->k_pad / L->kstep;
+  int jc;
+  tile_choice(L->n_phi, 1, &L->mt, &jc);
+  if (jc == 0) return FE_EUNSUPPORTED;
+  L->elt_bytes = mfma16 ? 2 : (f->precision == FE_FP64 ? 8 : 4);
+  L->tab_bytes = (f->precision == FE_FP64) ? 8 : 4;
+  L->vtab_bytes = (f->precision == FE_FP16_ACC32 || f->precision == FE_BF16_ACC32) ? 4 : 8;
+  size_t off = HEADER_BYTES;
+  const size_t afrag = (size_t)L->mt * L->nks * 64 * L->kpl * L->elt_bytes;
+  L->off_afrag = off;
+  off = align256(off + afrag);
+  L->off_afrag_lo = off;
+  if (f->precision == FE_SPLITFP16_ACC32) off = align256(off + afrag);
+  L->off_wtab = off;
+  off = align256(off + (size_t)L->ndt * L->n_phi * L->n_q_pad * L->tab_bytes);
+  L->off_vtab = off;
+  if (L->has_coeff) off = align256(off + (size_t)L->n_q * L->n_phi * L->vtab_bytes);
+  L->total = off;
+  return FE_OK;
+}
+
+namespace {
+
+template <class T>
+void put(unsigned char *base, size_t off, size_t idx, T v) {
+  std::memcpy(base + off + idx * sizeof(T), &v, sizeof(T));
+}
+
+void store_elt(int prec, unsigned char *buf, size_t off, size_t lo_off, size_t idx, double x) {
+  switch (prec) {
+    case FE_FP64: put<double>(buf, off, idx, x); break;
+    case FE_FP32: put<float>(buf, off, idx, (float)x); break;
+    case FE_FP16_ACC32: put<_Float16>(buf, off, idx, (_Float16)x); break;
+    case FE_BF16_ACC32: put<__bf16>(buf, off, idx, (__bf16)x); break;
+    case FE_SPLITFP16_ACC32: {
+      _Float16 hi = (_Float16)x;
+      _Float16 lo = (_Float16)((x - (double)hi) * 2048.0);
+      put<_Float16>(buf, off, idx, hi);
+      put<_Float16>(buf, lo_off, idx, lo);
+      break;
+    }
+  }
+}
+
+}  // namespace
+}  // namespace fe
+
+using namespace fe;
+
+extern "C" fe_status fe_form_prepare(const fe_form_desc *f, void *form_buf, size_t *form_bytes,
+                                     void *stream) {
+  FormLayout L;
+  fe_status st = compute_layout(f, &L);
+  if (st != FE_OK) return st;
+  if (!form_bytes) return FE_EINVAL;
+  if (!form_buf) {
+    *form_bytes = L.total;
+    return FE_OK;
+  }
+  if (*form_bytes < L.total) return FE_ESIZE;
+  int32_t nphi, nq;
+  st = fe_tabulate(f->cell, f->degree, f->quad_degree, 1, &nphi, &nq, nullptr, nullptr, nullptr);
+  if (st != FE_OK) return st;
+  const int d = L.d;
+  std::vector<double> pts((size_t)nq * d), w(nq), tab((size_t)(1 + d) * nq * nphi);
+  st = fe_tabulate(f->cell, f->degree, f->quad_degree, 1, &nphi, &nq, pts.data(), w.data(),
+                   tab.data());
+  if (st != FE_OK) return st;
+  const size_t slab = (size_t)nq * nphi;
+  auto Bop = [&](int s, int q, int i) -> double {
+    return (L.form == FE_MASS) ? tab[(size_t)q * nphi + i] : tab[(1 + s) * slab + (size_t)q * nphi + i];
+  };
+  std::vector<unsigned char> h(L.total, 0);
+  FormHeader hdr;
+  std::memset(&hdr, 0, sizeof(hdr));
+  hdr.magic = FORM_MAGIC;
+  hdr.d = d;
+  hdr.nd = L.nd;
+  hdr.n_phi = nphi;
+  hdr.n_q = nq;
+  hdr.prec = L.prec;
+  hdr.form = L.form;
+  // B^T fragments.  In the 16-bit modes B is scaled by an exact power of two
+  // so that max |B| lies in [2^14, 2^15): small tabulated values then stay
+  // normal numbers instead of being flushed by the matrix cores.
+  double max_b = 0.0;
+  for (int s = 0; s < L.nd; ++s)
+    for (int q = 0; q < nq; ++q)
+      for (int i = 0; i < nphi; ++i) max_b = std::max(max_b, std::fabs(Bop(s, q, i)));
+  double b_scale = 1.0;
+  if (L.elt_bytes == 2 && max_b > 0.0) b_scale = std::ldexp(1.0, 14 - std::ilogb(max_b));
+  hdr.b_scale = b_scale;
+  for (int mt = 0; mt < L.mt; ++mt)
+    for (int ks = 0; ks < L.nks; ++ks)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int e = 0; e < L.kpl; ++e) {
+          const int i = 16 * mt + lane % 16;
+          const int k = ks * L.kstep + (lane / 16) * L.kpl + e;
+          const int s = k / L.n_q_pad, q = k % L.n_q_pad;
+          double v = (i < nphi && q < nq && s < L.nd) ? Bop(s, q, i) * b_scale : 0.0;
+          size_t idx = (((size_t)mt * L.nks + ks) * 64 + lane) * L.kpl + e;
+          store_elt(L.prec, h.data(), L.off_afrag, L.off_afrag_lo, idx, v);
+        }
+  // weighted table w_q B_t(q, j), [t][j][n_q_pad]
+  double max_wb = 0.0;
+  for (int t = 0; t < L.ndt; ++t)
+    for (int j = 0; j < nphi; ++j)
+      for (int q = 0; q < L.n_q_pad; ++q) {
+        double v = 0.0;
+        if (q < nq && t < L.nd) v = w[q] * Bop(t, q, j);
+        max_wb = std::max(max_wb, std::fabs(v));
+        size_t idx = ((size_t)t * nphi + j) * L.n_q_pad + q;
+        if (L.tab_bytes == 8) put<double>(h.data(), L.off_wtab, idx, v);
+        else put<float>(h.data(), L.off_wtab, idx, (float)v);
+      }
+  double leb = 0.0;
+  for (int q = 0; q < nq; ++q) {
+    double s = 0.0;
+    for (int k = 0; k < nphi; ++k) s += std::fabs(tab[(size_t)q * nphi + k]);
+    leb = std::max(leb, s);
+  }
+  if (L.has_coeff)
+    for (int q = 0; q < nq; ++q)
+      for (int k = 0; k < nphi; ++k) {
+        double v = tab[(size_t)q * nphi + k];
+        size_t idx = (size_t)q * nphi + k;
+        if (L.vtab_bytes == 8) put<double>(h.data(), L.off_vtab, idx, v);
+        else put<float>(h.data(), L.off_vtab, idx, (float)v);
+      }
+  hdr.max_wb = max_wb;
+  hdr.lebesgue = leb;
+  std::memcpy(h.data(), &hdr, sizeof(hdr));
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(form_buf, h.data(), L.total, hipMemcpyHostToDevice, s) != hipSuccess)
+    return FE_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return FE_EHIP;
+  return FE_OK;
+}
+
+namespace fe {
+fe_status launch_cell(const CellLaunch &a) {
+  switch (a.L->prec) {
+    case FE_FP64: return launch_cell_fp64(a);
+    case FE_FP32: return launch_cell_fp32(a);
+    case FE_FP16_ACC32: return launch_cell_fp16(a);
+    case FE_BF16_ACC32: return launch_cell_bf16(a);
+    case FE_SPLITFP16_ACC32: return launch_cell_split(a);
+  }
+  return FE_EUNSUPPORTED;
+}
+}  // namespace fe
+
+extern "C" fe_status fe_cell_kernels(const fe_form_desc *f, const void *form_buf,
+                                     const fe_mesh_view *m, void *A_local, void *stream) {
+  FormLayout L;
+  fe_status st = compute_layout(f, &L);
+  if (st != FE_OK) return st;
+  if (!form_buf || !m || m->n_cells < 0 || m->n_dofs < 1) return FE_EINVAL;
+  if (m->n_cells == 0) return FE_OK;
+  if (!m->cell_coords || !A_local) return FE_EINVAL;
+  if (f->has_coeff && (!m->coeff || !m->dofmap)) return FE_EINVAL;
+  if (m->n_dofs > INT32_MAX) return FE_EOVERFLOW;
+  CellLaunch a;
+  a.L = &L;
+  a.form_buf = (const unsigned char *)form_buf;
+  a.status = (int32_t *)form_buf;
+  a.n_cells = m->n_cells;
+  a.coords = m->cell_coords;
+  a.dofmap = m->dofmap;
+  a.n_dofs = m->n_dofs;
+  a.coeff = f->has_coeff ? m->coeff : nullptr;
+  a.A_local = A_local;
+  a.stream = stream;
+  return launch_cell(a);
+}
+
+extern "C" fe_status fe_get_device_status(const void *buf, void *stream) {
+  if (!buf) return FE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  int32_t v = 0;
+  if (hipMemcpyAsync(&v, buf, sizeof(v), hipMemcpyDeviceToHost, s) != hipSuccess) return FE_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return FE_EHIP;
+  const int32_t zero = 0;
+  if (hipMemcpyAsync((void *)buf, &zero, sizeof(zero), hipMemcpyHostToDevice, s) != hipSuccess)
+    return FE_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return FE_EHIP;
+  if (v & STATUS_BAD_DOF) return FE_EINVAL;
+  if (v & STATUS_DEGENERATE) return FE_EDEGENERATE;
+  return FE_OK;
+}

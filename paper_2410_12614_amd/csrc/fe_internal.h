@@ -1,0 +1,83 @@
+// Internal declarations of the gfx950 finite element library (not part of the ABI).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "fe.h"
+
+#define FE_MAX_DEGREE 8
+#define FE_MAX_QUAD_DEGREE 17
+
+namespace fe {
+
+// ---- host tabulation (fe_tabulate.cpp) ----
+void gauss_jacobi_01(int m, int alpha, double *t, double *w);
+int simplex_dim(int d, int p);
+void lattice_indices(int d, int p, std::vector<int> &out);
+void lagrange_eval(int d, int p, const double *X, double *val, double *grad);
+
+// Device status word bits (stored in the first word of a form buffer or plan).
+enum : int32_t { STATUS_DEGENERATE = 1, STATUS_BAD_DOF = 2 };
+
+// Layout of a prepared form buffer.  Everything is derived from the form
+// descriptor alone, so host launchers can recompute it without reading the
+// device buffer.
+//
+// Operand conventions (K index k = s * n_q_pad + q, s < nd):
+//   afrag   : B^T packed per 16x16xKSTEP matrix-core fragment,
+//             [mt][ks][lane][KPL] with element B_s(q, i), i = 16 mt + lane % 16,
+//             k = ks*KSTEP + (lane / 16) * KPL + e  (zero padding)
+//   afrag_lo: split mode only, fl16((B - fl16(B)) * 2^11) in the same layout
+//   wtab    : weighted table w_q B_t(q, j), [t][j][n_q_pad], t < NDT
+//   vtab    : basis values phi_k(X_q), [n_q][n_phi] (coefficient evaluation)
+struct FormLayout {
+  int d, nd, ndt, n_phi, n_q, prec, form, has_coeff;
+  int kstep, kpl, n_q_pad, k_pad, nks, mt;
+  int elt_bytes;  // bytes per operand element in afrag
+  int tab_bytes;  // 4 (float tables) or 8 (double tables, FP64 mode)
+  int vtab_bytes; // value table for the coefficient: 8 unless FP16/BF16 storage
+  size_t off_afrag, off_afrag_lo, off_wtab, off_vtab, total;
+};
+
+struct FormHeader {
+  int32_t status;
+  int32_t magic;
+  int32_t d, nd, n_phi, n_q, prec, form;
+  double max_wb;    // max |w_q B_t(q, j)|
+  double lebesgue;  // max_q sum_k |phi_k(X_q)|
+  double b_scale;   // exact power of two applied to the B^T operand (FP16/BF16 modes)
+};
+
+constexpr int32_t FORM_MAGIC = 0x46453335;  // "FE35"
+constexpr size_t HEADER_BYTES = 256;
+
+fe_status compute_layout(const fe_form_desc *f, FormLayout *L);
+fe_status check_form(const fe_form_desc *f);
+
+// ---- cell kernel launchers, one per precision (fe_cell_<prec>.hip) ----
+struct CellLaunch {
+  const FormLayout *L;
+  const unsigned char *form_buf;  // device
+  int32_t *status;                // device status word (inside form_buf)
+  int64_t n_cells;
+  const double *coords;
+  const int32_t *dofmap;
+  int64_t n_dofs;
+  const double *coeff;
+  void *A_local;
+  void *stream;
+};
+fe_status launch_cell_fp64(const CellLaunch &a);
+fe_status launch_cell_fp32(const CellLaunch &a);
+fe_status launch_cell_fp16(const CellLaunch &a);
+fe_status launch_cell_bf16(const CellLaunch &a);
+fe_status launch_cell_split(const CellLaunch &a);
+fe_status launch_cell(const CellLaunch &a);
+
+// Matrix-core tile choice: MT = ceil(n_phi / 16) row tiles of B^T and JC
+// columns j per wave per pass (4 waves per workgroup).
+void tile_choice(int n_phi, int regmul, int *mt, int *jc);
+
+}  // namespace fe
