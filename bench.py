@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Throughput of FE cell kernels + CSR assembly on one MI355X.
+
+Workload: P4 Lagrange mass + stiffness matrices on the unit cube split into
+24^3 boxes x 6 Kuhn tetrahedra (82,944 cells, 35 dofs/cell), interior
+vertices jittered +-0.25 h, 5% of cells flattened to aspect ratio 1e3,
+collapsed Gauss-Jacobi quadrature of degree 8 (125 points), z = 1.  Both
+matrices share one CSR pattern (912,673 rows, 67,338,433 nnz each).
+
+One step = one FE_NUMERIC call of the library: cell kernels of both forms
+(geometry, H formation, matrix-core contraction) and the deterministic CSR
+assembly of both matrices, inputs resident in HBM.  The mixed FP16/FP32
+path is the reported value; the plain FP64 path is timed beside it on the
+same mesh, and the relative Frobenius error of the mixed result against the
+FP64 result is reported (the FP64 path itself matches the FP64 CPU oracle
+to 1e-12 in the GPU tests).
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Peaks used for roofline fractions (MI355X published figures).
+PEAK_HBM_GBS = 8000.0
+PEAK_MFMA_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "split": 2500.0, "fp32": 157.3, "fp64": 78.6}
+
+WORKLOAD = ("P4 Lagrange mass+stiffness, 24^3 x 6 jittered Kuhn tetrahedra (82,944 cells, "
+            "35 dofs/cell), 5% flattened to aspect 1e3, 125-point collapsed Gauss-Jacobi rule")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp16", choices=["fp16", "bf16", "split", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-sample-cells", type=int, default=16384)
+    return ap.parse_args()
+
+
+def time_steps(fn, steps, warmup):
+    """Average ms per call of ``fn`` over ``steps`` calls, HIP events on the
+    current stream (the stream the library launches on)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def cpu_baseline(mesh, sample_cells):
+    """The FP64 oracle (numeric phase: local matrices of both forms + CSR
+    assembly) on the first ``sample_cells`` cells, OpenMP over host cores."""
+    import oracle
+    n = min(sample_cells, mesh.n_cells)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    tab = oracle.tabulation(3, mesh.degree, 8)
+    cc, dm = mesh.cell_coords[:n], mesh.dofmap[:n]
+    rp, ci = oracle.csr_pattern(dm, mesh.n_dofs)          # symbolic: not timed
+    t0 = time.perf_counter()
+    for form in ("mass", "stiffness"):
+        A = oracle.local_matrices(form, cc, mesh.degree, 8, nthreads=threads, tab=tab)
+        oracle.assemble(dm, A, mesh.n_dofs, rp, ci)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} of {mesh.n_cells} cells, both forms, local matrices + CSR "
+                      f"assembly (FP64, {threads} OpenMP threads), {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is a design note, not an implemented path", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from fe_inputs import config_mesh
+    from paper_2410_12614_amd import api
+
+    mesh = config_mesh("c2")
+    mv = api.MeshView.from_numpy(mesh.cell_coords, mesh.dofmap, mesh.n_dofs)
+    forms = ("mass", "stiffness")
+
+    def assembly(prec):
+        return api.Assembly(mv, [api.form_desc(3, 4, 8, f, prec) for f in forms])
+
+    prec = args.precision
+    asm = assembly(prec)
+    ms = time_steps(asm.numeric, args.steps, args.warmup)
+    st = asm.status()
+    if any(s != 0 for s in st):
+        raise RuntimeError(f"device status {st}")
+
+    # per-kernel split of the step: cell kernels alone (both forms) vs the rest
+    n_phi = mesh.n_phi
+    A_loc = [torch.empty((mesh.n_cells, n_phi, n_phi), dtype=torch.float32, device="cuda") for _ in forms]
+    def cells_only():
+        for d, b, A in zip(asm.descs, asm.form_bufs, A_loc):
+            api.fe_cell_kernels(d, b, mv, A)
+    ms_cells = time_steps(cells_only, args.steps, args.warmup)
+    ms_cell_form = []
+    for d, b, A in zip(asm.descs, asm.form_bufs, A_loc):
+        ms_cell_form.append(time_steps(lambda: api.fe_cell_kernels(d, b, mv, A), args.steps, args.warmup))
+    del A_loc
+    ms_gather = max(ms - ms_cells, 1e-6)
+
+    result = {}
+    if not args.no_fp64:
+        asm64 = assembly("fp64")
+        ms64 = time_steps(asm64.numeric, max(3, args.steps // 4), 1)
+        v64 = asm64.numeric()
+        vm = asm.numeric()
+        torch.cuda.synchronize()
+        errs = {}
+        for f, a, b in zip(forms, vm, v64):
+            a, b = a[:asm.nnz].double(), b[:asm.nnz]
+            errs[f] = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+        result["fp64_path"] = {"value": mesh.n_cells / (ms64 / 1e3), "ms_per_step": ms64}
+        result["speedup_vs_fp64"] = ms64 / ms
+        result["rel_err_vs_fp64"] = errs
+        del asm64, v64
+
+    # roofline of the dominant kernel
+    nnz = asm.nnz
+    flops_mass = 2 * n_phi ** 2 * 125
+    flops_stiff = 2 * n_phi ** 2 * 375
+    alg_bytes_per_cell = 96 + 4 * n_phi + 2 * 4 * nnz / mesh.n_cells   # coords + dofmap + values once
+    kern = {
+        "cell_kernel_mass": {"ms": ms_cell_form[0], "alg_flops": flops_mass * mesh.n_cells},
+        "cell_kernel_stiffness": {"ms": ms_cell_form[1], "alg_flops": flops_stiff * mesh.n_cells},
+        "assembly_gather": {"ms": ms_gather, "alg_bytes": alg_bytes_per_cell * mesh.n_cells},
+    }
+    for k in ("cell_kernel_mass", "cell_kernel_stiffness"):
+        kern[k]["tflops"] = kern[k]["alg_flops"] / (kern[k]["ms"] / 1e3) / 1e12
+    kern["assembly_gather"]["gbs"] = kern["assembly_gather"]["alg_bytes"] / (ms_gather / 1e3) / 1e9
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    if dom == "assembly_gather":
+        ach = kern[dom]["gbs"]
+        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "traffic": None, "kernel": dom}
+    else:
+        ach = kern[dom]["tflops"]
+        pk = PEAK_MFMA_TFLOPS[prec]
+        roof = {"bound": "mfma", "achieved": ach, "peak": pk, "unit": "TFLOP/s",
+                "frac": ach / pk, "traffic": None, "kernel": dom}
+
+    line = {
+        "metric": "cells/sec (kernel+CSR assembly) mixed FP16/FP32 vs FP64 at stated rel. error",
+        "value": mesh.n_cells / (ms / 1e3),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp16": "f16 x f16 -> f32", "bf16": "bf16 x bf16 -> f32",
+                  "split": "2xf16 x 2xf16 -> f32", "fp32": "f32"}[prec],
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n_cells": mesh.n_cells, "degree": 4, "quad_degree": 8,
+                   "forms": list(forms), "precision": prec, "geometry": "f64", "nnz": nnz,
+                   "n_dofs": mesh.n_dofs},
+        "roofline": roof,
+        "kernels": kern,
+        **result,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(mesh, args.cpu_sample_cells)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

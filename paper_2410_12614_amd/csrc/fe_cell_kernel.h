@@ -32,6 +32,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "fe_internal.h"
@@ -211,8 +212,16 @@ __device__ __forceinline__ bool cell_geometry(int d, const double *x, double G[3
   return ok;
 }
 
-template <class P, int MT, int JC, int NDT, bool COEFF>
-__global__ __launch_bounds__(256) void cell_kernel(KArgs a) {
+template <class P>
+__device__ __forceinline__ typename P::frag lds_frag(const unsigned char *base, size_t idx) {
+  return *(const typename P::frag *)(base + idx * sizeof(typename P::frag));
+}
+
+// Persistent cell kernel: each workgroup walks batches of 16 cells.  With
+// STAGE, the B^T fragments of the whole K range are copied once into LDS and
+// shared by the four waves for every batch.
+template <class P, int MT, int JC, int NDT, bool COEFF, bool STAGE>
+__global__ __launch_bounds__(256, 2) void cell_kernel(KArgs a) {
   typedef typename P::real T;
   typedef typename P::zreal Z;
   typedef typename P::acc ACC;
@@ -220,197 +229,233 @@ __global__ __launch_bounds__(256) void cell_kernel(KArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int c = lane & 15, kb = lane >> 4;
-  const int64_t cell0 = (int64_t)blockIdx.x * 16;
-  const int64_t cell = cell0 + c;
-  const bool valid = cell < a.n_cells;
-  const int d = a.d, nphi = a.n_phi, n_q_pad = a.n_q_pad;
+  const int d = a.d, nphi = a.n_phi, n_q_pad = a.n_q_pad, nks = a.nks;
 
-  // ---- geometry (Section 4.2), one lane per cell, FP64 ----
-  double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  double adet = 0.0;
-  bool ok = true;
-  if (valid) ok = cell_geometry(d, a.coords + cell * (d + 1) * d, G, adet);
+  const size_t frag_bytes = STAGE ? (size_t)MT * nks * 64 * sizeof(FRAG) : 0;
+  unsigned char *s_af = smem;
+  unsigned char *s_afl = smem + frag_bytes;
+  unsigned char *zbase = smem + frag_bytes * (P::SPLIT ? 2 : 1);
+  Z *zq = (Z *)zbase;                                                   // [n_q_pad][16]
+  double *zloc = (double *)(zbase + (size_t)16 * n_q_pad * sizeof(Z));  // [16][n_phi]
+  double *zred = zloc + 16 * nphi;                                      // [256]
 
-  // ---- coefficient at the quadrature points (FE function evaluation) ----
-  Z *zq = (Z *)smem;                                            // [n_q_pad][16]
-  double *zloc = (double *)(smem + (size_t)16 * n_q_pad * sizeof(Z));  // [16][n_phi]
-  double zmax = 1.0;
-  if constexpr (COEFF) {
-    for (int idx = tid; idx < 16 * nphi; idx += 256) {
-      const int cc = idx / nphi, k = idx - cc * nphi;
-      const int64_t ce = cell0 + cc;
-      double z = 0.0;
-      if (ce < a.n_cells) {
-        const int32_t g = a.dofmap[ce * nphi + k];
-        if (g >= 0 && g < a.n_dofs) z = a.coeff[g];
-        else atomicOr(a.status, STATUS_BAD_DOF);
-      }
-      zloc[idx] = z;
+  if constexpr (STAGE) {
+    const size_t n16 = frag_bytes / 16;
+    const uint4 *src = (const uint4 *)a.afrag;
+    uint4 *dst = (uint4 *)s_af;
+    for (size_t t = tid; t < n16; t += 256) dst[t] = src[t];
+    if constexpr (P::SPLIT) {
+      const uint4 *src2 = (const uint4 *)a.afrag_lo;
+      uint4 *dst2 = (uint4 *)s_afl;
+      for (size_t t = tid; t < n16; t += 256) dst2[t] = src2[t];
     }
     __syncthreads();
-    const Z *vt = (const Z *)a.vtab;
-    double zpart = 0.0;   // this thread's |z_q| maximum for cell tid % 16
-    for (int idx = tid; idx < 16 * n_q_pad; idx += 256) {
-      const int q = idx >> 4, cc = idx & 15;
-      Z z = 0;
-      if (q < a.n_q)
-        for (int k = 0; k < nphi; ++k) z += (Z)zloc[cc * nphi + k] * vt[q * nphi + k];
-      zq[idx] = z;
-      zpart = fmax(zpart, fabs((double)z));
-    }
-    __shared__ double zred[256];
-    zred[tid] = zpart;
-    __syncthreads();
-    // max_q |z_q| of this lane's cell (threads tid and tid + 16 r share tid % 16)
-    double m = 0.0;
-    for (int r = 0; r < 16; ++r) m = fmax(m, zred[c + 16 * r]);
-    zmax = m;
   }
 
-  // ---- per-cell exact power-of-two scale ----
-  double gabs = adet;
-  if (a.nd > 1) {
-    gabs = 0.0;
-    for (int s = 0; s < 3; ++s) gabs = fmax(gabs, fabs(G[s][0]) + fabs(G[s][1]) + fabs(G[s][2]));
-  }
-  double sK = 1.0;
-  if constexpr (P::SCALED) {
-    // |H| <= sK * max|w B| * max_s sum_t |G_st| * max_q |z_q| < 2^15 <= FP16 max
-    const double bound = a.hdr->max_wb * gabs * zmax;
-    if (bound > 0.0 && isfinite(bound)) sK = ldexp(1.0, 14 - ilogb(bound));
-  }
-  if (valid && !ok) {
-    if (lane < 16 && wave == 0) atomicOr(a.status, STATUS_DEGENERATE);
-  }
-  T Gp[3][3];
-  for (int s = 0; s < 3; ++s)
-    for (int t = 0; t < 3; ++t) {
-      double v = (a.nd == 1) ? (s == 0 && t == 0 ? adet : 0.0) : G[s][t];
-      if (!valid) v = 0.0;
-      else if (!ok) v = NAN;
-      Gp[s][t] = (T)(v * sK);
-    }
-  const T inv = (T)(1.0 / (sK * a.hdr->b_scale));
+  const int64_t nbatch = (a.n_cells + 15) / 16;
+  for (int64_t batch = blockIdx.x; batch < nbatch; batch += gridDim.x) {
+    const int64_t cell0 = batch * 16;
+    const int64_t cell = cell0 + c;
+    const bool valid = cell < a.n_cells;
 
-  const T *wt = (const T *)a.wtab;
-  const int npass = (nphi + 4 * JC - 1) / (4 * JC);
-  for (int pass = 0; pass < npass; ++pass) {
-    const int jb = pass * 4 * JC + wave * JC;
-    if (jb >= nphi) continue;
-    ACC acc[MT][JC];
-    ACC acc2[P::SPLIT ? MT : 1][P::SPLIT ? JC : 1];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int jj = 0; jj < JC; ++jj) {
-        acc[mt][jj] = ACC{0, 0, 0, 0};
-        if constexpr (P::SPLIT) acc2[mt][jj] = ACC{0, 0, 0, 0};
-      }
-    for (int ks = 0; ks < a.nks; ++ks) {
-      const int k0 = ks * P::KSTEP;
-      const int s = k0 / n_q_pad;
-      const int qb = k0 - s * n_q_pad + kb * P::KPL;
-      FRAG afr[MT];
-      FRAG afl[P::SPLIT ? MT : 1];
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const size_t fi = ((size_t)mt * a.nks + ks) * 64 + lane;
-        afr[mt] = P::load(a.afrag, fi);
-        if constexpr (P::SPLIT) afl[mt] = P::load(a.afrag_lo, fi);
-      }
-      T g[NDT];
-#pragma unroll
-      for (int t = 0; t < NDT; ++t) g[t] = (s == 0) ? Gp[0][t] : ((s == 1) ? Gp[1][t] : Gp[2][t]);
-      T zf[P::KPL];
-      if constexpr (COEFF) {
-#pragma unroll
-        for (int e = 0; e < P::KPL; ++e) zf[e] = (T)zq[(qb + e) * 16 + c];
-      }
-#pragma unroll
-      for (int jj = 0; jj < JC; ++jj) {
-        const int jl = min(jb + jj, nphi - 1);
-        T h[P::KPL];
-#pragma unroll
-        for (int e = 0; e < P::KPL; ++e) h[e] = 0;
-#pragma unroll
-        for (int t = 0; t < NDT; ++t) {
-          const T *w = wt + ((size_t)t * nphi + jl) * n_q_pad + qb;
-          T wv[P::KPL];
-          if constexpr (P::KPL == 8) {
-            const float4 w0 = ((const float4 *)w)[0], w1 = ((const float4 *)w)[1];
-            wv[0] = w0.x; wv[1] = w0.y; wv[2] = w0.z; wv[3] = w0.w;
-            wv[4] = w1.x; wv[5] = w1.y; wv[6] = w1.z; wv[7] = w1.w;
-          } else {
-            wv[0] = w[0];
-          }
-#pragma unroll
-          for (int e = 0; e < P::KPL; ++e) h[e] += g[t] * wv[e];
+    // ---- geometry (Section 4.2), one lane per cell, FP64 ----
+    double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double adet = 0.0;
+    bool ok = true;
+    if (valid) ok = cell_geometry(d, a.coords + cell * (d + 1) * d, G, adet);
+
+    // ---- coefficient at the quadrature points (FE function evaluation) ----
+    double zmax = 1.0;
+    if constexpr (COEFF) {
+      __syncthreads();  // the previous batch is done with zq
+      for (int idx = tid; idx < 16 * nphi; idx += 256) {
+        const int cc = idx / nphi, k = idx - cc * nphi;
+        const int64_t ce = cell0 + cc;
+        double z = 0.0;
+        if (ce < a.n_cells) {
+          const int32_t g = a.dofmap[ce * nphi + k];
+          if (g >= 0 && g < a.n_dofs) z = a.coeff[g];
+          else atomicOr(a.status, STATUS_BAD_DOF);
         }
-        if constexpr (COEFF) {
-#pragma unroll
-          for (int e = 0; e < P::KPL; ++e) h[e] *= zf[e];
-        }
-        if constexpr (P::SPLIT) {
-          FRAG hh, hl;
-          P::pack2(h, hh, hl);
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt) {
-            acc[mt][jj] = P::mma(afr[mt], hh, acc[mt][jj]);
-            acc2[mt][jj] = P::mma(afr[mt], hl, acc2[mt][jj]);
-            acc2[mt][jj] = P::mma(afl[mt], hh, acc2[mt][jj]);
-          }
-        } else {
-          const FRAG hf = P::pack(h);
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt) acc[mt][jj] = P::mma(afr[mt], hf, acc[mt][jj]);
-        }
+        zloc[idx] = z;
       }
+      __syncthreads();
+      const Z *vt = (const Z *)a.vtab;
+      double zpart = 0.0;  // this thread's |z_q| maximum for cell tid % 16
+      for (int idx = tid; idx < 16 * n_q_pad; idx += 256) {
+        const int q = idx >> 4, cc = idx & 15;
+        Z z = 0;
+        if (q < a.n_q)
+          for (int k = 0; k < nphi; ++k) z += (Z)zloc[cc * nphi + k] * vt[q * nphi + k];
+        zq[idx] = z;
+        zpart = fmax(zpart, fabs((double)z));
+      }
+      zred[tid] = zpart;
+      __syncthreads();
+      // max_q |z_q| of this lane's cell (threads tid and tid + 16 r share tid % 16)
+      double m = 0.0;
+      for (int r = 0; r < 16; ++r) m = fmax(m, zred[c + 16 * r]);
+      zmax = m;
     }
-    if (valid) {
-      T *A = (T *)a.A + (size_t)cell * nphi * nphi;
+
+    // ---- per-cell exact power-of-two scale ----
+    double gabs = adet;
+    if (a.nd > 1) {
+      gabs = 0.0;
+      for (int s = 0; s < 3; ++s) gabs = fmax(gabs, fabs(G[s][0]) + fabs(G[s][1]) + fabs(G[s][2]));
+    }
+    double sK = 1.0;
+    if constexpr (P::SCALED) {
+      // |H| <= sK * max|w B| * max_s sum_t |G_st| * max_q |z_q| < 2^15 <= FP16 max
+      const double bound = a.hdr->max_wb * gabs * zmax;
+      if (bound > 0.0 && isfinite(bound)) sK = ldexp(1.0, 14 - ilogb(bound));
+    }
+    if (valid && !ok && wave == 0 && kb == 0) atomicOr(a.status, STATUS_DEGENERATE);
+    T Gp[3][3];
+    for (int s = 0; s < 3; ++s)
+      for (int t = 0; t < 3; ++t) {
+        double v = (a.nd == 1) ? (s == 0 && t == 0 ? adet : 0.0) : G[s][t];
+        if (!valid) v = 0.0;
+        else if (!ok) v = NAN;
+        Gp[s][t] = (T)(v * sK);
+      }
+    const T inv = (T)(1.0 / (sK * a.hdr->b_scale));
+
+    const T *wt = (const T *)a.wtab;
+    const int npass = (nphi + 4 * JC - 1) / (4 * JC);
+    for (int pass = 0; pass < npass; ++pass) {
+      const int jb = pass * 4 * JC + wave * JC;
+      if (jb >= nphi) continue;
+      ACC acc[MT][JC];
+      ACC acc2[P::SPLIT ? MT : 1][P::SPLIT ? JC : 1];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int jj = 0; jj < JC; ++jj) {
-          const int j = jb + jj;
-          if (j < nphi) {
+          acc[mt][jj] = ACC{0, 0, 0, 0};
+          if constexpr (P::SPLIT) acc2[mt][jj] = ACC{0, 0, 0, 0};
+        }
+      for (int ks = 0; ks < nks; ++ks) {
+        const int k0 = ks * P::KSTEP;
+        const int s = k0 / n_q_pad;
+        const int qb = k0 - s * n_q_pad + kb * P::KPL;
+        FRAG afr[MT];
+        FRAG afl[P::SPLIT ? MT : 1];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int i = mt * 16 + P::row(kb, r);
-              if (i < nphi) {
-                T v = acc[mt][jj][r];
-                if constexpr (P::SPLIT) v += acc2[mt][jj][r] * (T)(1.0 / 2048.0);
-                A[(size_t)i * nphi + j] = v * inv;
+        for (int mt = 0; mt < MT; ++mt) {
+          const size_t fi = ((size_t)mt * nks + ks) * 64 + lane;
+          if constexpr (STAGE) {
+            afr[mt] = lds_frag<P>(s_af, fi);
+            if constexpr (P::SPLIT) afl[mt] = lds_frag<P>(s_afl, fi);
+          } else {
+            afr[mt] = P::load(a.afrag, fi);
+            if constexpr (P::SPLIT) afl[mt] = P::load(a.afrag_lo, fi);
+          }
+        }
+        T g[NDT];
+#pragma unroll
+        for (int t = 0; t < NDT; ++t) g[t] = (s == 0) ? Gp[0][t] : ((s == 1) ? Gp[1][t] : Gp[2][t]);
+        T zf[P::KPL];
+        if constexpr (COEFF) {
+#pragma unroll
+          for (int e = 0; e < P::KPL; ++e) zf[e] = (T)zq[(qb + e) * 16 + c];
+        }
+#pragma unroll
+        for (int jj = 0; jj < JC; ++jj) {
+          const int jl = min(jb + jj, nphi - 1);
+          T h[P::KPL];
+#pragma unroll
+          for (int e = 0; e < P::KPL; ++e) h[e] = 0;
+#pragma unroll
+          for (int t = 0; t < NDT; ++t) {
+            const T *w = wt + ((size_t)t * nphi + jl) * n_q_pad + qb;
+            T wv[P::KPL];
+            if constexpr (P::KPL == 8) {
+              const float4 w0 = ((const float4 *)w)[0], w1 = ((const float4 *)w)[1];
+              wv[0] = w0.x; wv[1] = w0.y; wv[2] = w0.z; wv[3] = w0.w;
+              wv[4] = w1.x; wv[5] = w1.y; wv[6] = w1.z; wv[7] = w1.w;
+            } else {
+              wv[0] = w[0];
+            }
+#pragma unroll
+            for (int e = 0; e < P::KPL; ++e) h[e] += g[t] * wv[e];
+          }
+          if constexpr (COEFF) {
+#pragma unroll
+            for (int e = 0; e < P::KPL; ++e) h[e] *= zf[e];
+          }
+          if constexpr (P::SPLIT) {
+            FRAG hh, hl;
+            P::pack2(h, hh, hl);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+              acc[mt][jj] = P::mma(afr[mt], hh, acc[mt][jj]);
+              acc2[mt][jj] = P::mma(afr[mt], hl, acc2[mt][jj]);
+              acc2[mt][jj] = P::mma(afl[mt], hh, acc2[mt][jj]);
+            }
+          } else {
+            const FRAG hf = P::pack(h);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt][jj] = P::mma(afr[mt], hf, acc[mt][jj]);
+          }
+        }
+      }
+      // The tile holds column j of A_K (rows i); by the symmetry of the mass
+      // and stiffness forms it is stored as row j, so each lane's rows land
+      // on consecutive addresses.
+      if (valid) {
+        T *A = (T *)a.A + (size_t)cell * nphi * nphi;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int jj = 0; jj < JC; ++jj) {
+            const int j = jb + jj;
+            if (j < nphi) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int i = mt * 16 + P::row(kb, r);
+                if (i < nphi) {
+                  T v = acc[mt][jj][r];
+                  if constexpr (P::SPLIT) v += acc2[mt][jj][r] * (T)(1.0 / 2048.0);
+                  A[(size_t)j * nphi + i] = v * inv;
+                }
               }
             }
           }
-        }
+      }
     }
   }
 }
 
-template <class P, int MT, int JC, int NDT, bool COEFF>
+template <class P, int MT, int JC, int NDT, bool COEFF, bool STAGE>
 static fe_status launch_one(const KArgs &k, int64_t n_cells, size_t smem, hipStream_t s) {
-  auto kern = cell_kernel<P, MT, JC, NDT, COEFF>;
+  auto kern = cell_kernel<P, MT, JC, NDT, COEFF, STAGE>;
   if (smem > 65536) {
     if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)smem) != hipSuccess)
       return FE_EHIP;
   }
-  const int64_t blocks = (n_cells + 15) / 16;
-  if (blocks > INT32_MAX) return FE_EOVERFLOW;
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return FE_EHIP;
+  const int64_t nbatch = (n_cells + 15) / 16;
+  // two resident workgroups per compute unit when LDS allows, one otherwise
+  const int per_cu = smem <= 80 * 1024 ? 2 : 1;
+  const int64_t blocks = std::min<int64_t>(nbatch, (int64_t)ncu * per_cu);
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), smem, s, k);
   return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
 }
 
 template <class P, int MT, int JC>
 static fe_status launch_mt(const KArgs &k, int64_t n_cells, size_t smem, hipStream_t s, int ndt,
-                           bool coeff) {
-  if (ndt == 1)
-    return coeff ? launch_one<P, MT, JC, 1, true>(k, n_cells, smem, s)
-                 : launch_one<P, MT, JC, 1, false>(k, n_cells, smem, s);
-  return coeff ? launch_one<P, MT, JC, 3, true>(k, n_cells, smem, s)
-               : launch_one<P, MT, JC, 3, false>(k, n_cells, smem, s);
+                           bool coeff, bool stage) {
+#define FE_L(NDT, C, ST) \
+  if (ndt == NDT && coeff == C && stage == ST) return launch_one<P, MT, JC, NDT, C, ST>(k, n_cells, smem, s);
+  FE_L(1, false, false) FE_L(1, true, false) FE_L(3, false, false) FE_L(3, true, false)
+  FE_L(1, false, true) FE_L(1, true, true) FE_L(3, false, true) FE_L(3, true, true)
+#undef FE_L
+  return FE_EUNSUPPORTED;
 }
 
 template <class P>
@@ -438,17 +483,24 @@ fe_status launch_cell_impl(const CellLaunch &a) {
   k.n_q_pad = L.n_q_pad;
   k.nks = L.nks;
   const bool coeff = L.has_coeff != 0;
-  const size_t smem =
-      coeff ? (size_t)16 * L.n_q_pad * sizeof(typename P::zreal) + (size_t)16 * L.n_phi * 8 : 0;
+  typedef typename P::frag FRAG;
+  const size_t frag_bytes = (size_t)mt * L.nks * 64 * sizeof(FRAG) * (P::SPLIT ? 2 : 1);
+  const size_t zbytes = coeff ? (size_t)16 * L.n_q_pad * sizeof(typename P::zreal) +
+                                    (size_t)16 * L.n_phi * 8 + 256 * 8
+                              : 0;
+  // stage B^T in LDS when it fits next to the coefficient tables with room
+  // for two resident workgroups
+  const bool stage = frag_bytes + zbytes <= 80 * 1024;
+  const size_t smem = (stage ? frag_bytes : 0) + zbytes;
   hipStream_t s = (hipStream_t)a.stream;
   const int ndt = L.ndt;
 #define FE_CASE(M, J) \
-  if (mt == M && jc == J) return launch_mt<P, M, J>(k, a.n_cells, smem, s, ndt, coeff);
+  if (mt == M && jc == J) return launch_mt<P, M, J>(k, a.n_cells, smem, s, ndt, coeff, stage);
   if constexpr (P::REGMUL == 1) {
     FE_CASE(1, 4) FE_CASE(2, 8) FE_CASE(3, 9) FE_CASE(4, 7) FE_CASE(6, 7) FE_CASE(8, 6)
     FE_CASE(11, 3)
   } else {
-    FE_CASE(1, 4) FE_CASE(2, 8) FE_CASE(3, 9) FE_CASE(4, 7) FE_CASE(6, 3) FE_CASE(8, 3)
+    FE_CASE(1, 4) FE_CASE(2, 5) FE_CASE(3, 5) FE_CASE(4, 4) FE_CASE(6, 3) FE_CASE(8, 2)
     FE_CASE(11, 2)
   }
 #undef FE_CASE

@@ -252,18 +252,26 @@ __global__ __launch_bounds__(256) void k_ranks(const int32_t *dofmap, int64_t n_
   }
 }
 
-// Numeric gather: one wave per CSR row, NF forms, LDS window of W entries.
+// Numeric gather: one wave per CSR row, NF forms, LDS window of W entries per
+// form.  The incident local rows are visited in adjacency order (cell
+// ascending, then local index); their loads are issued GROUP at a time and
+// the LDS additions then applied in that same order, so the sum of every
+// entry is formed in a fixed order.
+constexpr int GATHER_W = 512;
+constexpr int GATHER_GROUP = 4;
+
 template <class T, int NF>
 __global__ __launch_bounds__(256) void k_gather(const int64_t *adj_ptr, const int64_t *adj,
                                                 const uint16_t *rank, const int64_t *row_ptr,
-                                                int64_t n_rows, int n_phi, int W,
+                                                int64_t n_rows, int n_phi,
                                                 const T *A0, const T *A1, const T *A2,
                                                 const T *A3, T *V0, T *V1, T *V2, T *V3) {
-  extern __shared__ __align__(16) unsigned char gsm[];
+  constexpr int W = GATHER_W;
+  __shared__ T sbuf[4][NF][W];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t g = (int64_t)blockIdx.x * 4 + wave;
   if (g >= n_rows) return;
-  T *buf = (T *)gsm + (size_t)wave * NF * W;
+  T (*buf)[W] = sbuf[wave];
   const T *A[4] = {A0, A1, A2, A3};
   T *V[4] = {V0, V1, V2, V3};
   const int64_t r0 = row_ptr[g];
@@ -273,21 +281,34 @@ __global__ __launch_bounds__(256) void k_gather(const int64_t *adj_ptr, const in
     const int wl = min(W, len - w0);
     for (int r = lane; r < wl; r += 64)
 #pragma unroll
-      for (int f = 0; f < NF; ++f) buf[f * W + r] = 0;
-    for (int64_t a = a0; a < a1; ++a) {
-      const int64_t ent = adj[a];
-      const size_t base = ((size_t)(ent >> 8) * n_phi + (ent & 255)) * n_phi;
-      for (int j = lane; j < n_phi; j += 64) {
-        const int r = (int)rank[base + j] - w0;
-        if (r >= 0 && r < wl) {
+      for (int f = 0; f < NF; ++f) buf[f][r] = 0;
+    for (int j0 = 0; j0 < n_phi; j0 += 64) {
+      const int j = j0 + lane;
+      for (int64_t a = a0; a < a1; a += GATHER_GROUP) {
+        int rk[GATHER_GROUP];
+        T v[GATHER_GROUP][NF];
 #pragma unroll
-          for (int f = 0; f < NF; ++f) buf[f * W + r] += A[f][base + j];
+        for (int u = 0; u < GATHER_GROUP; ++u) {
+          rk[u] = -1;
+          if (a + u < a1 && j < n_phi) {
+            const int64_t ent = adj[a + u];
+            const size_t base = ((size_t)(ent >> 8) * n_phi + (ent & 255)) * n_phi + j;
+            rk[u] = (int)rank[base] - w0;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) v[u][f] = A[f][base];
+          }
         }
+#pragma unroll
+        for (int u = 0; u < GATHER_GROUP; ++u)
+          if (rk[u] >= 0 && rk[u] < wl) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) buf[f][rk[u]] += v[u][f];
+          }
       }
     }
     for (int r = lane; r < wl; r += 64)
 #pragma unroll
-      for (int f = 0; f < NF; ++f) V[f][r0 + w0 + r] = buf[f * W + r];
+      for (int f = 0; f < NF; ++f) V[f][r0 + w0 + r] = buf[f][r];
   }
 }
 
@@ -295,16 +316,9 @@ template <class T, int NF>
 fe_status launch_gather(const int64_t *adj_ptr, const int64_t *adj, const uint16_t *rank,
                         const int64_t *row_ptr, int64_t n_rows, int n_phi, void *const *A,
                         void *const *V, hipStream_t s) {
-  const int W = (int)(16384 / (NF * sizeof(T)));  // 16 KiB of LDS per wave
-  const size_t smem = (size_t)4 * NF * W * sizeof(T);
   const int64_t blocks = (n_rows + 3) / 4;
-  auto kern = k_gather<T, NF>;
-  if (smem > 65536 && hipFuncSetAttribute((const void *)kern,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize,
-                                          (int)smem) != hipSuccess)
-    return FE_EHIP;
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), smem, s, adj_ptr, adj, rank, row_ptr,
-                     n_rows, n_phi, W, (const T *)A[0], (const T *)A[1], (const T *)A[2],
+  hipLaunchKernelGGL((k_gather<T, NF>), dim3((unsigned)blocks), dim3(256), 0, s, adj_ptr, adj, rank,
+                     row_ptr, n_rows, n_phi, (const T *)A[0], (const T *)A[1], (const T *)A[2],
                      (const T *)A[3], (T *)V[0], (T *)V[1], (T *)V[2], (T *)V[3]);
   return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
 }

@@ -28,7 +28,7 @@ fe_status check_form(const fe_form_desc *f) {
 void tile_choice(int n_phi, int regmul, int *mt, int *jc) {
   const int m = (n_phi + 15) / 16;
   static const int jc1[12] = {0, 4, 8, 9, 7, 0, 7, 0, 6, 0, 0, 3};
-  static const int jc2[12] = {0, 4, 8, 9, 7, 0, 3, 0, 3, 0, 0, 2};
+  static const int jc2[12] = {0, 4, 5, 5, 4, 0, 3, 0, 2, 0, 0, 2};
   *mt = m;
   *jc = (m >= 1 && m <= 11) ? (regmul == 1 ? jc1[m] : jc2[m]) : 0;
 }
