@@ -86,7 +86,7 @@ enum {
 enum { FE_GEOM_FP64 = 0 };
 
 /* Phases of fe_assemble_csr. */
-enum { FE_SYMBOLIC_COUNT = 0, FE_SYMBOLIC_FILL = 1, FE_NUMERIC = 2 };
+enum { FE_SYMBOLIC_COUNT = 0, FE_SYMBOLIC_FILL = 1, FE_NUMERIC = 2, FE_NUMERIC_GATHER = 3 };
 
 typedef struct fe_form_desc {
   int32_t cell;           /* FE_TRIANGLE or FE_TETRAHEDRON                     */
@@ -110,6 +110,7 @@ typedef struct fe_mesh_view {
 typedef struct fe_csr {
   int64_t n_rows;   /* = n_dofs                                               */
   int64_t nnz;      /* written by FE_SYMBOLIC_COUNT                            */
+  int64_t max_row_len; /* written by FE_SYMBOLIC_COUNT: longest row           */
   int64_t *row_ptr; /* device [n_rows+1]                                       */
   int32_t *col_idx; /* device [nnz], ascending and unique per row              */
   void *values;     /* device [nnz], double for FE_FP64 else float             */
@@ -194,15 +195,25 @@ fe_status fe_cell_kernels(const fe_form_desc *f, const void *form_buf, const fe_
  *       matrices of all forms), sized by a query with workspace == NULL.
  *
  * Phases:
- *   FE_SYMBOLIC_COUNT : fills mats[0].row_ptr and writes nnz into every
- *       mats[f].nnz.  SYNCHRONISES the stream (nnz is read back).
- *   FE_SYMBOLIC_FILL  : fills mats[0].col_idx (sorted) and the plan.
- *       Asynchronous.  Errors: FE_EOVERFLOW when a row holds 65536 or more
- *       entries (checked on the host after COUNT).
- *   FE_NUMERIC : for every form, runs the cell kernels and sums every
- *       CSR entry's contributions in the fixed order (cell ascending, then
- *       local row), writing every value exactly once (no separate
- *       zero-fill).  Asynchronous, never synchronises, bitwise repeatable.
+ *   FE_SYMBOLIC_COUNT : fills mats[0].row_ptr and writes nnz and max_row_len
+ *       into every mats[f].  SYNCHRONISES the stream (nnz is read back).
+ *       FE_EOVERFLOW when a row holds 65536 or more entries.
+ *   FE_SYMBOLIC_FILL  : fills mats[0].col_idx (sorted) and the plan: the
+ *       position of every local entry inside its CSR row and, when every
+ *       row fits one owner task, the row-ownership schedule of the fused
+ *       numeric path.  SYNCHRONISES the stream.
+ *   FE_NUMERIC : writes the values of every form.  For forms without a
+ *       coefficient whose rows fit one owner task (mats[0].max_row_len <=
+ *       1024) it runs a per-cell FP64 geometry pass and one fused kernel
+ *       per form: every wave owns a range of CSR rows in LDS, computes the
+ *       local rows A_K(j, :) of exactly the dofs it owns on the matrix cores
+ *       and writes its rows once.  Otherwise it runs the cell kernels into
+ *       the workspace followed by the row gather.  Either way every entry's
+ *       contributions are summed in the fixed order cell ascending and every
+ *       value is written exactly once (no separate zero-fill).
+ *       Asynchronous, never synchronises, bitwise repeatable.
+ *   FE_NUMERIC_GATHER : as FE_NUMERIC but always through the workspace and
+ *       the row gather (for comparison and testing).
  * Errors: FE_EINVAL (NULL pointers, dof entries out of range are reported
  * through the status word of the plan), FE_ESIZE, FE_EUNSUPPORTED, FE_EHIP.
  * ------------------------------------------------------------------------ */

@@ -33,6 +33,7 @@ FE_GEOM_FP64 = 0
 FE_SYMBOLIC_COUNT = 0
 FE_SYMBOLIC_FILL = 1
 FE_NUMERIC = 2
+FE_NUMERIC_GATHER = 3
 
 # every symbol declared in include/fe.h
 EXPORTS = (
@@ -62,7 +63,8 @@ class fe_mesh_view(ctypes.Structure):
 
 
 class fe_csr(ctypes.Structure):
-    _fields_ = [("n_rows", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+    _fields_ = [("n_rows", ctypes.c_int64), ("nnz", ctypes.c_int64), ("max_row_len", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p),
                 ("col_idx", ctypes.c_void_p), ("values", ctypes.c_void_p)]
 
 

@@ -160,10 +160,17 @@ class Assembly:
         check(fe_assemble_csr(self.descs, self.form_bufs, mesh, L.FE_SYMBOLIC_FILL, self.mats,
                               self.plan, None, stream), "fe_assemble_csr(FILL)")
 
-    def numeric(self) -> list:
-        check(fe_assemble_csr(self.descs, self.form_bufs, self.mesh, L.FE_NUMERIC, self.mats,
+    def numeric(self, gather: bool = False) -> list:
+        """FE_NUMERIC (fused row-ownership path where it applies) or, with
+        ``gather``, FE_NUMERIC_GATHER (cell kernels + row gather)."""
+        phase = L.FE_NUMERIC_GATHER if gather else L.FE_NUMERIC
+        check(fe_assemble_csr(self.descs, self.form_bufs, self.mesh, phase, self.mats,
                               self.plan, self.workspace, self.stream), "fe_assemble_csr(NUMERIC)")
         return self.values
+
+    @property
+    def max_row_len(self) -> int:
+        return int(self.mats[0].max_row_len)
 
     def status(self) -> list:
         return [fe_get_device_status(b, self.stream) for b in self.form_bufs] + \

@@ -26,8 +26,9 @@
 // pair and FP64 (the list of precisions and the mixed-precision strategy of
 // Section 4.5).
 //
-// Workgroup: 256 threads = 4 waves.  Lane l of a wave owns cell c = l % 16
-// and K-slot kb = l / 16; wave w handles columns j in [pass*4*JC + w*JC, +JC).
+// Workgroup: NW waves (4, or 8 when the tables are staged in LDS).  Lane l
+// of a wave owns cell c = l % 16 and K-slot kb = l / 16; wave w handles the
+// columns j in [pass*NW*JC + w*JC, +JC).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -217,11 +218,13 @@ __device__ __forceinline__ typename P::frag lds_frag(const unsigned char *base, 
   return *(const typename P::frag *)(base + idx * sizeof(typename P::frag));
 }
 
-// Persistent cell kernel: each workgroup walks batches of 16 cells.  With
-// STAGE, the B^T fragments of the whole K range are copied once into LDS and
-// shared by the four waves for every batch.
-template <class P, int MT, int JC, int NDT, bool COEFF, bool STAGE>
-__global__ __launch_bounds__(256, 2) void cell_kernel(KArgs a) {
+// Persistent cell kernel: each workgroup (NW waves) walks batches of 16
+// cells.  STAGE >= 1 copies the B^T fragments of the whole K range into LDS
+// once; STAGE == 2 also copies the weighted table (the 16 lanes of a K-slot
+// read one row j, a broadcast).  Both are then shared by all waves for every
+// batch.
+template <class P, int MT, int JC, int NDT, bool COEFF, int STAGE, int NW>
+__global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
   typedef typename P::real T;
   typedef typename P::zreal Z;
   typedef typename P::acc ACC;
@@ -231,26 +234,33 @@ __global__ __launch_bounds__(256, 2) void cell_kernel(KArgs a) {
   const int c = lane & 15, kb = lane >> 4;
   const int d = a.d, nphi = a.n_phi, n_q_pad = a.n_q_pad, nks = a.nks;
 
-  const size_t frag_bytes = STAGE ? (size_t)MT * nks * 64 * sizeof(FRAG) : 0;
+  constexpr int NT = NW * 64;
+  const size_t frag_bytes = STAGE >= 1 ? (size_t)MT * nks * 64 * sizeof(FRAG) : 0;
+  const size_t wtab_bytes = STAGE == 2 ? (size_t)NDT * nphi * n_q_pad * sizeof(T) : 0;
   unsigned char *s_af = smem;
   unsigned char *s_afl = smem + frag_bytes;
-  unsigned char *zbase = smem + frag_bytes * (P::SPLIT ? 2 : 1);
+  T *s_wt = (T *)(smem + frag_bytes * (P::SPLIT ? 2 : 1));
+  unsigned char *zbase = smem + frag_bytes * (P::SPLIT ? 2 : 1) + wtab_bytes;
   Z *zq = (Z *)zbase;                                                   // [n_q_pad][16]
   double *zloc = (double *)(zbase + (size_t)16 * n_q_pad * sizeof(Z));  // [16][n_phi]
-  double *zred = zloc + 16 * nphi;                                      // [256]
+  double *zred = zloc + 16 * nphi;                                      // [NT]
 
-  if constexpr (STAGE) {
+  if constexpr (STAGE >= 1) {
     const size_t n16 = frag_bytes / 16;
     const uint4 *src = (const uint4 *)a.afrag;
     uint4 *dst = (uint4 *)s_af;
-    for (size_t t = tid; t < n16; t += 256) dst[t] = src[t];
+    for (size_t t = tid; t < n16; t += NT) dst[t] = src[t];
     if constexpr (P::SPLIT) {
       const uint4 *src2 = (const uint4 *)a.afrag_lo;
       uint4 *dst2 = (uint4 *)s_afl;
-      for (size_t t = tid; t < n16; t += 256) dst2[t] = src2[t];
+      for (size_t t = tid; t < n16; t += NT) dst2[t] = src2[t];
     }
-    __syncthreads();
   }
+  if constexpr (STAGE == 2) {
+    const size_t n16 = wtab_bytes / 16;
+    for (size_t t = tid; t < n16; t += NT) ((uint4 *)s_wt)[t] = ((const uint4 *)a.wtab)[t];
+  }
+  if constexpr (STAGE >= 1) __syncthreads();
 
   const int64_t nbatch = (a.n_cells + 15) / 16;
   for (int64_t batch = blockIdx.x; batch < nbatch; batch += gridDim.x) {
@@ -268,7 +278,7 @@ __global__ __launch_bounds__(256, 2) void cell_kernel(KArgs a) {
     double zmax = 1.0;
     if constexpr (COEFF) {
       __syncthreads();  // the previous batch is done with zq
-      for (int idx = tid; idx < 16 * nphi; idx += 256) {
+      for (int idx = tid; idx < 16 * nphi; idx += NT) {
         const int cc = idx / nphi, k = idx - cc * nphi;
         const int64_t ce = cell0 + cc;
         double z = 0.0;
@@ -282,7 +292,7 @@ __global__ __launch_bounds__(256, 2) void cell_kernel(KArgs a) {
       __syncthreads();
       const Z *vt = (const Z *)a.vtab;
       double zpart = 0.0;  // this thread's |z_q| maximum for cell tid % 16
-      for (int idx = tid; idx < 16 * n_q_pad; idx += 256) {
+      for (int idx = tid; idx < 16 * n_q_pad; idx += NT) {
         const int q = idx >> 4, cc = idx & 15;
         Z z = 0;
         if (q < a.n_q)
@@ -294,7 +304,7 @@ __global__ __launch_bounds__(256, 2) void cell_kernel(KArgs a) {
       __syncthreads();
       // max_q |z_q| of this lane's cell (threads tid and tid + 16 r share tid % 16)
       double m = 0.0;
-      for (int r = 0; r < 16; ++r) m = fmax(m, zred[c + 16 * r]);
+      for (int r = 0; r < NT / 16; ++r) m = fmax(m, zred[c + 16 * r]);
       zmax = m;
     }
 
@@ -305,10 +315,14 @@ __global__ __launch_bounds__(256, 2) void cell_kernel(KArgs a) {
       for (int s = 0; s < 3; ++s) gabs = fmax(gabs, fabs(G[s][0]) + fabs(G[s][1]) + fabs(G[s][2]));
     }
     double sK = 1.0;
+    int esK = 0;
     if constexpr (P::SCALED) {
       // |H| <= sK * max|w B| * max_s sum_t |G_st| * max_q |z_q| < 2^15 <= FP16 max
       const double bound = a.hdr->max_wb * gabs * zmax;
-      if (bound > 0.0 && isfinite(bound)) sK = ldexp(1.0, 14 - ilogb(bound));
+      if (bound > 0.0 && isfinite(bound)) {
+        esK = 14 - ilogb(bound);
+        sK = ldexp(1.0, esK);
+      }
     }
     if (valid && !ok && wave == 0 && kb == 0) atomicOr(a.status, STATUS_DEGENERATE);
     T Gp[3][3];
@@ -319,12 +333,13 @@ __global__ __launch_bounds__(256, 2) void cell_kernel(KArgs a) {
         else if (!ok) v = NAN;
         Gp[s][t] = (T)(v * sK);
       }
-    const T inv = (T)(1.0 / (sK * a.hdr->b_scale));
+    // sK and the B scale are exact powers of two: invert by exponents
+    const T inv = (T)ldexp(1.0, -esK - ilogb(a.hdr->b_scale));
 
     const T *wt = (const T *)a.wtab;
-    const int npass = (nphi + 4 * JC - 1) / (4 * JC);
+    const int npass = (nphi + NW * JC - 1) / (NW * JC);
     for (int pass = 0; pass < npass; ++pass) {
-      const int jb = pass * 4 * JC + wave * JC;
+      const int jb = pass * NW * JC + wave * JC;
       if (jb >= nphi) continue;
       ACC acc[MT][JC];
       ACC acc2[P::SPLIT ? MT : 1][P::SPLIT ? JC : 1];
@@ -344,7 +359,7 @@ __global__ __launch_bounds__(256, 2) void cell_kernel(KArgs a) {
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
           const size_t fi = ((size_t)mt * nks + ks) * 64 + lane;
-          if constexpr (STAGE) {
+          if constexpr (STAGE >= 1) {
             afr[mt] = lds_frag<P>(s_af, fi);
             if constexpr (P::SPLIT) afl[mt] = lds_frag<P>(s_afl, fi);
           } else {
@@ -368,7 +383,9 @@ __global__ __launch_bounds__(256, 2) void cell_kernel(KArgs a) {
           for (int e = 0; e < P::KPL; ++e) h[e] = 0;
 #pragma unroll
           for (int t = 0; t < NDT; ++t) {
-            const T *w = wt + ((size_t)t * nphi + jl) * n_q_pad + qb;
+            const T *w;
+            if constexpr (STAGE == 2) w = s_wt + ((size_t)t * nphi + jl) * n_q_pad + qb;
+            else w = wt + ((size_t)t * nphi + jl) * n_q_pad + qb;
             T wv[P::KPL];
             if constexpr (P::KPL == 8) {
               const float4 w0 = ((const float4 *)w)[0], w1 = ((const float4 *)w)[1];
@@ -427,9 +444,9 @@ __global__ __launch_bounds__(256, 2) void cell_kernel(KArgs a) {
   }
 }
 
-template <class P, int MT, int JC, int NDT, bool COEFF, bool STAGE>
+template <class P, int MT, int JC, int NDT, bool COEFF, int STAGE, int NW>
 static fe_status launch_one(const KArgs &k, int64_t n_cells, size_t smem, hipStream_t s) {
-  auto kern = cell_kernel<P, MT, JC, NDT, COEFF, STAGE>;
+  auto kern = cell_kernel<P, MT, JC, NDT, COEFF, STAGE, NW>;
   if (smem > 65536) {
     if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)smem) != hipSuccess)
@@ -440,22 +457,21 @@ static fe_status launch_one(const KArgs &k, int64_t n_cells, size_t smem, hipStr
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return FE_EHIP;
   const int64_t nbatch = (n_cells + 15) / 16;
-  // two resident workgroups per compute unit when LDS allows, one otherwise
-  const int per_cu = smem <= 80 * 1024 ? 2 : 1;
+  // eight waves per compute unit: two 4-wave or one 8-wave workgroup
+  const int per_cu = (NW == 4 && smem <= 80 * 1024) ? 2 : 1;
   const int64_t blocks = std::min<int64_t>(nbatch, (int64_t)ncu * per_cu);
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), smem, s, k);
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(NW * 64), smem, s, k);
   return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
 }
 
-template <class P, int MT, int JC>
+template <class P, int MT, int JC, int NW, int STAGE>
 static fe_status launch_mt(const KArgs &k, int64_t n_cells, size_t smem, hipStream_t s, int ndt,
-                           bool coeff, bool stage) {
-#define FE_L(NDT, C, ST) \
-  if (ndt == NDT && coeff == C && stage == ST) return launch_one<P, MT, JC, NDT, C, ST>(k, n_cells, smem, s);
-  FE_L(1, false, false) FE_L(1, true, false) FE_L(3, false, false) FE_L(3, true, false)
-  FE_L(1, false, true) FE_L(1, true, true) FE_L(3, false, true) FE_L(3, true, true)
-#undef FE_L
-  return FE_EUNSUPPORTED;
+                           bool coeff) {
+  if (ndt == 1)
+    return coeff ? launch_one<P, MT, JC, 1, true, STAGE, NW>(k, n_cells, smem, s)
+                 : launch_one<P, MT, JC, 1, false, STAGE, NW>(k, n_cells, smem, s);
+  return coeff ? launch_one<P, MT, JC, 3, true, STAGE, NW>(k, n_cells, smem, s)
+               : launch_one<P, MT, JC, 3, false, STAGE, NW>(k, n_cells, smem, s);
 }
 
 template <class P>
@@ -484,18 +500,41 @@ fe_status launch_cell_impl(const CellLaunch &a) {
   k.nks = L.nks;
   const bool coeff = L.has_coeff != 0;
   typedef typename P::frag FRAG;
+  typedef typename P::real T;
   const size_t frag_bytes = (size_t)mt * L.nks * 64 * sizeof(FRAG) * (P::SPLIT ? 2 : 1);
+  const size_t wtab_bytes = (size_t)L.ndt * L.n_phi * L.n_q_pad * sizeof(T);
+  hipStream_t s = (hipStream_t)a.stream;
+  const int ndt = L.ndt;
+  // 8-wave workgroups with fragments and weighted table in LDS when both fit
+  // (small forms: row tiles <= 4); else 4-wave workgroups, fragments staged
+  // when they fit beside the coefficient tables.
+  {
+    const size_t zbytes8 = coeff ? (size_t)16 * L.n_q_pad * sizeof(typename P::zreal) +
+                                       (size_t)16 * L.n_phi * 8 + 512 * 8
+                                 : 0;
+    const size_t smem8 = frag_bytes + wtab_bytes + zbytes8;
+    if (mt <= 4 && smem8 <= 156 * 1024) {
+      int jc8 = 0;
+      if (mt == 1) jc8 = 2;
+      if (mt == 2) jc8 = 4;
+      if (mt == 3) jc8 = 5;
+      if (mt == 4) jc8 = (P::REGMUL == 1) ? 7 : 4;
+#define FE_C8(M, J) \
+  if (mt == M && jc8 == J) return launch_mt<P, M, J, 8, 2>(k, a.n_cells, smem8, s, ndt, coeff);
+      FE_C8(1, 2) FE_C8(2, 4) FE_C8(3, 5) FE_C8(4, 7) FE_C8(4, 4)
+#undef FE_C8
+    }
+  }
   const size_t zbytes = coeff ? (size_t)16 * L.n_q_pad * sizeof(typename P::zreal) +
                                     (size_t)16 * L.n_phi * 8 + 256 * 8
                               : 0;
-  // stage B^T in LDS when it fits next to the coefficient tables with room
-  // for two resident workgroups
   const bool stage = frag_bytes + zbytes <= 80 * 1024;
   const size_t smem = (stage ? frag_bytes : 0) + zbytes;
-  hipStream_t s = (hipStream_t)a.stream;
-  const int ndt = L.ndt;
-#define FE_CASE(M, J) \
-  if (mt == M && jc == J) return launch_mt<P, M, J>(k, a.n_cells, smem, s, ndt, coeff, stage);
+#define FE_CASE(M, J)                                                                   \
+  if (mt == M && jc == J) {                                                             \
+    if (stage) return launch_mt<P, M, J, 4, 1>(k, a.n_cells, smem, s, ndt, coeff);      \
+    return launch_mt<P, M, J, 4, 0>(k, a.n_cells, smem, s, ndt, coeff);                 \
+  }
   if constexpr (P::REGMUL == 1) {
     FE_CASE(1, 4) FE_CASE(2, 8) FE_CASE(3, 9) FE_CASE(4, 7) FE_CASE(6, 7) FE_CASE(8, 6)
     FE_CASE(11, 3)

@@ -1,6 +1,9 @@
-// Cell-kernel instantiations for one precision (see fe_cell_kernel.h).
+// Cell-kernel and fused-assembly instantiations for one precision
+// (see fe_cell_kernel.h and fe_fused.h).
 #include "fe_cell_kernel.h"
+#include "fe_fused.h"
 
 namespace fe {
 fe_status launch_cell_split(const CellLaunch &a) { return launch_cell_impl<PolSplit>(a); }
+fe_status launch_fused_split(const FusedLaunch &a) { return launch_fused_impl<PolSplit>(a); }
 }  // namespace fe

@@ -21,7 +21,10 @@
 #include <algorithm>
 #include <cstring>
 
+#include "fe_cell_kernel.h"
 #include "fe_internal.h"
+
+#include <vector>
 
 namespace fe {
 namespace {
@@ -32,12 +35,15 @@ struct PlanHeader {
   int64_t n_cells, n_dofs;
   int32_t n_phi, pad;
   int64_t nnz, max_deg, max_len;
+  int32_t ntasks;  // fused schedule: number of owner tasks (0 = not built)
+  int32_t ntiles;
 };
 constexpr int32_t PLAN_MAGIC = 0x46455043;  // "FEPC"
 
 struct PlanLayout {
-  size_t off_adj_ptr, off_cursor, off_adj, off_rank, off_scan, total;
+  size_t off_adj_ptr, off_cursor, off_adj, off_rank, off_scan, off_tasks, off_lanes, total;
   size_t scan_blocks;
+  int64_t tasks_max, tiles_max;
 };
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -58,8 +64,126 @@ PlanLayout plan_layout(int64_t n_cells, int n_phi, int64_t n_dofs) {
   P.scan_blocks = (size_t)(n_dofs + 1 + SCAN_TILE - 1) / SCAN_TILE;
   P.off_scan = off;
   off = a256(off + sizeof(int64_t) * (P.scan_blocks + 1));
+  // Fused schedule.  Consecutive tasks hold more than FUSED_SPAN entries
+  // together unless a task closed on its tile cap (at least 12*16 - max_deg
+  // pairs), so the number of tasks is bounded by 2 nnz / SPAN + pairs / 64 + 2
+  // with nnz <= pairs * n_phi; every task adds at most one partial tile.
+  const int64_t pairs = n_cells * n_phi;
+  P.tasks_max = std::min<int64_t>(n_dofs, 2 * pairs * n_phi / FUSED_SPAN + pairs / 64 + 2);
+  P.tiles_max = (pairs + 15) / 16 + P.tasks_max;
+  P.off_tasks = off;
+  off = a256(off + sizeof(FusedTask) * P.tasks_max);
+  P.off_lanes = off;
+  off = a256(off + sizeof(FusedLane) * 16 * P.tiles_max);
   P.total = off;
   return P;
+}
+
+// Row-ownership schedule of the fused numeric path (host, once per dof map).
+// Rows are packed in order into tasks of at most FUSED_SPAN CSR entries and
+// FUSED_TILE_MAX tiles; each task's (cell, local index) pairs are dealt into
+// 16-lane tiles by sweeping its rows, one pair per row per sweep, in
+// adjacency order, so repeated rows inside a tile are rare and their lanes
+// carry increasing round numbers.  Returns false when a row is too long or
+// the bounds of the layout would be exceeded.
+bool build_fused_schedule(const std::vector<int64_t> &rp, const std::vector<int64_t> &ap,
+                          const std::vector<int64_t> &adj, int64_t n_rows,
+                          const PlanLayout &P, std::vector<FusedTask> &tasks,
+                          std::vector<FusedLane> &lanes) {
+  tasks.clear();
+  lanes.clear();
+  std::vector<int64_t> cursor;
+  std::vector<int> in_tile;
+  int64_t r = 0;
+  while (r < n_rows) {
+    const int64_t r0 = r;
+    int64_t span = 0, npairs = 0;
+    while (r < n_rows) {
+      const int64_t len = rp[r + 1] - rp[r], deg = ap[r + 1] - ap[r];
+      if (len > FUSED_SPAN || deg > 16 * FUSED_TILE_MAX) return false;
+      if (r > r0 && (span + len > FUSED_SPAN || npairs + deg > 16 * FUSED_TILE_MAX)) break;
+      span += len;
+      npairs += deg;
+      ++r;
+    }
+    const int64_t nr = r - r0;
+    cursor.assign(nr, 0);
+    in_tile.assign(nr, 0);
+    FusedTask tk;
+    tk.r0 = (int32_t)r0;
+    tk.r1 = (int32_t)r;
+    tk.t0 = (int32_t)(lanes.size() / 16);
+    tk.base = rp[r0];
+    tk.span = (int32_t)(rp[r] - rp[r0]);
+    tk.pad = 0;
+    int64_t left = npairs;
+    int nt = 0;
+    while (left > 0) {
+      std::fill(in_tile.begin(), in_tile.end(), 0);
+      int filled = 0;
+      while (filled < 16 && left > 0) {
+        for (int64_t q = 0; q < nr && filled < 16; ++q) {
+          const int64_t g = r0 + q;
+          if (cursor[q] < ap[g + 1] - ap[g]) {
+            const int64_t ent = adj[ap[g] + cursor[q]];
+            FusedLane L;
+            L.cell = (int32_t)(ent >> 8);
+            L.j = (uint8_t)(ent & 255);
+            L.rowoff = (uint16_t)(rp[g] - rp[r0]);
+            L.round = (uint8_t)in_tile[q]++;
+            lanes.push_back(L);
+            ++cursor[q];
+            ++filled;
+            --left;
+          }
+        }
+      }
+      for (; filled < 16; ++filled) {
+        FusedLane L;
+        L.cell = -1;
+        L.j = 0;
+        L.rowoff = 0;
+        L.round = 0;
+        lanes.push_back(L);
+      }
+      ++nt;
+    }
+    tk.nt = nt;
+    tasks.push_back(tk);
+    if ((int64_t)tasks.size() > P.tasks_max || (int64_t)(lanes.size() / 16) > P.tiles_max) return false;
+  }
+  return true;
+}
+
+// Geometry pass of the fused path: one thread per cell, FP64 (Section 4.2).
+__global__ void k_geometry(const double *coords, int64_t n_cells, int d, CellGeo *geo,
+                           int32_t *status) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cells) return;
+  double G[3][3], adet;
+  const bool ok = cell_geometry(d, coords + c * (d + 1) * d, G, adet);
+  CellGeo g;
+  g.g[0] = G[0][0];
+  g.g[1] = G[0][1];
+  g.g[2] = G[0][2];
+  g.g[3] = G[1][1];
+  g.g[4] = G[1][2];
+  g.g[5] = G[2][2];
+  g.adet = adet;
+  g.ok = ok ? 1.0 : 0.0;
+  geo[c] = g;
+  if (!ok) atomicOr(status, STATUS_DEGENERATE);
+}
+
+fe_status launch_fused(const FusedLaunch &a) {
+  switch (a.L->prec) {
+    case FE_FP64: return launch_fused_fp64(a);
+    case FE_FP32: return launch_fused_fp32(a);
+    case FE_FP16_ACC32: return launch_fused_fp16(a);
+    case FE_BF16_ACC32: return launch_fused_bf16(a);
+    case FE_SPLITFP16_ACC32: return launch_fused_split(a);
+  }
+  return FE_EUNSUPPORTED;
 }
 
 // ---------------------------------------------------------------- kernels
@@ -363,8 +487,9 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
   const int64_t n_cells = m->n_cells, n_dofs = m->n_dofs;
   const size_t elt = (forms[0].precision == FE_FP64) ? 8 : 4;
   const PlanLayout P = plan_layout(n_cells, n_phi, n_dofs);
-  const size_t ws_need = std::max<size_t>(256, (size_t)n_forms * n_cells * n_phi * n_phi * elt);
-  if (!plan || (phase == FE_NUMERIC && !workspace)) {
+  const size_t geo_offset = a256((size_t)n_forms * n_cells * n_phi * n_phi * elt);
+  const size_t ws_need = std::max<size_t>(256, geo_offset + sizeof(CellGeo) * (size_t)n_cells);
+  if (!plan || ((phase == FE_NUMERIC || phase == FE_NUMERIC_GATHER) && !workspace)) {
     if (!plan_bytes && !ws_bytes) return FE_EINVAL;
     if (plan_bytes) *plan_bytes = P.total;
     if (ws_bytes) *ws_bytes = ws_need;
@@ -435,6 +560,7 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
     for (int f = 0; f < n_forms; ++f) {
       mats[f].n_rows = n_dofs;
       mats[f].nnz = nnz;
+      mats[f].max_row_len = h.max_len;
     }
     if (h.max_len >= 65536) return FE_EOVERFLOW;
     return FE_OK;
@@ -468,15 +594,63 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
     }
     if (hipGetLastError() != hipSuccess) return FE_EHIP;
     if (!sync_ok(s)) return FE_EHIP;
+    // fused schedule (host): needs row_ptr and the sorted adjacency
+    h.ntasks = 0;
+    h.ntiles = 0;
+    if (h.max_len <= FUSED_SPAN && n_cells > 0) {
+      std::vector<int64_t> rp(n_dofs + 1), apv(n_dofs + 1), adjv((size_t)n_cells * n_phi);
+      if (hipMemcpy(rp.data(), row_ptr, sizeof(int64_t) * rp.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(apv.data(), adj_ptr, sizeof(int64_t) * apv.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(adjv.data(), adj, sizeof(int64_t) * adjv.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        return FE_EHIP;
+      std::vector<FusedTask> tasks;
+      std::vector<FusedLane> lanes;
+      if (build_fused_schedule(rp, apv, adjv, n_dofs, P, tasks, lanes)) {
+        if (hipMemcpy(pb + P.off_tasks, tasks.data(), sizeof(FusedTask) * tasks.size(),
+                      hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(pb + P.off_lanes, lanes.data(), sizeof(FusedLane) * lanes.size(),
+                      hipMemcpyHostToDevice) != hipSuccess)
+          return FE_EHIP;
+        h.ntasks = (int32_t)tasks.size();
+        h.ntiles = (int32_t)(lanes.size() / 16);
+      }
+    }
+    if (hipMemcpy(hdr_d, &h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess) return FE_EHIP;
     return FE_OK;
   }
 
-  if (phase != FE_NUMERIC) return FE_EINVAL;
+  if (phase != FE_NUMERIC && phase != FE_NUMERIC_GATHER) return FE_EINVAL;
   if (ws_bytes && *ws_bytes < ws_need) return FE_ESIZE;
   if (!mats[0].col_idx) return FE_EINVAL;
   for (int f = 0; f < n_forms; ++f)
     if (!form_bufs || !form_bufs[f] || !mats[f].values) return FE_EINVAL;
   if (n_cells == 0) return FE_OK;  // values of an empty pattern: nothing to write
+  bool fused = phase == FE_NUMERIC && mats[0].max_row_len > 0 &&
+               mats[0].max_row_len <= FUSED_SPAN;
+  for (int f = 0; f < n_forms; ++f) fused = fused && fused_eligible(L[f]);
+  if (fused) {
+    CellGeo *geo = (CellGeo *)((unsigned char *)workspace + geo_offset);
+    hipLaunchKernelGGL(k_geometry, dim3((unsigned)((n_cells + 255) / 256)), dim3(256), 0, s,
+                       m->cell_coords, n_cells, L[0].d, geo, (int32_t *)form_bufs[0]);
+    if (hipGetLastError() != hipSuccess) return FE_EHIP;
+    for (int f = 0; f < n_forms; ++f) {
+      FusedLaunch a;
+      a.L = &L[f];
+      a.form_buf = (const unsigned char *)form_bufs[f];
+      a.geo = geo;
+      a.tasks = (const FusedTask *)(pb + P.off_tasks);
+      a.ntasks = &hdr_d->ntasks;
+      a.ntasks_max = P.tasks_max;
+      a.lanes = (const FusedLane *)(pb + P.off_lanes);
+      a.rank = rank;
+      a.row_ptr = row_ptr;
+      a.values = mats[f].values;
+      a.stream = stream;
+      fe_status st = launch_fused(a);
+      if (st != FE_OK) return st;
+    }
+    return FE_OK;
+  }
   void *Aloc[4] = {nullptr, nullptr, nullptr, nullptr};
   void *V[4] = {nullptr, nullptr, nullptr, nullptr};
   const size_t stride = (size_t)n_cells * n_phi * n_phi * elt;

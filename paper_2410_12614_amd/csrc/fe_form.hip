@@ -192,6 +192,16 @@ extern "C" fe_status fe_form_prepare(const fe_form_desc *f, void *form_buf, size
 }
 
 namespace fe {
+// The fused path needs the weighted table staged in LDS next to the row
+// buffers (see fe_fused.h): 8 waves x FUSED_SPAN values + table (+ fragments).
+bool fused_eligible(const FormLayout &L) {
+  if (L.has_coeff) return false;
+  const size_t real = (L.prec == FE_FP64) ? 8 : 4;
+  const size_t rows_bytes = (size_t)FUSED_WAVES * FUSED_SPAN * real;
+  const size_t wtab_bytes = (size_t)L.ndt * L.n_phi * (L.n_q_pad + 16 / real) * real;
+  return wtab_bytes + rows_bytes <= 156 * 1024;
+}
+
 fe_status launch_cell(const CellLaunch &a) {
   switch (a.L->prec) {
     case FE_FP64: return launch_cell_fp64(a);

@@ -76,6 +76,55 @@ fe_status launch_cell_bf16(const CellLaunch &a);
 fe_status launch_cell_split(const CellLaunch &a);
 fe_status launch_cell(const CellLaunch &a);
 
+// ---- fused (row-ownership) numeric path, see fe_fused.h ----
+constexpr int FUSED_SPAN = 1024;    // CSR entries per task (LDS row buffer of one wave)
+constexpr int FUSED_WAVES = 8;      // waves per workgroup
+constexpr int FUSED_TT = 2;         // tiles formed together (share the B^T fragments)
+constexpr int FUSED_TILE_MAX = 12;  // tiles per task
+
+struct FusedTask {
+  int32_t r0, r1;  // rows [r0, r1)
+  int32_t t0, nt;  // tiles [t0, t0 + nt)
+  int64_t base;    // row_ptr[r0]: first CSR entry of the task
+  int32_t span;    // row_ptr[r1] - row_ptr[r0]
+  int32_t pad;
+};
+
+struct FusedLane {
+  int32_t cell;     // < 0: idle lane
+  uint16_t rowoff;  // offset of the row inside the task's CSR span
+  uint8_t j;        // local index of the row's dof in the cell
+  uint8_t round;    // earlier lanes of the tile holding the same row
+};
+
+// Per-cell FP64 geometry from the geometry pass: symmetric G
+// (G00 G01 G02 G11 G12 G22), |det J| and a validity flag.
+struct CellGeo {
+  double g[6];
+  double adet;
+  double ok;
+};
+
+struct FusedLaunch {
+  const FormLayout *L;
+  const unsigned char *form_buf;
+  const CellGeo *geo;
+  const FusedTask *tasks;
+  const int32_t *ntasks;  // device: number of tasks
+  int64_t ntasks_max;     // host bound used to size the grid
+  const FusedLane *lanes;
+  const uint16_t *rank;
+  const int64_t *row_ptr;
+  void *values;
+  void *stream;
+};
+bool fused_eligible(const FormLayout &L);
+fe_status launch_fused_fp64(const FusedLaunch &a);
+fe_status launch_fused_fp32(const FusedLaunch &a);
+fe_status launch_fused_fp16(const FusedLaunch &a);
+fe_status launch_fused_bf16(const FusedLaunch &a);
+fe_status launch_fused_split(const FusedLaunch &a);
+
 // Matrix-core tile choice: MT = ceil(n_phi / 16) row tiles of B^T and JC
 // columns j per wave per pass (4 waves per workgroup).
 void tile_choice(int n_phi, int regmul, int *mt, int *jc);

@@ -41,11 +41,11 @@ def gpu():
     torch.cuda.synchronize()
 
 
-def run_assembly(mesh, forms, prec, q, coeff=None):
+def run_assembly(mesh, forms, prec, q, coeff=None, gather=False):
     descs = [api.form_desc(mesh.d, mesh.degree, q, f, prec, has_coeff=coeff is not None) for f in forms]
     mv = api.MeshView.from_numpy(mesh.cell_coords, mesh.dofmap, mesh.n_dofs, coeff)
     asm = api.Assembly(mv, descs)
-    vals = asm.numeric()
+    vals = asm.numeric(gather=gather)
     torch.cuda.synchronize()
     st = asm.status()
     return asm, [v[:asm.nnz].double().cpu().numpy() for v in vals], st
@@ -77,16 +77,17 @@ def mesh_of(name):
     return _MESH[name]
 
 
+@pytest.mark.parametrize("path", ["numeric", "gather"])
 @pytest.mark.parametrize("name", ["c1", "c2s", "c3s"])
 @pytest.mark.parametrize("prec", ["fp64", "fp16", "split", "fp32", "bf16"])
-def test_assembly_parity(name, prec):
+def test_assembly_parity(name, prec, path):
     if name == "c1" and prec != "fp64":
         pytest.skip("c1 is the FP64 correctness configuration")
     mesh = mesh_of(name)
     _, forms, q, has_c = CASES[name]
     coeff = mesh.coeff if has_c else None
-    say(f"[parity] {name} {prec} cells={mesh.n_cells} p={mesh.degree} q={q}")
-    asm, vals, st = run_assembly(mesh, forms, prec, q, coeff)
+    say(f"[parity] {name} {prec} {path} cells={mesh.n_cells} p={mesh.degree} q={q}")
+    asm, vals, st = run_assembly(mesh, forms, prec, q, coeff, gather=(path == "gather"))
     assert all(s == 0 for s in st), st
     for f, v in zip(forms, vals):
         rp, ci, ref, _ = oracle_csr(name, mesh, f, q, coeff)
@@ -97,7 +98,7 @@ def test_assembly_parity(name, prec):
             err = np.abs(v - ref).max() / scale
         else:
             err = np.linalg.norm(v - ref) / np.linalg.norm(ref)
-        say(f"[parity] {name} {prec} {f}: err {err:.3e} (bar {TOL[prec]:.0e})")
+        say(f"[parity] {name} {prec} {path} {f}: err {err:.3e} (bar {TOL[prec]:.0e})")
         assert err <= TOL[prec], (name, prec, f, err)
 
 
@@ -126,6 +127,26 @@ def test_all_degrees_local_matrices(p, q, prec):
             err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
         say(f"[local] p={p} {prec} {form}: err {err:.3e}")
         assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16", "split", "fp32", "bf16"])
+@pytest.mark.parametrize("p,q", [(2, 4), (4, 8), (5, 10)])
+def test_fused_equals_gather_bitwise(prec, p, q):
+    """The fused row-ownership path and the cell-kernel + row-gather path sum
+    every entry in the same order (cell ascending) from the same matrix-core
+    columns, so their values agree bit for bit."""
+    mesh = config_mesh("c2", n=3 if p < 5 else 2, degree=p)
+    descs = [api.form_desc(3, p, q, f, prec) for f in ("mass", "stiffness")]
+    mv = api.MeshView.from_numpy(mesh.cell_coords, mesh.dofmap, mesh.n_dofs)
+    asm = api.Assembly(mv, descs)
+    assert 0 < asm.max_row_len <= 1024
+    a = [v.clone() for v in asm.numeric()]
+    b = asm.numeric(gather=True)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        diff = (x != y).sum().item()
+        say(f"[fused=gather] p={p} {prec}: {diff} differing entries of {x.numel()}")
+        assert torch.equal(x, y)
 
 
 def test_numeric_is_bitwise_repeatable():
