@@ -111,6 +111,8 @@ typedef struct fe_csr {
   int64_t n_rows;   /* = n_dofs                                               */
   int64_t nnz;      /* written by FE_SYMBOLIC_COUNT                            */
   int64_t max_row_len; /* written by FE_SYMBOLIC_COUNT: longest row           */
+  int64_t schedule; /* written by FE_SYMBOLIC_FILL: owner tasks of the fused
+                       numeric schedule, 0 when none was built              */
   int64_t *row_ptr; /* device [n_rows+1]                                       */
   int32_t *col_idx; /* device [nnz], ascending and unique per row              */
   void *values;     /* device [nnz], double for FE_FP64 else float             */
@@ -192,7 +194,8 @@ fe_status fe_cell_kernels(const fe_form_desc *f, const void *form_buf, const fe_
  *       position of every local entry inside its CSR row.  Its size depends
  *       only on the mesh (n_cells, n_phi, n_dofs).
  *   workspace / ws_bytes : device scratch for the numeric phase (local
- *       matrices of all forms), sized by a query with workspace == NULL.
+ *       matrices of all forms for the gather, per-cell factors of H for the
+ *       fused path), sized by a query with workspace == NULL.
  *
  * Phases:
  *   FE_SYMBOLIC_COUNT : fills mats[0].row_ptr and writes nnz and max_row_len
@@ -200,15 +203,18 @@ fe_status fe_cell_kernels(const fe_form_desc *f, const void *form_buf, const fe_
  *       FE_EOVERFLOW when a row holds 65536 or more entries.
  *   FE_SYMBOLIC_FILL  : fills mats[0].col_idx (sorted) and the plan: the
  *       position of every local entry inside its CSR row and, when every
- *       row fits one owner task, the row-ownership schedule of the fused
- *       numeric path.  SYNCHRONISES the stream.
- *   FE_NUMERIC : writes the values of every form.  For forms without a
- *       coefficient whose rows fit one owner task (mats[0].max_row_len <=
- *       1024) it runs a per-cell FP64 geometry pass and one fused kernel
- *       per form: every wave owns a range of CSR rows in LDS, computes the
- *       local rows A_K(j, :) of exactly the dofs it owns on the matrix cores
- *       and writes its rows once.  Otherwise it runs the cell kernels into
- *       the workspace followed by the row gather.  Either way every entry's
+ *       row fits one owner task (at most 1024 entries and 64 incident
+ *       (cell, local index) pairs), the row-ownership schedule of the fused
+ *       numeric path; writes its task count into every mats[f].schedule.
+ *       SYNCHRONISES the stream.
+ *   FE_NUMERIC : writes the values of every form.  With a schedule
+ *       (mats[0].schedule > 0, the mats of the FILL phase) and forms without
+ *       a coefficient whose tables fit the on-chip memory, it runs per form a
+ *       per-cell FP64 geometry pass and one fused kernel: every wave owns a
+ *       range of CSR rows in LDS, computes the local rows A_K(j, :) of
+ *       exactly the dofs it owns on the matrix cores and writes its rows
+ *       once.  Otherwise it runs the cell kernels into the workspace
+ *       followed by the row gather.  Either way every entry's
  *       contributions are summed in the fixed order cell ascending and every
  *       value is written exactly once (no separate zero-fill).
  *       Asynchronous, never synchronises, bitwise repeatable.

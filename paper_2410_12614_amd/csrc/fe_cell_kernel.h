@@ -213,6 +213,67 @@ __device__ __forceinline__ bool cell_geometry(int d, const double *x, double G[3
   return ok;
 }
 
+// Factors of H for one cell: the geometry tensor (|det J| for the mass
+// form) times the exact power-of-two scale sigma = 2^e with
+// |H| <= sigma max|w B| max_s sum_t |G_st| max_q |z_q| < 2^15, rounded once to
+// the arithmetic type of H, and the exact inverse of sigma and of the B^T
+// scale.  Invalid (padding) cells get zero factors, degenerate cells NaN.
+template <class P>
+__device__ __forceinline__ void cell_factors(const FormHeader *hdr, int nd, bool valid, bool ok,
+                                             const double G[3][3], double adet, double zmax,
+                                             typename P::real Gp[3][3], typename P::real &inv) {
+  typedef typename P::real T;
+  double gabs = adet;
+  if (nd > 1) {
+    gabs = 0.0;
+    for (int s = 0; s < 3; ++s) gabs = fmax(gabs, fabs(G[s][0]) + fabs(G[s][1]) + fabs(G[s][2]));
+  }
+  double sK = 1.0;
+  int esK = 0;
+  if constexpr (P::SCALED) {
+    const double bound = hdr->max_wb * gabs * zmax;
+    if (bound > 0.0 && isfinite(bound)) {
+      esK = 14 - ilogb(bound);
+      sK = ldexp(1.0, esK);
+    }
+  }
+  for (int s = 0; s < 3; ++s)
+    for (int t = 0; t < 3; ++t) {
+      double v = (nd == 1) ? (s == 0 && t == 0 ? adet : 0.0) : G[s][t];
+      if (!valid) v = 0.0;
+      else if (!ok) v = NAN;
+      Gp[s][t] = (T)(v * sK);
+    }
+  // both scales are exact powers of two: invert by exponents
+  inv = (T)ldexp(1.0, -esK - ilogb(hdr->b_scale));
+}
+
+// H for one lane: h[e] = sum_t Gs[t] w[t][e] (times z[e] with a coefficient),
+// always summed t = 0, 1, 2 from zero so that every kernel forms the same
+// values.
+template <class T, int NDT, int KPL>
+__device__ __forceinline__ void form_h(const T *Gs, const T (&w)[NDT][KPL], T (&h)[KPL]) {
+#pragma unroll
+  for (int e = 0; e < KPL; ++e) {
+    T x = 0;
+#pragma unroll
+    for (int t = 0; t < NDT; ++t) x += Gs[t] * w[t][e];
+    h[e] = x;
+  }
+}
+
+// 8 (KPL = 8) or 1 consecutive entries of the weighted table
+template <class T, int KPL>
+__device__ __forceinline__ void load_w(const T *w, T (&v)[KPL]) {
+  if constexpr (KPL == 8) {
+    const float4 w0 = ((const float4 *)w)[0], w1 = ((const float4 *)w)[1];
+    v[0] = w0.x; v[1] = w0.y; v[2] = w0.z; v[3] = w0.w;
+    v[4] = w1.x; v[5] = w1.y; v[6] = w1.z; v[7] = w1.w;
+  } else {
+    v[0] = w[0];
+  }
+}
+
 template <class P>
 __device__ __forceinline__ typename P::frag lds_frag(const unsigned char *base, size_t idx) {
   return *(const typename P::frag *)(base + idx * sizeof(typename P::frag));
@@ -308,33 +369,9 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
       zmax = m;
     }
 
-    // ---- per-cell exact power-of-two scale ----
-    double gabs = adet;
-    if (a.nd > 1) {
-      gabs = 0.0;
-      for (int s = 0; s < 3; ++s) gabs = fmax(gabs, fabs(G[s][0]) + fabs(G[s][1]) + fabs(G[s][2]));
-    }
-    double sK = 1.0;
-    int esK = 0;
-    if constexpr (P::SCALED) {
-      // |H| <= sK * max|w B| * max_s sum_t |G_st| * max_q |z_q| < 2^15 <= FP16 max
-      const double bound = a.hdr->max_wb * gabs * zmax;
-      if (bound > 0.0 && isfinite(bound)) {
-        esK = 14 - ilogb(bound);
-        sK = ldexp(1.0, esK);
-      }
-    }
     if (valid && !ok && wave == 0 && kb == 0) atomicOr(a.status, STATUS_DEGENERATE);
-    T Gp[3][3];
-    for (int s = 0; s < 3; ++s)
-      for (int t = 0; t < 3; ++t) {
-        double v = (a.nd == 1) ? (s == 0 && t == 0 ? adet : 0.0) : G[s][t];
-        if (!valid) v = 0.0;
-        else if (!ok) v = NAN;
-        Gp[s][t] = (T)(v * sK);
-      }
-    // sK and the B scale are exact powers of two: invert by exponents
-    const T inv = (T)ldexp(1.0, -esK - ilogb(a.hdr->b_scale));
+    T Gp[3][3], inv;
+    cell_factors<P>(a.hdr, a.nd, valid, ok, G, adet, zmax, Gp, inv);
 
     const T *wt = (const T *)a.wtab;
     const int npass = (nphi + NW * JC - 1) / (NW * JC);
@@ -350,26 +387,28 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
           acc[mt][jj] = ACC{0, 0, 0, 0};
           if constexpr (P::SPLIT) acc2[mt][jj] = ACC{0, 0, 0, 0};
         }
-      for (int ks = 0; ks < nks; ++ks) {
-        const int k0 = ks * P::KSTEP;
-        const int s = k0 / n_q_pad;
-        const int qb = k0 - s * n_q_pad + kb * P::KPL;
-        FRAG afr[MT];
-        FRAG afl[P::SPLIT ? MT : 1];
+      // K = (s, q) is walked as q-chunk outer, s inner: one chunk of the
+      // weighted table serves all s, and the accumulation order of every
+      // output is (chunk 0: s = 0..NDT-1), (chunk 1: ...), as in the fused
+      // kernel.
+      const int nqc = n_q_pad / P::KSTEP;
+      for (int qc = 0; qc < nqc; ++qc) {
+        const int qb = qc * P::KSTEP + kb * P::KPL;
+        FRAG afr[NDT][MT];
+        FRAG afl[P::SPLIT ? NDT : 1][P::SPLIT ? MT : 1];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const size_t fi = ((size_t)mt * nks + ks) * 64 + lane;
-          if constexpr (STAGE >= 1) {
-            afr[mt] = lds_frag<P>(s_af, fi);
-            if constexpr (P::SPLIT) afl[mt] = lds_frag<P>(s_afl, fi);
-          } else {
-            afr[mt] = P::load(a.afrag, fi);
-            if constexpr (P::SPLIT) afl[mt] = P::load(a.afrag_lo, fi);
+        for (int s = 0; s < NDT; ++s)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const size_t fi = frag_slot(mt, s, qc, MT, NDT) * 64 + lane;
+            if constexpr (STAGE >= 1) {
+              afr[s][mt] = lds_frag<P>(s_af, fi);
+              if constexpr (P::SPLIT) afl[s][mt] = lds_frag<P>(s_afl, fi);
+            } else {
+              afr[s][mt] = P::load(a.afrag, fi);
+              if constexpr (P::SPLIT) afl[s][mt] = P::load(a.afrag_lo, fi);
+            }
           }
-        }
-        T g[NDT];
-#pragma unroll
-        for (int t = 0; t < NDT; ++t) g[t] = (s == 0) ? Gp[0][t] : ((s == 1) ? Gp[1][t] : Gp[2][t]);
         T zf[P::KPL];
         if constexpr (COEFF) {
 #pragma unroll
@@ -378,42 +417,34 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
 #pragma unroll
         for (int jj = 0; jj < JC; ++jj) {
           const int jl = min(jb + jj, nphi - 1);
-          T h[P::KPL];
-#pragma unroll
-          for (int e = 0; e < P::KPL; ++e) h[e] = 0;
+          T wv[NDT][P::KPL];
 #pragma unroll
           for (int t = 0; t < NDT; ++t) {
-            const T *w;
-            if constexpr (STAGE == 2) w = s_wt + ((size_t)t * nphi + jl) * n_q_pad + qb;
-            else w = wt + ((size_t)t * nphi + jl) * n_q_pad + qb;
-            T wv[P::KPL];
-            if constexpr (P::KPL == 8) {
-              const float4 w0 = ((const float4 *)w)[0], w1 = ((const float4 *)w)[1];
-              wv[0] = w0.x; wv[1] = w0.y; wv[2] = w0.z; wv[3] = w0.w;
-              wv[4] = w1.x; wv[5] = w1.y; wv[6] = w1.z; wv[7] = w1.w;
+            if constexpr (STAGE == 2) load_w<T, P::KPL>(s_wt + ((size_t)t * nphi + jl) * n_q_pad + qb, wv[t]);
+            else load_w<T, P::KPL>(wt + ((size_t)t * nphi + jl) * n_q_pad + qb, wv[t]);
+          }
+#pragma unroll
+          for (int s = 0; s < NDT; ++s) {
+            T h[P::KPL];
+            form_h<T, NDT, P::KPL>(Gp[s], wv, h);
+            if constexpr (COEFF) {
+#pragma unroll
+              for (int e = 0; e < P::KPL; ++e) h[e] *= zf[e];
+            }
+            if constexpr (P::SPLIT) {
+              FRAG hh, hl;
+              P::pack2(h, hh, hl);
+#pragma unroll
+              for (int mt = 0; mt < MT; ++mt) {
+                acc[mt][jj] = P::mma(afr[s][mt], hh, acc[mt][jj]);
+                acc2[mt][jj] = P::mma(afr[s][mt], hl, acc2[mt][jj]);
+                acc2[mt][jj] = P::mma(afl[s][mt], hh, acc2[mt][jj]);
+              }
             } else {
-              wv[0] = w[0];
+              const FRAG hf = P::pack(h);
+#pragma unroll
+              for (int mt = 0; mt < MT; ++mt) acc[mt][jj] = P::mma(afr[s][mt], hf, acc[mt][jj]);
             }
-#pragma unroll
-            for (int e = 0; e < P::KPL; ++e) h[e] += g[t] * wv[e];
-          }
-          if constexpr (COEFF) {
-#pragma unroll
-            for (int e = 0; e < P::KPL; ++e) h[e] *= zf[e];
-          }
-          if constexpr (P::SPLIT) {
-            FRAG hh, hl;
-            P::pack2(h, hh, hl);
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-              acc[mt][jj] = P::mma(afr[mt], hh, acc[mt][jj]);
-              acc2[mt][jj] = P::mma(afr[mt], hl, acc2[mt][jj]);
-              acc2[mt][jj] = P::mma(afl[mt], hh, acc2[mt][jj]);
-            }
-          } else {
-            const FRAG hf = P::pack(h);
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) acc[mt][jj] = P::mma(afr[mt], hf, acc[mt][jj]);
           }
         }
       }

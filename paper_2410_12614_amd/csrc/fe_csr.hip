@@ -44,7 +44,12 @@ struct PlanLayout {
   size_t off_adj_ptr, off_cursor, off_adj, off_rank, off_scan, off_tasks, off_lanes, total;
   size_t scan_blocks;
   int64_t tasks_max, tiles_max;
+  int rstride;
 };
+
+// Rank rows are padded to whole 16-row tiles (padding entries hold 0xffff)
+// so that the fused kernel reads a lane's four ranks with one aligned load.
+int rank_stride(int n_phi) { return (n_phi + 15) / 16 * 16; }
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -59,17 +64,20 @@ PlanLayout plan_layout(int64_t n_cells, int n_phi, int64_t n_dofs) {
   off = a256(off + sizeof(int64_t) * n_dofs);
   P.off_adj = off;
   off = a256(off + sizeof(int64_t) * (size_t)n_cells * n_phi);
+  P.rstride = rank_stride(n_phi);
   P.off_rank = off;
-  off = a256(off + sizeof(uint16_t) * (size_t)n_cells * n_phi * n_phi);
+  off = a256(off + sizeof(uint16_t) * (size_t)n_cells * n_phi * P.rstride);
   P.scan_blocks = (size_t)(n_dofs + 1 + SCAN_TILE - 1) / SCAN_TILE;
   P.off_scan = off;
   off = a256(off + sizeof(int64_t) * (P.scan_blocks + 1));
-  // Fused schedule.  Consecutive tasks hold more than FUSED_SPAN entries
-  // together unless a task closed on its tile cap (at least 12*16 - max_deg
-  // pairs), so the number of tasks is bounded by 2 nnz / SPAN + pairs / 64 + 2
-  // with nnz <= pairs * n_phi; every task adds at most one partial tile.
+  // Fused schedule.  A task holds at least FUSED_SPAN / 2 entries unless the
+  // next row did not fit (then the next task holds more than FUSED_SPAN / 2)
+  // or it closed on its tile cap, so for meshes whose rows have at most 32
+  // incident pairs the number of tasks is below 4 nnz / SPAN + pairs / 32 + 2
+  // with nnz <= pairs * n_phi; every task adds at most one partial tile.  A
+  // schedule that does not fit is not used (the numeric phase then gathers).
   const int64_t pairs = n_cells * n_phi;
-  P.tasks_max = std::min<int64_t>(n_dofs, 2 * pairs * n_phi / FUSED_SPAN + pairs / 64 + 2);
+  P.tasks_max = std::min<int64_t>(n_dofs, 4 * pairs * n_phi / FUSED_SPAN + pairs / 32 + 2);
   P.tiles_max = (pairs + 15) / 16 + P.tasks_max;
   P.off_tasks = off;
   off = a256(off + sizeof(FusedTask) * P.tasks_max);
@@ -81,11 +89,14 @@ PlanLayout plan_layout(int64_t n_cells, int n_phi, int64_t n_dofs) {
 
 // Row-ownership schedule of the fused numeric path (host, once per dof map).
 // Rows are packed in order into tasks of at most FUSED_SPAN CSR entries and
-// FUSED_TILE_MAX tiles; each task's (cell, local index) pairs are dealt into
-// 16-lane tiles by sweeping its rows, one pair per row per sweep, in
-// adjacency order, so repeated rows inside a tile are rare and their lanes
-// carry increasing round numbers.  Returns false when a row is too long or
-// the bounds of the layout would be exceeded.
+// FUSED_TILE_MAX tiles of 16 (cell, local index) pairs.  Among the feasible
+// ends of a task holding at least FUSED_SPAN / 2 entries, the one whose pairs
+// fill their tiles best is taken (then the longest), since idle lanes of a
+// partial tile cost as much as busy ones.  Each task's pairs are dealt into
+// tiles by sweeping its rows, one pair per row per sweep, in adjacency order,
+// so repeated rows inside a tile are rare and their lanes carry increasing
+// round numbers.  Returns false when a row is too long or has too many pairs,
+// or the bounds of the layout would be exceeded.
 bool build_fused_schedule(const std::vector<int64_t> &rp, const std::vector<int64_t> &ap,
                           const std::vector<int64_t> &adj, int64_t n_rows,
                           const PlanLayout &P, std::vector<FusedTask> &tasks,
@@ -94,17 +105,37 @@ bool build_fused_schedule(const std::vector<int64_t> &rp, const std::vector<int6
   lanes.clear();
   std::vector<int64_t> cursor;
   std::vector<int> in_tile;
+  constexpr int64_t PAIRS_MAX = 16 * FUSED_TILE_MAX;
   int64_t r = 0;
   while (r < n_rows) {
     const int64_t r0 = r;
     int64_t span = 0, npairs = 0;
+    int64_t best_end = -1, best_pairs = 0, best_span = 0;
     while (r < n_rows) {
       const int64_t len = rp[r + 1] - rp[r], deg = ap[r + 1] - ap[r];
-      if (len > FUSED_SPAN || deg > 16 * FUSED_TILE_MAX) return false;
-      if (r > r0 && (span + len > FUSED_SPAN || npairs + deg > 16 * FUSED_TILE_MAX)) break;
+      if (len > FUSED_SPAN || deg > PAIRS_MAX) return false;
+      if (r > r0 && (span + len > FUSED_SPAN || npairs + deg > PAIRS_MAX)) break;
       span += len;
       npairs += deg;
       ++r;
+      if (2 * span >= FUSED_SPAN) {
+        // fill fraction npairs / (16 ceil(npairs / 16)), compared exactly
+        const int64_t tiles = (npairs + 15) / 16, btiles = (best_pairs + 15) / 16;
+        bool better = best_end < 0;
+        if (!better) {
+          const int64_t lhs = npairs * btiles, rhs = best_pairs * tiles;
+          better = lhs > rhs || (lhs == rhs && span > best_span);
+        }
+        if (better) {
+          best_end = r;
+          best_pairs = npairs;
+          best_span = span;
+        }
+      }
+    }
+    if (best_end > 0) {
+      r = best_end;
+      npairs = best_pairs;
     }
     const int64_t nr = r - r0;
     cursor.assign(nr, 0);
@@ -146,6 +177,11 @@ bool build_fused_schedule(const std::vector<int64_t> &rp, const std::vector<int6
         L.round = 0;
         lanes.push_back(L);
       }
+      // a tile has 16 lanes, so rounds fit 4 bits; every lane also carries
+      // the tile's last round
+      uint8_t maxr = 0;
+      for (size_t u = lanes.size() - 16; u < lanes.size(); ++u) maxr = std::max(maxr, lanes[u].round);
+      for (size_t u = lanes.size() - 16; u < lanes.size(); ++u) lanes[u].round |= (uint8_t)(maxr << 4);
       ++nt;
     }
     tk.nt = nt;
@@ -153,26 +189,6 @@ bool build_fused_schedule(const std::vector<int64_t> &rp, const std::vector<int6
     if ((int64_t)tasks.size() > P.tasks_max || (int64_t)(lanes.size() / 16) > P.tiles_max) return false;
   }
   return true;
-}
-
-// Geometry pass of the fused path: one thread per cell, FP64 (Section 4.2).
-__global__ void k_geometry(const double *coords, int64_t n_cells, int d, CellGeo *geo,
-                           int32_t *status) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_cells) return;
-  double G[3][3], adet;
-  const bool ok = cell_geometry(d, coords + c * (d + 1) * d, G, adet);
-  CellGeo g;
-  g.g[0] = G[0][0];
-  g.g[1] = G[0][1];
-  g.g[2] = G[0][2];
-  g.g[3] = G[1][1];
-  g.g[4] = G[1][2];
-  g.g[5] = G[2][2];
-  g.adet = adet;
-  g.ok = ok ? 1.0 : 0.0;
-  geo[c] = g;
-  if (!ok) atomicOr(status, STATUS_DEGENERATE);
 }
 
 fe_status launch_fused(const FusedLaunch &a) {
@@ -354,8 +370,8 @@ __global__ __launch_bounds__(256) void k_rows(const int32_t *dofmap, int n_phi,
 
 // One wave per local row (K, i): rank of every dof(K, j) inside CSR row dof(K, i).
 __global__ __launch_bounds__(256) void k_ranks(const int32_t *dofmap, int64_t n_cells, int n_phi,
-                                               const int64_t *row_ptr, const int32_t *col_idx,
-                                               uint16_t *rank) {
+                                               int rstride, const int64_t *row_ptr,
+                                               const int32_t *col_idx, uint16_t *rank) {
   const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (e >= n_cells * n_phi) return;
@@ -364,6 +380,7 @@ __global__ __launch_bounds__(256) void k_ranks(const int32_t *dofmap, int64_t n_
   const int64_t r0 = row_ptr[g];
   const int64_t len = row_ptr[g + 1] - r0;
   const int32_t *row = col_idx + r0;
+  for (int j = n_phi + lane; j < rstride; j += 64) rank[e * rstride + j] = 0xffff;
   for (int j = lane; j < n_phi; j += 64) {
     const int32_t h = dofmap[K * n_phi + j];
     int64_t lo = 0, hi = len;
@@ -372,7 +389,7 @@ __global__ __launch_bounds__(256) void k_ranks(const int32_t *dofmap, int64_t n_
       if (row[mid] < h) lo = mid + 1;
       else hi = mid;
     }
-    rank[e * n_phi + j] = (uint16_t)lo;
+    rank[e * rstride + j] = (uint16_t)lo;
   }
 }
 
@@ -387,7 +404,7 @@ constexpr int GATHER_GROUP = 4;
 template <class T, int NF>
 __global__ __launch_bounds__(256) void k_gather(const int64_t *adj_ptr, const int64_t *adj,
                                                 const uint16_t *rank, const int64_t *row_ptr,
-                                                int64_t n_rows, int n_phi,
+                                                int64_t n_rows, int n_phi, int rstride,
                                                 const T *A0, const T *A1, const T *A2,
                                                 const T *A3, T *V0, T *V1, T *V2, T *V3) {
   constexpr int W = GATHER_W;
@@ -416,8 +433,9 @@ __global__ __launch_bounds__(256) void k_gather(const int64_t *adj_ptr, const in
           rk[u] = -1;
           if (a + u < a1 && j < n_phi) {
             const int64_t ent = adj[a + u];
-            const size_t base = ((size_t)(ent >> 8) * n_phi + (ent & 255)) * n_phi + j;
-            rk[u] = (int)rank[base] - w0;
+            const size_t row = (size_t)(ent >> 8) * n_phi + (ent & 255);
+            const size_t base = row * n_phi + j;
+            rk[u] = (int)rank[row * rstride + j] - w0;
 #pragma unroll
             for (int f = 0; f < NF; ++f) v[u][f] = A[f][base];
           }
@@ -438,11 +456,11 @@ __global__ __launch_bounds__(256) void k_gather(const int64_t *adj_ptr, const in
 
 template <class T, int NF>
 fe_status launch_gather(const int64_t *adj_ptr, const int64_t *adj, const uint16_t *rank,
-                        const int64_t *row_ptr, int64_t n_rows, int n_phi, void *const *A,
-                        void *const *V, hipStream_t s) {
+                        const int64_t *row_ptr, int64_t n_rows, int n_phi, int rstride,
+                        void *const *A, void *const *V, hipStream_t s) {
   const int64_t blocks = (n_rows + 3) / 4;
   hipLaunchKernelGGL((k_gather<T, NF>), dim3((unsigned)blocks), dim3(256), 0, s, adj_ptr, adj, rank,
-                     row_ptr, n_rows, n_phi, (const T *)A[0], (const T *)A[1], (const T *)A[2],
+                     row_ptr, n_rows, n_phi, rstride, (const T *)A[0], (const T *)A[1], (const T *)A[2],
                      (const T *)A[3], (T *)V[0], (T *)V[1], (T *)V[2], (T *)V[3]);
   return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
 }
@@ -488,7 +506,9 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
   const size_t elt = (forms[0].precision == FE_FP64) ? 8 : 4;
   const PlanLayout P = plan_layout(n_cells, n_phi, n_dofs);
   const size_t geo_offset = a256((size_t)n_forms * n_cells * n_phi * n_phi * elt);
-  const size_t ws_need = std::max<size_t>(256, geo_offset + sizeof(CellGeo) * (size_t)n_cells);
+  // per-form factor records of the fused path (FormGeo<double> is the larger)
+  const size_t geo_bytes = a256(sizeof(FormGeo<double>) * (size_t)n_cells);
+  const size_t ws_need = std::max<size_t>(256, geo_offset + (size_t)n_forms * geo_bytes);
   if (!plan || ((phase == FE_NUMERIC || phase == FE_NUMERIC_GATHER) && !workspace)) {
     if (!plan_bytes && !ws_bytes) return FE_EINVAL;
     if (plan_bytes) *plan_bytes = P.total;
@@ -590,7 +610,8 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
     if (n_cells > 0) {
       const int64_t ne = n_cells * n_phi;
       hipLaunchKernelGGL(k_ranks, dim3((unsigned)((ne + 3) / 4)), dim3(256), 0, s, m->dofmap,
-                         n_cells, n_phi, (const int64_t *)row_ptr, mats[0].col_idx, rank);
+                         n_cells, n_phi, P.rstride, (const int64_t *)row_ptr, mats[0].col_idx,
+                         rank);
     }
     if (hipGetLastError() != hipSuccess) return FE_EHIP;
     if (!sync_ok(s)) return FE_EHIP;
@@ -616,6 +637,7 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
       }
     }
     if (hipMemcpy(hdr_d, &h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess) return FE_EHIP;
+    for (int f = 0; f < n_forms; ++f) mats[f].schedule = h.ntasks;
     return FE_OK;
   }
 
@@ -625,25 +647,23 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
   for (int f = 0; f < n_forms; ++f)
     if (!form_bufs || !form_bufs[f] || !mats[f].values) return FE_EINVAL;
   if (n_cells == 0) return FE_OK;  // values of an empty pattern: nothing to write
-  bool fused = phase == FE_NUMERIC && mats[0].max_row_len > 0 &&
-               mats[0].max_row_len <= FUSED_SPAN;
+  // fused row-ownership path when the FILL phase built its schedule
+  bool fused = phase == FE_NUMERIC && mats[0].schedule > 0;
   for (int f = 0; f < n_forms; ++f) fused = fused && fused_eligible(L[f]);
   if (fused) {
-    CellGeo *geo = (CellGeo *)((unsigned char *)workspace + geo_offset);
-    hipLaunchKernelGGL(k_geometry, dim3((unsigned)((n_cells + 255) / 256)), dim3(256), 0, s,
-                       m->cell_coords, n_cells, L[0].d, geo, (int32_t *)form_bufs[0]);
-    if (hipGetLastError() != hipSuccess) return FE_EHIP;
     for (int f = 0; f < n_forms; ++f) {
       FusedLaunch a;
       a.L = &L[f];
       a.form_buf = (const unsigned char *)form_bufs[f];
-      a.geo = geo;
+      a.status = (int32_t *)form_bufs[f];
+      a.coords = m->cell_coords;
+      a.n_cells = n_cells;
+      a.geo = (unsigned char *)workspace + geo_offset + f * geo_bytes;
       a.tasks = (const FusedTask *)(pb + P.off_tasks);
-      a.ntasks = &hdr_d->ntasks;
-      a.ntasks_max = P.tasks_max;
+      a.ntasks = mats[0].schedule;
       a.lanes = (const FusedLane *)(pb + P.off_lanes);
       a.rank = rank;
-      a.row_ptr = row_ptr;
+      a.rstride = P.rstride;
       a.values = mats[f].values;
       a.stream = stream;
       fe_status st = launch_fused(a);
@@ -676,17 +696,17 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
   fe_status st = FE_EINVAL;
   if (elt == 8) {
     switch (n_forms) {
-      case 1: st = launch_gather<double, 1>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
-      case 2: st = launch_gather<double, 2>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
-      case 3: st = launch_gather<double, 3>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
-      case 4: st = launch_gather<double, 4>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
+      case 1: st = launch_gather<double, 1>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, P.rstride, Aloc, V, s); break;
+      case 2: st = launch_gather<double, 2>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, P.rstride, Aloc, V, s); break;
+      case 3: st = launch_gather<double, 3>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, P.rstride, Aloc, V, s); break;
+      case 4: st = launch_gather<double, 4>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, P.rstride, Aloc, V, s); break;
     }
   } else {
     switch (n_forms) {
-      case 1: st = launch_gather<float, 1>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
-      case 2: st = launch_gather<float, 2>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
-      case 3: st = launch_gather<float, 3>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
-      case 4: st = launch_gather<float, 4>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
+      case 1: st = launch_gather<float, 1>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, P.rstride, Aloc, V, s); break;
+      case 2: st = launch_gather<float, 2>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, P.rstride, Aloc, V, s); break;
+      case 3: st = launch_gather<float, 3>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, P.rstride, Aloc, V, s); break;
+      case 4: st = launch_gather<float, 4>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, P.rstride, Aloc, V, s); break;
     }
   }
   return st;

@@ -51,7 +51,7 @@ fe_status compute_layout(const fe_form_desc *f, FormLayout *L) {
   L->kstep = mfma16 ? 32 : 4;
   L->kpl = mfma16 ? 8 : 1;
   L->n_q_pad = (L->n_q + L->kstep - 1) / L->kstep * L->kstep;
-  L->k_pad = L->nd * L->n_q_pad;
+  L->k_pad = L->ndt * L->n_q_pad;  // derivative slabs s >= nd (triangles) are zero
   L->nks = L->k_pad / L->kstep;
   int jc;
   tile_choice(L->n_phi, 1, &L->mt, &jc);
@@ -144,17 +144,20 @@ extern "C" fe_status fe_form_prepare(const fe_form_desc *f, void *form_buf, size
   double b_scale = 1.0;
   if (L.elt_bytes == 2 && max_b > 0.0) b_scale = std::ldexp(1.0, 14 - std::ilogb(max_b));
   hdr.b_scale = b_scale;
-  for (int mt = 0; mt < L.mt; ++mt)
-    for (int ks = 0; ks < L.nks; ++ks)
-      for (int lane = 0; lane < 64; ++lane)
-        for (int e = 0; e < L.kpl; ++e) {
-          const int i = 16 * mt + lane % 16;
-          const int k = ks * L.kstep + (lane / 16) * L.kpl + e;
-          const int s = k / L.n_q_pad, q = k % L.n_q_pad;
-          double v = (i < nphi && q < nq && s < L.nd) ? Bop(s, q, i) * b_scale : 0.0;
-          size_t idx = (((size_t)mt * L.nks + ks) * 64 + lane) * L.kpl + e;
-          store_elt(L.prec, h.data(), L.off_afrag, L.off_afrag_lo, idx, v);
-        }
+  // fragment of row tile mt, derivative s and quadrature chunk qc at slot
+  // frag_slot(mt, s, qc): the fragments one chunk needs are contiguous
+  const int nqc = L.n_q_pad / L.kstep;
+  for (int qc = 0; qc < nqc; ++qc)
+    for (int s = 0; s < L.ndt; ++s)
+      for (int mt = 0; mt < L.mt; ++mt)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int e = 0; e < L.kpl; ++e) {
+            const int i = 16 * mt + lane % 16;
+            const int q = qc * L.kstep + (lane / 16) * L.kpl + e;
+            double v = (i < nphi && q < nq && s < L.nd) ? Bop(s, q, i) * b_scale : 0.0;
+            size_t idx = (frag_slot(mt, s, qc, L.mt, L.ndt) * 64 + lane) * L.kpl + e;
+            store_elt(L.prec, h.data(), L.off_afrag, L.off_afrag_lo, idx, v);
+          }
   // weighted table w_q B_t(q, j), [t][j][n_q_pad]
   double max_wb = 0.0;
   for (int t = 0; t < L.ndt; ++t)
@@ -195,11 +198,7 @@ namespace fe {
 // The fused path needs the weighted table staged in LDS next to the row
 // buffers (see fe_fused.h): 8 waves x FUSED_SPAN values + table (+ fragments).
 bool fused_eligible(const FormLayout &L) {
-  if (L.has_coeff) return false;
-  const size_t real = (L.prec == FE_FP64) ? 8 : 4;
-  const size_t rows_bytes = (size_t)FUSED_WAVES * FUSED_SPAN * real;
-  const size_t wtab_bytes = (size_t)L.ndt * L.n_phi * (L.n_q_pad + 16 / real) * real;
-  return wtab_bytes + rows_bytes <= 156 * 1024;
+  return !L.has_coeff && fused_lds(L, 4, false) <= FUSED_LDS_BUDGET;
 }
 
 fe_status launch_cell(const CellLaunch &a) {

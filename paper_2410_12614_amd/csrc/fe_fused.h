@@ -21,6 +21,11 @@
 // adjacency lists (cell ascending); lanes of one tile holding the same row
 // add in rounds, in that same order.  Every CSR entry is therefore summed in
 // the fixed order cell ascending, exactly as by the row gather.
+//
+// Latency: the per-cell factors of H come from a geometry pass (FormGeo
+// records); the task record, lane records and factors of a wave's next task
+// are loaded while the current task computes.  The lane records of a task
+// sit one per lane and reach the lanes of a tile by cross-lane permutes.
 #pragma once
 
 #include "fe_cell_kernel.h"
@@ -30,300 +35,352 @@ namespace fe {
 struct FusedArgs {
   const unsigned char *afrag, *afrag_lo;
   const void *wtab;
-  const FormHeader *hdr;
-  const CellGeo *geo;
+  const void *geo;        // FormGeo<T>[n_cells]
   const FusedTask *tasks;
-  const int32_t *ntasks;
+  int ntasks;
   const FusedLane *lanes;
-  const uint16_t *rank;   // [n_cells][n_phi][n_phi]: rank of dof(K, i) in row dof(K, j) at [K][j][i]
-  const int64_t *row_ptr;
+  const uint16_t *rank;   // [n_cells][n_phi][rstride]: rank of dof(K, i) in row dof(K, j) at [K][j][i]
   void *values;
-  int n_phi, nd, n_q_pad, nks;
+  int n_phi, n_q_pad, nks, rstride;
 };
 
-template <class P, int MT, int NDT, bool STAGE_A, bool STAGE_W>
-__global__ __launch_bounds__(FUSED_WAVES * 64) void fused_kernel(FusedArgs a) {
+// Geometry pass: FP64 geometry of every cell (Section 4.2) and the factors of
+// H of one form, with the arithmetic of the cell kernel.
+template <class P>
+__global__ __launch_bounds__(256) void k_form_geo(const double *coords, int64_t n_cells, int d,
+                                                   int nd, const FormHeader *hdr,
+                                                   FormGeo<typename P::real> *geo,
+                                                   int32_t *status) {
+  typedef typename P::real T;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cells) return;
+  double G[3][3], adet;
+  const bool ok = cell_geometry(d, coords + c * (d + 1) * d, G, adet);
+  T Gp[3][3], inv;
+  cell_factors<P>(hdr, nd, true, ok, G, adet, 1.0, Gp, inv);
+  FormGeo<T> r;
+  r.g[0] = Gp[0][0];
+  r.g[1] = Gp[0][1];
+  r.g[2] = Gp[0][2];
+  r.g[3] = Gp[1][1];
+  r.g[4] = Gp[1][2];
+  r.g[5] = Gp[2][2];
+  r.inv = inv;
+  r.pad = 0;
+  geo[c] = r;
+  if (!ok) atomicOr(status, STATUS_DEGENERATE);
+}
+
+__device__ __forceinline__ int lane_word1(const FusedLane &l) {
+  return (int)l.rowoff | ((int)l.j << 16) | ((int)l.round << 24);
+}
+
+template <class T>
+__device__ __forceinline__ T shfl_t(T v, int src) {
+  if constexpr (sizeof(T) == 8) {
+    const int2 w = *reinterpret_cast<const int2 *>(&v);
+    int2 r;
+    r.x = __shfl(w.x, src);
+    r.y = __shfl(w.y, src);
+    return *reinterpret_cast<const T *>(&r);
+  } else {
+    return __shfl(v, src);
+  }
+}
+
+template <class P, int MT, int NDT, bool STAGE_A, int NW>
+__global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
   typedef typename P::real T;
   typedef typename P::acc ACC;
   typedef typename P::frag FRAG;
-  constexpr int TT = FUSED_TT;
+  typedef FormGeo<T> GEO;
+  constexpr int KPL = P::KPL;
+  // output rows 4 kb + r (r < 4) of the single-precision-output instructions
+  // are consecutive, so a lane's four ranks are one 8-byte load; the FP64
+  // instruction holds rows kb + 4 r
+  constexpr bool CONSEC = sizeof(T) == 4;
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int n = lane & 15, kb = lane >> 4;
   const int nphi = a.n_phi, n_q_pad = a.n_q_pad, nks = a.nks;
+  const int nqc = n_q_pad / P::KSTEP;
 
-  // staged weighted-table rows are padded by 16 bytes: the 16 lanes of a
-  // K-slot read 16 different rows j at the same offset, which would all fall
-  // into the same LDS banks with an unpadded power-of-two row stride
+  // Staged weighted table, one row per j holding (chunk qc, slab t, K-slot
+  // entries) in the order the K loop reads them, so that a lane's reads are
+  // one base plus constant offsets.  Rows are padded by 16 bytes: the 16
+  // lanes of a K-slot read 16 different rows j at the same offset, which
+  // would fall into the same LDS banks with a power-of-two row stride.
   constexpr int WPAD = 16 / sizeof(T);
-  const int wrow = n_q_pad + WPAD;
+  const int jstride = NDT * n_q_pad + WPAD;
   const size_t frag_bytes = STAGE_A ? (size_t)MT * nks * 64 * sizeof(FRAG) : 0;
-  const size_t wtab_bytes = STAGE_W ? (size_t)NDT * nphi * wrow * sizeof(T) : 0;
+  const size_t wtab_bytes = (size_t)nphi * jstride * sizeof(T);
   unsigned char *s_af = smem;
   unsigned char *s_afl = smem + frag_bytes;
   T *s_wt = (T *)(smem + frag_bytes * (P::SPLIT ? 2 : 1));
-  T *rowbuf = (T *)(smem + frag_bytes * (P::SPLIT ? 2 : 1) + wtab_bytes) + (size_t)wave * FUSED_SPAN;
+  T *rowbuf = (T *)(smem + frag_bytes * (P::SPLIT ? 2 : 1) + wtab_bytes) +
+              (size_t)wave * (FUSED_SPAN + 64);
 
   if constexpr (STAGE_A) {
     const size_t n16 = frag_bytes / 16;
-    for (size_t t = tid; t < n16; t += FUSED_WAVES * 64) ((uint4 *)s_af)[t] = ((const uint4 *)a.afrag)[t];
+    for (size_t t = tid; t < n16; t += NW * 64) ((uint4 *)s_af)[t] = ((const uint4 *)a.afrag)[t];
     if constexpr (P::SPLIT)
-      for (size_t t = tid; t < n16; t += FUSED_WAVES * 64)
-        ((uint4 *)s_afl)[t] = ((const uint4 *)a.afrag_lo)[t];
+      for (size_t t = tid; t < n16; t += NW * 64) ((uint4 *)s_afl)[t] = ((const uint4 *)a.afrag_lo)[t];
   }
-  if constexpr (STAGE_W) {
-    const int per_row = n_q_pad * (int)sizeof(T) / 16;   // 16-byte chunks per row
+  {
+    // global table [t][j][n_q_pad], copied by 16-byte pieces (one piece never
+    // straddles two K-steps: a K-step is 16, 32 or 128 bytes)
+    constexpr int E = 16 / sizeof(T);
+    const int per_row = n_q_pad / E;
     const int nrows = NDT * nphi;
-    for (int t = tid; t < nrows * per_row; t += FUSED_WAVES * 64) {
-      const int row = t / per_row, col = t - row * per_row;
-      ((uint4 *)(s_wt + (size_t)row * wrow))[col] = ((const uint4 *)a.wtab)[(size_t)row * per_row + col];
+    for (int u = tid; u < nrows * per_row; u += NW * 64) {
+      const int row = u / per_row, q = (u - row * per_row) * E;
+      const int t = row / nphi, j = row - t * nphi;
+      const int qc = q / P::KSTEP, qq = q - qc * P::KSTEP;
+      *(uint4 *)(s_wt + (size_t)j * jstride + (qc * NDT + t) * P::KSTEP + qq) =
+          ((const uint4 *)a.wtab)[u];
     }
   }
-  if constexpr (STAGE_A || STAGE_W) __syncthreads();
-  const int ebs = ilogb(a.hdr->b_scale);
+  __syncthreads();
 
-  const int ntasks = *a.ntasks;
-  for (int task = blockIdx.x * FUSED_WAVES + wave; task < ntasks; task += gridDim.x * FUSED_WAVES) {
-    const FusedTask tk = a.tasks[task];
+  const GEO *geo = (const GEO *)a.geo;
+  const int ntasks = a.ntasks;
+  const int stride = gridDim.x * NW;
+  int task = blockIdx.x * NW + wave;
+
+  // lane record (two words) and factors of slot `lane` of the wave's task
+  FusedTask tk{};
+  int lw0 = -1, lw1 = 0;
+  GEO gg{};
+  if (task < ntasks) {
+    tk = a.tasks[task];
+    if (lane < tk.nt * 16) {
+      const FusedLane l = a.lanes[(size_t)tk.t0 * 16 + lane];
+      lw0 = l.cell;
+      lw1 = lane_word1(l);
+    }
+    if (lw0 >= 0) gg = geo[lw0];
+  }
+
+  while (task < ntasks) {
+    const int nt = tk.nt, span = tk.span;
     const int64_t base = tk.base;
-    const int span = tk.span;
+    const int cw0 = lw0, cw1 = lw1;
+    const GEO cg = gg;
+    const int next = task + stride;
+    const bool has_next = next < ntasks;
+    if (has_next) tk = a.tasks[next];
+
     for (int t = lane; t < span; t += 64) rowbuf[t] = 0;
 
-    for (int t0 = 0; t0 < tk.nt; t0 += TT) {
-      int cell[TT], jv[TT], roff[TT], rnd[TT];
-      T Gp[TT][3][3];
-      T inv[TT];
-#pragma unroll
-      for (int tt = 0; tt < TT; ++tt) {
-        cell[tt] = -1;
-        jv[tt] = 0;
-        roff[tt] = 0;
-        rnd[tt] = 0;
-        if (t0 + tt < tk.nt) {
-          const FusedLane L = a.lanes[(size_t)(tk.t0 + t0 + tt) * 16 + n];
-          cell[tt] = L.cell;
-          jv[tt] = L.j;
-          roff[tt] = L.rowoff;
-          rnd[tt] = L.round;
-        }
-        double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        double sK = 1.0, adet = 0.0;
-        int esK = 0;
-        bool ok = true;
-        if (cell[tt] >= 0) {
-          const CellGeo cg = a.geo[cell[tt]];
-          G[0][0] = cg.g[0]; G[0][1] = G[1][0] = cg.g[1]; G[0][2] = G[2][0] = cg.g[2];
-          G[1][1] = cg.g[3]; G[1][2] = G[2][1] = cg.g[4]; G[2][2] = cg.g[5];
-          adet = cg.adet;
-          ok = cg.ok != 0.0;
-          double gabs = adet;
-          if (a.nd > 1) {
-            gabs = 0.0;
-            for (int s = 0; s < 3; ++s) gabs = fmax(gabs, fabs(G[s][0]) + fabs(G[s][1]) + fabs(G[s][2]));
-          }
-          if constexpr (P::SCALED) {
-            const double bound = a.hdr->max_wb * gabs;
-            if (bound > 0.0 && isfinite(bound)) {
-              esK = 14 - ilogb(bound);
-              sK = ldexp(1.0, esK);
-            }
-          }
-        }
-        for (int s = 0; s < 3; ++s)
-          for (int t = 0; t < 3; ++t) {
-            double v = (a.nd == 1) ? (s == 0 && t == 0 ? adet : 0.0) : G[s][t];
-            if (cell[tt] < 0) v = 0.0;
-            else if (!ok) v = NAN;
-            Gp[tt][s][t] = (T)(v * sK);
-          }
-        // sK and the B scale are exact powers of two: invert by exponents
-        inv[tt] = (T)ldexp(1.0, -esK - ebs);
+    for (int tl = 0; tl < nt; ++tl) {
+      // this lane's column: slot 16 tl + n of the task
+      const int src = 16 * tl + n;
+      const int cell = __shfl(cw0, src);
+      const int w1 = __shfl(cw1, src);
+      const int roff = w1 & 0xffff, jv = (w1 >> 16) & 0xff, rnd = (w1 >> 24) & 0xf;
+      T Gs[3][3];
+      {
+        const T g0 = shfl_t(cg.g[0], src), g1 = shfl_t(cg.g[1], src), g2 = shfl_t(cg.g[2], src);
+        const T g3 = shfl_t(cg.g[3], src), g4 = shfl_t(cg.g[4], src), g5 = shfl_t(cg.g[5], src);
+        Gs[0][0] = g0; Gs[0][1] = g1; Gs[0][2] = g2;
+        Gs[1][0] = g1; Gs[1][1] = g3; Gs[1][2] = g4;
+        Gs[2][0] = g2; Gs[2][1] = g4; Gs[2][2] = g5;
       }
+      const T inv = shfl_t(cg.inv, src);
 
       // positions of this tile's outputs inside their rows, loaded before the
-      // contraction so that their latency hides behind it
-      int rv[TT][MT][4];
-#pragma unroll
-      for (int tt = 0; tt < TT; ++tt) {
-        const uint16_t *rk = a.rank + ((size_t)(cell[tt] < 0 ? 0 : cell[tt]) * nphi + jv[tt]) * nphi;
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int i = mt * 16 + P::row(kb, q);
-            rv[tt][mt][q] = (cell[tt] >= 0 && i < nphi) ? (int)rk[i] : -1;
-          }
-      }
-
-      ACC acc[MT][TT];
-      ACC acc2[P::SPLIT ? MT : 1][P::SPLIT ? TT : 1];
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int tt = 0; tt < TT; ++tt) {
-          acc[mt][tt] = ACC{0, 0, 0, 0};
-          if constexpr (P::SPLIT) acc2[mt][tt] = ACC{0, 0, 0, 0};
-        }
-      for (int ks = 0; ks < nks; ++ks) {
-        const int k0 = ks * P::KSTEP;
-        const int s = k0 / n_q_pad;
-        const int qb = k0 - s * n_q_pad + kb * P::KPL;
-        FRAG afr[MT];
-        FRAG afl[P::SPLIT ? MT : 1];
+      // contraction so that their latency hides behind it; padding entries
+      // (i >= n_phi) hold 0xffff
+      int rv[MT][4];
+      {
+        const uint16_t *rk = a.rank + ((size_t)(cell < 0 ? 0 : cell) * nphi + jv) * a.rstride;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-          const size_t fi = ((size_t)mt * nks + ks) * 64 + lane;
-          if constexpr (STAGE_A) {
-            afr[mt] = lds_frag<P>(s_af, fi);
-            if constexpr (P::SPLIT) afl[mt] = lds_frag<P>(s_afl, fi);
+          if constexpr (CONSEC) {
+            const uint2 u = *(const uint2 *)(rk + mt * 16 + 4 * kb);
+            rv[mt][0] = (int)(u.x & 0xffff);
+            rv[mt][1] = (int)(u.x >> 16);
+            rv[mt][2] = (int)(u.y & 0xffff);
+            rv[mt][3] = (int)(u.y >> 16);
           } else {
-            afr[mt] = P::load(a.afrag, fi);
-            if constexpr (P::SPLIT) afl[mt] = P::load(a.afrag_lo, fi);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) rv[mt][q] = (int)rk[mt * 16 + P::row(kb, q)];
           }
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (cell < 0 || rv[mt][q] == 0xffff) rv[mt][q] = -1;
         }
+      }
+      // next task's lane records, behind the first tile's contraction
+      if (tl == 0 && has_next) {
+        lw0 = -1;
+        lw1 = 0;
+        if (lane < tk.nt * 16) {
+          const FusedLane l = a.lanes[(size_t)tk.t0 * 16 + lane];
+          lw0 = l.cell;
+          lw1 = lane_word1(l);
+        }
+      }
+
+      ACC acc[MT];
+      ACC acc2[P::SPLIT ? MT : 1];
 #pragma unroll
-        for (int tt = 0; tt < TT; ++tt) {
-          T h[P::KPL];
+      for (int mt = 0; mt < MT; ++mt) {
+        acc[mt] = ACC{0, 0, 0, 0};
+        if constexpr (P::SPLIT) acc2[mt] = ACC{0, 0, 0, 0};
+      }
+      // K = (s, q) walked q-chunk outer, s inner, as in the cell kernel
+      const T *wcol = s_wt + (size_t)jv * jstride + kb * KPL;
+      for (int qc = 0; qc < nqc; ++qc) {
+        T wv[NDT][KPL];
 #pragma unroll
-          for (int e = 0; e < P::KPL; ++e) h[e] = 0;
+        for (int t = 0; t < NDT; ++t) load_w<T, KPL>(wcol + (qc * NDT + t) * P::KSTEP, wv[t]);
 #pragma unroll
-          for (int t = 0; t < NDT; ++t) {
-            const T g = (s == 0) ? Gp[tt][0][t] : ((s == 1) ? Gp[tt][1][t] : Gp[tt][2][t]);
-            const T *w;
-            if constexpr (STAGE_W) w = s_wt + ((size_t)t * nphi + jv[tt]) * wrow + qb;
-            else w = (const T *)a.wtab + ((size_t)t * nphi + jv[tt]) * n_q_pad + qb;
-            T wv[P::KPL];
-            if constexpr (P::KPL == 8) {
-              const float4 w0 = ((const float4 *)w)[0], w1 = ((const float4 *)w)[1];
-              wv[0] = w0.x; wv[1] = w0.y; wv[2] = w0.z; wv[3] = w0.w;
-              wv[4] = w1.x; wv[5] = w1.y; wv[6] = w1.z; wv[7] = w1.w;
-            } else {
-              wv[0] = w[0];
-            }
-#pragma unroll
-            for (int e = 0; e < P::KPL; ++e) h[e] += g * wv[e];
-          }
+        for (int s = 0; s < NDT; ++s) {
+          T h[KPL];
+          form_h<T, NDT, KPL>(Gs[s], wv, h);
           if constexpr (P::SPLIT) {
             FRAG hh, hl;
             P::pack2(h, hh, hl);
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
-              acc[mt][tt] = P::mma(afr[mt], hh, acc[mt][tt]);
-              acc2[mt][tt] = P::mma(afr[mt], hl, acc2[mt][tt]);
-              acc2[mt][tt] = P::mma(afl[mt], hh, acc2[mt][tt]);
+              const size_t fi = frag_slot(mt, s, qc, MT, NDT) * 64 + lane;
+              FRAG af, al;
+              if constexpr (STAGE_A) {
+                af = lds_frag<P>(s_af, fi);
+                al = lds_frag<P>(s_afl, fi);
+              } else {
+                af = P::load(a.afrag, fi);
+                al = P::load(a.afrag_lo, fi);
+              }
+              acc[mt] = P::mma(af, hh, acc[mt]);
+              acc2[mt] = P::mma(af, hl, acc2[mt]);
+              acc2[mt] = P::mma(al, hh, acc2[mt]);
             }
           } else {
             const FRAG hf = P::pack(h);
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) acc[mt][tt] = P::mma(afr[mt], hf, acc[mt][tt]);
+            for (int mt = 0; mt < MT; ++mt) {
+              const size_t fi = frag_slot(mt, s, qc, MT, NDT) * 64 + lane;
+              FRAG af;
+              if constexpr (STAGE_A) af = lds_frag<P>(s_af, fi);
+              else af = P::load(a.afrag, fi);
+              acc[mt] = P::mma(af, hf, acc[mt]);
+            }
           }
         }
       }
 
-      // scatter into the owned rows, one round per repeated row
+      // next task's factors: its lane records have arrived by now
+      if (tl == 0 && has_next) {
+        gg = GEO{};
+        if (lw0 >= 0) gg = geo[lw0];
+      }
+
+      // scatter into the owned rows, one round per repeated row; within a
+      // round every lane adds to a different entry.  Padding rows and idle
+      // lanes update a private slot of the lane instead (no branch per entry).
+      int addr[MT][4];
+      T val[MT][4];
 #pragma unroll
-      for (int tt = 0; tt < TT; ++tt) {
-        if (t0 + tt >= tk.nt) break;
-        int maxr = rnd[tt];
-        for (int off = 1; off < 64; off <<= 1) maxr = max(maxr, __shfl_xor(maxr, off));
-        for (int r = 0; r <= maxr; ++r) {
-          if (cell[tt] >= 0 && rnd[tt] == r) {
+      for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
+        for (int q = 0; q < 4; ++q) {
+          T v = acc[mt][q];
+          if constexpr (P::SPLIT) v += acc2[mt][q] * (T)(1.0 / 2048.0);
+          const bool ok = rv[mt][q] >= 0;
+          addr[mt][q] = ok ? roff + rv[mt][q] : FUSED_SPAN + lane;
+          val[mt][q] = ok ? v * inv : (T)0;
+        }
+      // the tile's last round, the same in every lane record of the tile
+      const int maxr = __builtin_amdgcn_readfirstlane((int)((unsigned)w1 >> 28));
+      for (int r = 0; r <= maxr; ++r) {
+        if (rnd == r) {
+          // read all, then write all: a lane's entries are distinct and the
+          // lanes of one round hold distinct rows
+          T old[MT][4];
 #pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                if (rv[tt][mt][q] >= 0) {
-                  T v = acc[mt][tt][q];
-                  if constexpr (P::SPLIT) v += acc2[mt][tt][q] * (T)(1.0 / 2048.0);
-                  rowbuf[roff[tt] + rv[tt][mt][q]] += v * inv[tt];
-                }
-              }
-          }
+          for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) old[mt][q] = rowbuf[addr[mt][q]];
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) rowbuf[addr[mt][q]] = old[mt][q] + val[mt][q];
         }
       }
     }
     T *V = (T *)a.values + base;
     for (int t = lane; t < span; t += 64) V[t] = rowbuf[t];
+    task = next;
   }
 }
 
-template <class P, int MT, int NDT, bool SA, bool SW>
-static fe_status launch_fused_one(const FusedArgs &k, int64_t ntasks_max, size_t smem,
-                                  hipStream_t s) {
-  auto kern = fused_kernel<P, MT, NDT, SA, SW>;
+template <class P, int MT, int NDT, bool SA, int NW>
+static fe_status launch_fused_one(const FusedArgs &k, size_t smem, hipStream_t s) {
+  auto kern = fused_kernel<P, MT, NDT, SA, NW>;
   if (smem > 65536 && hipFuncSetAttribute((const void *)kern,
                                           hipFuncAttributeMaxDynamicSharedMemorySize,
                                           (int)smem) != hipSuccess)
     return FE_EHIP;
-  int dev = 0, ncu = 256;
+  int dev = 0, ncu = 256, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, NW * 64, smem) !=
+          hipSuccess)
     return FE_EHIP;
-  const int64_t need = (ntasks_max + FUSED_WAVES - 1) / FUSED_WAVES;
-  const int per_cu = smem <= 76 * 1024 ? 2 : 1;
+  if (per_cu < 1) return FE_EUNSUPPORTED;
+  const int64_t need = ((int64_t)k.ntasks + NW - 1) / NW;
   const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)ncu * per_cu));
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(FUSED_WAVES * 64), smem, s, k);
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(NW * 64), smem, s, k);
   return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
 }
 
-// LDS staging of the fused kernel: the weighted table is read per lane with
-// 16 different rows per K-slot, so the fused path is used only when it fits
-// in LDS next to the row buffers (else the caller takes the row-gather path).
-inline bool fused_staging(const FormLayout *L, bool *sa, bool *sw) {
-  const size_t real = (L->prec == FE_FP64) ? 8 : 4;
-  const size_t frag = (L->elt_bytes == 2) ? 16 : L->elt_bytes;
-  const size_t rows_bytes = (size_t)FUSED_WAVES * FUSED_SPAN * real;
-  const size_t frag_bytes =
-      (size_t)L->mt * L->nks * 64 * frag * (L->prec == FE_SPLITFP16_ACC32 ? 2 : 1);
-  const size_t wtab_bytes = (size_t)L->ndt * L->n_phi * (L->n_q_pad + 16 / real) * real;
-  const size_t budget = 156 * 1024;
-  // the table is required in LDS; the B^T fragments join it when room remains
-  *sw = wtab_bytes + rows_bytes <= budget;
-  *sa = *sw && frag_bytes + wtab_bytes + rows_bytes <= budget;
-  return true;
+template <class P, int MT, int NDT>
+static fe_status launch_fused_nw(const FusedArgs &k, const FormLayout &L, hipStream_t s) {
+  // the most waves per workgroup that fit, B^T fragments staged when they fit
+  if (fused_lds(L, 12, true) <= FUSED_LDS_BUDGET)
+    return launch_fused_one<P, MT, NDT, true, 12>(k, fused_lds(L, 12, true), s);
+  if (fused_lds(L, 8, true) <= FUSED_LDS_BUDGET)
+    return launch_fused_one<P, MT, NDT, true, 8>(k, fused_lds(L, 8, true), s);
+  if (fused_lds(L, 8, false) <= FUSED_LDS_BUDGET)
+    return launch_fused_one<P, MT, NDT, false, 8>(k, fused_lds(L, 8, false), s);
+  if (fused_lds(L, 4, false) <= FUSED_LDS_BUDGET)
+    return launch_fused_one<P, MT, NDT, false, 4>(k, fused_lds(L, 4, false), s);
+  return FE_EUNSUPPORTED;
 }
 
 template <class P>
 fe_status launch_fused_impl(const FusedLaunch &a) {
+  typedef typename P::real T;
   const FormLayout &L = *a.L;
-  typedef typename P::frag FRAG;
+  hipStream_t s = (hipStream_t)a.stream;
+  if (!fused_eligible(L)) return FE_EUNSUPPORTED;
+  if (a.n_cells > 0) {
+    hipLaunchKernelGGL(k_form_geo<P>, dim3((unsigned)((a.n_cells + 255) / 256)), dim3(256), 0, s,
+                       a.coords, a.n_cells, L.d, L.nd, (const FormHeader *)a.form_buf,
+                       (FormGeo<T> *)a.geo, a.status);
+    if (hipGetLastError() != hipSuccess) return FE_EHIP;
+  }
+  if (a.ntasks <= 0) return FE_OK;
   FusedArgs k;
   k.afrag = a.form_buf + L.off_afrag;
   k.afrag_lo = a.form_buf + L.off_afrag_lo;
   k.wtab = a.form_buf + L.off_wtab;
-  k.hdr = (const FormHeader *)a.form_buf;
   k.geo = a.geo;
   k.tasks = a.tasks;
-  k.ntasks = a.ntasks;
+  k.ntasks = (int)a.ntasks;
   k.lanes = a.lanes;
   k.rank = a.rank;
-  k.row_ptr = a.row_ptr;
   k.values = a.values;
   k.n_phi = L.n_phi;
-  k.nd = L.nd;
   k.n_q_pad = L.n_q_pad;
   k.nks = L.nks;
-  const size_t rows_bytes = (size_t)FUSED_WAVES * FUSED_SPAN * sizeof(typename P::real);
-  const size_t frag_bytes = (size_t)L.mt * L.nks * 64 * sizeof(FRAG) * (P::SPLIT ? 2 : 1);
-  const size_t wtab_bytes =
-      (size_t)L.ndt * L.n_phi * (L.n_q_pad + 16 / sizeof(typename P::real)) * sizeof(typename P::real);
-  bool sa, sw;
-  if (!fused_staging(a.L, &sa, &sw) || !sw) return FE_EUNSUPPORTED;
-  const size_t smem = rows_bytes + (sa ? frag_bytes : 0) + (sw ? wtab_bytes : 0);
-  hipStream_t s = (hipStream_t)a.stream;
-  const int ndt = L.ndt;
-#define FE_FL(M)                                                                          \
-  if (L.mt == M) {                                                                        \
-    if (ndt == 1) {                                                                       \
-      if (sa && sw) return launch_fused_one<P, M, 1, true, true>(k, a.ntasks_max, smem, s);             \
-      if (sa) return launch_fused_one<P, M, 1, true, false>(k, a.ntasks_max, smem, s);                  \
-      if (sw) return launch_fused_one<P, M, 1, false, true>(k, a.ntasks_max, smem, s);                  \
-      return launch_fused_one<P, M, 1, false, false>(k, a.ntasks_max, smem, s);                         \
-    }                                                                                     \
-    if (sa && sw) return launch_fused_one<P, M, 3, true, true>(k, a.ntasks_max, smem, s);               \
-    if (sa) return launch_fused_one<P, M, 3, true, false>(k, a.ntasks_max, smem, s);                    \
-    if (sw) return launch_fused_one<P, M, 3, false, true>(k, a.ntasks_max, smem, s);                    \
-    return launch_fused_one<P, M, 3, false, false>(k, a.ntasks_max, smem, s);                           \
+  k.rstride = a.rstride;
+#define FE_FL(M)                                               \
+  if (L.mt == M) {                                             \
+    if (L.ndt == 1) return launch_fused_nw<P, M, 1>(k, L, s);  \
+    return launch_fused_nw<P, M, 3>(k, L, s);                  \
   }
   FE_FL(1) FE_FL(2) FE_FL(3) FE_FL(4) FE_FL(6) FE_FL(8) FE_FL(11)
 #undef FE_FL

@@ -54,6 +54,13 @@ constexpr int32_t FORM_MAGIC = 0x46453335;  // "FE35"
 constexpr size_t HEADER_BYTES = 256;
 
 fe_status compute_layout(const fe_form_desc *f, FormLayout *L);
+
+// Slot of the B^T fragment (16 rows x one K-step) of row tile mt, derivative
+// slab s and quadrature chunk qc: chunk-major, so that the fragments of one
+// chunk are contiguous.
+constexpr size_t frag_slot(int mt, int s, int qc, int n_mt, int ndt) {
+  return ((size_t)qc * ndt + s) * n_mt + mt;
+}
 fe_status check_form(const fe_form_desc *f);
 
 // ---- cell kernel launchers, one per precision (fe_cell_<prec>.hip) ----
@@ -78,9 +85,7 @@ fe_status launch_cell(const CellLaunch &a);
 
 // ---- fused (row-ownership) numeric path, see fe_fused.h ----
 constexpr int FUSED_SPAN = 1024;    // CSR entries per task (LDS row buffer of one wave)
-constexpr int FUSED_WAVES = 8;      // waves per workgroup
-constexpr int FUSED_TT = 2;         // tiles formed together (share the B^T fragments)
-constexpr int FUSED_TILE_MAX = 12;  // tiles per task
+constexpr int FUSED_TILE_MAX = 4;   // tiles per task: one lane record per lane of a wave
 
 struct FusedTask {
   int32_t r0, r1;  // rows [r0, r1)
@@ -94,30 +99,49 @@ struct FusedLane {
   int32_t cell;     // < 0: idle lane
   uint16_t rowoff;  // offset of the row inside the task's CSR span
   uint8_t j;        // local index of the row's dof in the cell
-  uint8_t round;    // earlier lanes of the tile holding the same row
+  uint8_t round;    // low 4 bits: earlier lanes of the tile holding the same
+                    // row; high 4 bits: the largest such count in the tile
 };
 
-// Per-cell FP64 geometry from the geometry pass: symmetric G
-// (G00 G01 G02 G11 G12 G22), |det J| and a validity flag.
-struct CellGeo {
-  double g[6];
-  double adet;
-  double ok;
+// Per-cell, per-form factors of H from the geometry pass: the symmetric
+// scaled geometry tensor sigma_K G (G00 G01 G02 G11 G12 G22; mass: sigma_K
+// |det J| in g[0]) in the arithmetic type of H, and the exact inverse of the
+// two power-of-two scales.  NaN factors mark a degenerate cell.
+template <class T>
+struct FormGeo {
+  T g[6];
+  T inv;
+  T pad;
 };
 
 struct FusedLaunch {
   const FormLayout *L;
   const unsigned char *form_buf;
-  const CellGeo *geo;
+  int32_t *status;        // device status word (inside form_buf)
+  const double *coords;   // device [n_cells][d+1][d]
+  int64_t n_cells;
+  void *geo;              // workspace: n_cells FormGeo records
   const FusedTask *tasks;
-  const int32_t *ntasks;  // device: number of tasks
-  int64_t ntasks_max;     // host bound used to size the grid
+  int64_t ntasks;         // tasks of the schedule (from the FILL phase)
   const FusedLane *lanes;
-  const uint16_t *rank;
-  const int64_t *row_ptr;
+  const uint16_t *rank;   // [n_cells][n_phi][rstride]
+  int rstride;
   void *values;
   void *stream;
 };
+// LDS of the fused kernel with nw waves per workgroup: the weighted table
+// (always staged: it is read per lane with 16 different rows per K-slot),
+// the B^T fragments if staged, and one row buffer per wave.
+inline size_t fused_lds(const FormLayout &L, int nw, bool with_frags) {
+  const size_t real = (L.prec == FE_FP64) ? 8 : 4;
+  const size_t frag = (L.elt_bytes == 2) ? 16 : L.elt_bytes;
+  const size_t rows = (size_t)nw * (FUSED_SPAN + 64) * real;  // + a private slot per lane
+  const size_t frags =
+      with_frags ? (size_t)L.mt * L.nks * 64 * frag * (L.prec == FE_SPLITFP16_ACC32 ? 2 : 1) : 0;
+  const size_t wtab = (size_t)L.n_phi * (L.ndt * L.n_q_pad + 16 / real) * real;
+  return rows + frags + wtab;
+}
+constexpr size_t FUSED_LDS_BUDGET = 156 * 1024;
 bool fused_eligible(const FormLayout &L);
 fe_status launch_fused_fp64(const FusedLaunch &a);
 fe_status launch_fused_fp32(const FusedLaunch &a);

@@ -127,10 +127,10 @@ def test_assemble_size_query(lib):
     assert st == 0
     # plan holds at least the 16-bit rank of every local entry
     assert pb >= 82944 * 35 * 35 * 2
-    # workspace: FP32 local matrices of both forms (gather path) + per-cell
-    # FP64 geometry records (64 bytes) of the fused path
+    # workspace: FP32 local matrices of both forms (gather path) + per-form,
+    # per-cell factor records (at most 64 bytes) of the fused path
     local = 2 * 82944 * 35 * 35 * 4
-    assert wb == ((local + 255) // 256) * 256 + 64 * 82944
+    assert wb == ((local + 255) // 256) * 256 + 2 * 64 * 82944
 
 
 def test_assemble_argument_errors(lib):
