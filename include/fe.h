@@ -66,14 +66,16 @@ enum { FE_MASS = 0, FE_STIFFNESS = 1 };
 /* Arithmetic of the contraction A = B^T H (List 1, Section 4.5):
  *   FE_FP64            everything in double (u_s = u_q = u_g = FP64)
  *   FE_FP32            B and H in single, single accumulation
- *   FE_FP16_ACC32      B and H stored in half (u_s = FP16), products and
- *                      accumulation in single on the matrix cores (u_q)
- *   FE_BF16_ACC32      as above with bfloat16 storage
- *   FE_SPLITFP16_ACC32 B and H each stored as a pair hi + 2^-11 lo of halves;
- *                      three products hi*hi + 2^-11 (hi*lo + lo*hi), single
- *                      accumulation.
- * In all modes geometry is FP64 and H is formed in single (double for
- * FE_FP64) from FP64 geometry and rounded once to the storage format. */
+ *   FE_FP16_ACC32      B, the weighted table w_q B and the geometry factors
+ *                      stored in half and H computed in half (u_s = FP16, as
+ *                      in List 1), products and accumulation in single on
+ *                      the matrix cores (u_q)
+ *   FE_BF16_ACC32      B and H stored in bfloat16; H formed in single and
+ *                      rounded once
+ *   FE_SPLITFP16_ACC32 B and H each stored as a pair hi + 2^-11 lo of halves
+ *                      (H formed in single first); three products
+ *                      hi*hi + 2^-11 (hi*lo + lo*hi), single accumulation.
+ * In all modes geometry is FP64 (u_g). */
 enum {
   FE_FP64 = 0,
   FE_FP32 = 1,

@@ -53,6 +53,10 @@ typedef double f64x4_t __attribute__((ext_vector_type(4)));
 struct PolF16 {
   static constexpr int KSTEP = 32, KPL = 8, REGMUL = 1;
   static constexpr bool SPLIT = false, SCALED = true;
+  // H is computed in the storage precision (List 1: u_s stores B and C and
+  // computes H): packed half FMAs on a half weighted table
+  static constexpr bool H16 = true;
+  typedef _Float16 hreal;
   typedef float real;
   typedef float zreal;  // coefficient evaluation: u_p = u^2 for FP16 storage
   typedef f32x4_t acc;
@@ -75,6 +79,8 @@ struct PolF16 {
 struct PolBF16 {
   static constexpr int KSTEP = 32, KPL = 8, REGMUL = 1;
   static constexpr bool SPLIT = false, SCALED = true;
+  static constexpr bool H16 = false;  // H formed in single, rounded once
+  typedef float hreal;
   typedef float real;
   typedef float zreal;
   typedef f32x4_t acc;
@@ -99,6 +105,8 @@ struct PolBF16 {
 struct PolSplit {
   static constexpr int KSTEP = 32, KPL = 8, REGMUL = 2;
   static constexpr bool SPLIT = true, SCALED = true;
+  static constexpr bool H16 = false;  // H formed in single, then split
+  typedef float hreal;
   typedef float real;
   typedef double zreal;  // the pair carries ~22 bits: u^2 calls for double
   typedef f32x4_t acc;
@@ -123,6 +131,8 @@ struct PolSplit {
 struct PolF32 {
   static constexpr int KSTEP = 4, KPL = 1, REGMUL = 1;
   static constexpr bool SPLIT = false, SCALED = true;
+  static constexpr bool H16 = false;
+  typedef float hreal;
   typedef float real;
   typedef double zreal;
   typedef f32x4_t acc;
@@ -140,6 +150,8 @@ struct PolF32 {
 struct PolF64 {
   static constexpr int KSTEP = 4, KPL = 1, REGMUL = 2;
   static constexpr bool SPLIT = false, SCALED = false;
+  static constexpr bool H16 = false;
+  typedef double hreal;
   typedef double real;
   typedef double zreal;
   typedef f64x4_t acc;
@@ -159,7 +171,7 @@ struct PolF64 {
 struct KArgs {
   const unsigned char *afrag;     // B^T fragments (hi for split)
   const unsigned char *afrag_lo;  // split mode
-  const void *wtab;               // [NDT][n_phi][n_q_pad], float or double
+  const void *wtab;               // [NDT][n_phi][n_q_pad], P::hreal
   const void *vtab;               // [n_q][n_phi], zreal
   const FormHeader *hdr;
   int32_t *status;
@@ -221,8 +233,9 @@ __device__ __forceinline__ bool cell_geometry(int d, const double *x, double G[3
 template <class P>
 __device__ __forceinline__ void cell_factors(const FormHeader *hdr, int nd, bool valid, bool ok,
                                              const double G[3][3], double adet, double zmax,
-                                             typename P::real Gp[3][3], typename P::real &inv) {
+                                             typename P::hreal Gp[3][3], typename P::real &inv) {
   typedef typename P::real T;
+  typedef typename P::hreal HT;
   double gabs = adet;
   if (nd > 1) {
     gabs = 0.0;
@@ -230,7 +243,15 @@ __device__ __forceinline__ void cell_factors(const FormHeader *hdr, int nd, bool
   }
   double sK = 1.0;
   int esK = 0;
-  if constexpr (P::SCALED) {
+  if constexpr (P::H16) {
+    // half arithmetic: the partial sums over t and their product with z stay
+    // below 2^15 (the table carries its own scale)
+    const double bound = hdr->max_wb * hdr->w_scale * gabs * fmax(zmax, 1.0);
+    if (bound > 0.0 && isfinite(bound)) {
+      esK = 14 - ilogb(bound);
+      sK = ldexp(1.0, esK);
+    }
+  } else if constexpr (P::SCALED) {
     const double bound = hdr->max_wb * gabs * zmax;
     if (bound > 0.0 && isfinite(bound)) {
       esK = 14 - ilogb(bound);
@@ -242,10 +263,23 @@ __device__ __forceinline__ void cell_factors(const FormHeader *hdr, int nd, bool
       double v = (nd == 1) ? (s == 0 && t == 0 ? adet : 0.0) : G[s][t];
       if (!valid) v = 0.0;
       else if (!ok) v = NAN;
-      Gp[s][t] = (T)(v * sK);
+      Gp[s][t] = (HT)(v * sK);
     }
-  // both scales are exact powers of two: invert by exponents
-  inv = (T)ldexp(1.0, -esK - ilogb(hdr->b_scale));
+  // all scales are exact powers of two: invert by exponents
+  if constexpr (P::H16)
+    inv = (T)ldexp(1.0, -esK - ilogb(hdr->b_scale) - ilogb(hdr->w_scale));
+  else
+    inv = (T)ldexp(1.0, -esK - ilogb(hdr->b_scale));
+}
+
+// H for one lane in half arithmetic: h = Gs[0] w[0] + Gs[1] w[1] + Gs[2] w[2],
+// each step one packed half operation (a product, then fused multiply-adds)
+template <int NDT>
+__device__ __forceinline__ half8_t form_h16(const _Float16 *Gs, const half8_t (&w)[NDT]) {
+  half8_t h = w[0] * Gs[0];
+#pragma unroll
+  for (int t = 1; t < NDT; ++t) h = __builtin_elementwise_fma(w[t], (half8_t)Gs[t], h);
+  return h;
 }
 
 // H for one lane: h[e] = sum_t Gs[t] w[t][e] (times z[e] with a coefficient),
@@ -287,6 +321,7 @@ __device__ __forceinline__ typename P::frag lds_frag(const unsigned char *base, 
 template <class P, int MT, int JC, int NDT, bool COEFF, int STAGE, int NW>
 __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
   typedef typename P::real T;
+  typedef typename P::hreal HT;  // weighted table and H formation
   typedef typename P::zreal Z;
   typedef typename P::acc ACC;
   typedef typename P::frag FRAG;
@@ -297,10 +332,10 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
 
   constexpr int NT = NW * 64;
   const size_t frag_bytes = STAGE >= 1 ? (size_t)MT * nks * 64 * sizeof(FRAG) : 0;
-  const size_t wtab_bytes = STAGE == 2 ? (size_t)NDT * nphi * n_q_pad * sizeof(T) : 0;
+  const size_t wtab_bytes = STAGE == 2 ? (size_t)NDT * nphi * n_q_pad * sizeof(HT) : 0;
   unsigned char *s_af = smem;
   unsigned char *s_afl = smem + frag_bytes;
-  T *s_wt = (T *)(smem + frag_bytes * (P::SPLIT ? 2 : 1));
+  HT *s_wt = (HT *)(smem + frag_bytes * (P::SPLIT ? 2 : 1));
   unsigned char *zbase = smem + frag_bytes * (P::SPLIT ? 2 : 1) + wtab_bytes;
   Z *zq = (Z *)zbase;                                                   // [n_q_pad][16]
   double *zloc = (double *)(zbase + (size_t)16 * n_q_pad * sizeof(Z));  // [16][n_phi]
@@ -370,10 +405,11 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
     }
 
     if (valid && !ok && wave == 0 && kb == 0) atomicOr(a.status, STATUS_DEGENERATE);
-    T Gp[3][3], inv;
+    HT Gp[3][3];
+    T inv;
     cell_factors<P>(a.hdr, a.nd, valid, ok, G, adet, zmax, Gp, inv);
 
-    const T *wt = (const T *)a.wtab;
+    const HT *wt = (const HT *)a.wtab;
     const int npass = (nphi + NW * JC - 1) / (NW * JC);
     for (int pass = 0; pass < npass; ++pass) {
       const int jb = pass * NW * JC + wave * JC;
@@ -417,33 +453,49 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
 #pragma unroll
         for (int jj = 0; jj < JC; ++jj) {
           const int jl = min(jb + jj, nphi - 1);
-          T wv[NDT][P::KPL];
+          const HT *wj = (STAGE == 2 ? s_wt : wt) + (size_t)jl * n_q_pad + qb;
+          if constexpr (P::H16) {
+            half8_t wv[NDT];
 #pragma unroll
-          for (int t = 0; t < NDT; ++t) {
-            if constexpr (STAGE == 2) load_w<T, P::KPL>(s_wt + ((size_t)t * nphi + jl) * n_q_pad + qb, wv[t]);
-            else load_w<T, P::KPL>(wt + ((size_t)t * nphi + jl) * n_q_pad + qb, wv[t]);
-          }
+            for (int t = 0; t < NDT; ++t) wv[t] = *(const half8_t *)(wj + (size_t)t * nphi * n_q_pad);
 #pragma unroll
-          for (int s = 0; s < NDT; ++s) {
-            T h[P::KPL];
-            form_h<T, NDT, P::KPL>(Gp[s], wv, h);
-            if constexpr (COEFF) {
+            for (int s = 0; s < NDT; ++s) {
+              half8_t hf = form_h16<NDT>(Gp[s], wv);
+              if constexpr (COEFF) {
+                half8_t z8;
 #pragma unroll
-              for (int e = 0; e < P::KPL; ++e) h[e] *= zf[e];
-            }
-            if constexpr (P::SPLIT) {
-              FRAG hh, hl;
-              P::pack2(h, hh, hl);
-#pragma unroll
-              for (int mt = 0; mt < MT; ++mt) {
-                acc[mt][jj] = P::mma(afr[s][mt], hh, acc[mt][jj]);
-                acc2[mt][jj] = P::mma(afr[s][mt], hl, acc2[mt][jj]);
-                acc2[mt][jj] = P::mma(afl[s][mt], hh, acc2[mt][jj]);
+                for (int e = 0; e < 8; ++e) z8[e] = (_Float16)zf[e];
+                hf = hf * z8;
               }
-            } else {
-              const FRAG hf = P::pack(h);
 #pragma unroll
               for (int mt = 0; mt < MT; ++mt) acc[mt][jj] = P::mma(afr[s][mt], hf, acc[mt][jj]);
+            }
+          } else {
+            T wv[NDT][P::KPL];
+#pragma unroll
+            for (int t = 0; t < NDT; ++t) load_w<T, P::KPL>(wj + (size_t)t * nphi * n_q_pad, wv[t]);
+#pragma unroll
+            for (int s = 0; s < NDT; ++s) {
+              T h[P::KPL];
+              form_h<T, NDT, P::KPL>(Gp[s], wv, h);
+              if constexpr (COEFF) {
+#pragma unroll
+                for (int e = 0; e < P::KPL; ++e) h[e] *= zf[e];
+              }
+              if constexpr (P::SPLIT) {
+                FRAG hh, hl;
+                P::pack2(h, hh, hl);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                  acc[mt][jj] = P::mma(afr[s][mt], hh, acc[mt][jj]);
+                  acc2[mt][jj] = P::mma(afr[s][mt], hl, acc2[mt][jj]);
+                  acc2[mt][jj] = P::mma(afl[s][mt], hh, acc2[mt][jj]);
+                }
+              } else {
+                const FRAG hf = P::pack(h);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt][jj] = P::mma(afr[s][mt], hf, acc[mt][jj]);
+              }
             }
           }
         }
@@ -533,7 +585,7 @@ fe_status launch_cell_impl(const CellLaunch &a) {
   typedef typename P::frag FRAG;
   typedef typename P::real T;
   const size_t frag_bytes = (size_t)mt * L.nks * 64 * sizeof(FRAG) * (P::SPLIT ? 2 : 1);
-  const size_t wtab_bytes = (size_t)L.ndt * L.n_phi * L.n_q_pad * sizeof(T);
+  const size_t wtab_bytes = (size_t)L.ndt * L.n_phi * L.n_q_pad * sizeof(typename P::hreal);
   hipStream_t s = (hipStream_t)a.stream;
   const int ndt = L.ndt;
   // 8-wave workgroups with fragments and weighted table in LDS when both fit

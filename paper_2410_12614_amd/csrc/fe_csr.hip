@@ -41,7 +41,8 @@ struct PlanHeader {
 constexpr int32_t PLAN_MAGIC = 0x46455043;  // "FEPC"
 
 struct PlanLayout {
-  size_t off_adj_ptr, off_cursor, off_adj, off_rank, off_scan, off_tasks, off_lanes, total;
+  size_t off_adj_ptr, off_cursor, off_adj, off_rank, off_srank, off_scan, off_tasks, off_lanes,
+      total;
   size_t scan_blocks;
   int64_t tasks_max, tiles_max;
   int rstride;
@@ -66,6 +67,8 @@ PlanLayout plan_layout(int64_t n_cells, int n_phi, int64_t n_dofs) {
   off = a256(off + sizeof(int64_t) * (size_t)n_cells * n_phi);
   P.rstride = rank_stride(n_phi);
   P.off_rank = off;
+  off = a256(off + sizeof(uint16_t) * (size_t)n_cells * n_phi * P.rstride);
+  P.off_srank = off;  // the same ranks in fused-schedule order (LDS offsets)
   off = a256(off + sizeof(uint16_t) * (size_t)n_cells * n_phi * P.rstride);
   P.scan_blocks = (size_t)(n_dofs + 1 + SCAN_TILE - 1) / SCAN_TILE;
   P.off_scan = off;
@@ -92,21 +95,19 @@ PlanLayout plan_layout(int64_t n_cells, int n_phi, int64_t n_dofs) {
 // FUSED_TILE_MAX tiles of 16 (cell, local index) pairs.  Among the feasible
 // ends of a task holding at least FUSED_SPAN / 2 entries, the one whose pairs
 // fill their tiles best is taken (then the longest), since idle lanes of a
-// partial tile cost as much as busy ones.  Each task's pairs are dealt into
-// tiles by sweeping its rows, one pair per row per sweep, in adjacency order,
-// so repeated rows inside a tile are rare and their lanes carry increasing
-// round numbers.  Returns false when a row is too long or has too many pairs,
-// or the bounds of the layout would be exceeded.
+// partial tile cost as much as busy ones.  The task's pairs are then dealt
+// into tiles (below); lanes of one tile holding the same row carry
+// increasing round numbers in adjacency order.  Returns false when a row is
+// too long or has too many pairs, or the bounds of the layout would be
+// exceeded.
 bool build_fused_schedule(const std::vector<int64_t> &rp, const std::vector<int64_t> &ap,
                           const std::vector<int64_t> &adj, int64_t n_rows,
                           const PlanLayout &P, std::vector<FusedTask> &tasks,
                           std::vector<FusedLane> &lanes) {
   tasks.clear();
   lanes.clear();
-  std::vector<int64_t> cursor;
-  std::vector<int> in_tile;
   constexpr int64_t PAIRS_MAX = 16 * FUSED_TILE_MAX;
-  int64_t r = 0;
+  int64_t r = 0, p0 = 0;
   while (r < n_rows) {
     const int64_t r0 = r;
     int64_t span = 0, npairs = 0;
@@ -138,51 +139,98 @@ bool build_fused_schedule(const std::vector<int64_t> &rp, const std::vector<int6
       npairs = best_pairs;
     }
     const int64_t nr = r - r0;
-    cursor.assign(nr, 0);
-    in_tile.assign(nr, 0);
     FusedTask tk;
     tk.r0 = (int32_t)r0;
-    tk.r1 = (int32_t)r;
     tk.t0 = (int32_t)(lanes.size() / 16);
     tk.base = rp[r0];
     tk.span = (int32_t)(rp[r] - rp[r0]);
-    tk.pad = 0;
-    int64_t left = npairs;
-    int nt = 0;
-    while (left > 0) {
-      std::fill(in_tile.begin(), in_tile.end(), 0);
-      int filled = 0;
-      while (filled < 16 && left > 0) {
-        for (int64_t q = 0; q < nr && filled < 16; ++q) {
-          const int64_t g = r0 + q;
-          if (cursor[q] < ap[g + 1] - ap[g]) {
-            const int64_t ent = adj[ap[g] + cursor[q]];
-            FusedLane L;
-            L.cell = (int32_t)(ent >> 8);
-            L.j = (uint8_t)(ent & 255);
-            L.rowoff = (uint16_t)(rp[g] - rp[r0]);
-            L.round = (uint8_t)in_tile[q]++;
-            lanes.push_back(L);
-            ++cursor[q];
-            ++filled;
-            --left;
+    tk.p0 = (int32_t)p0;
+    p0 += npairs;
+    // Deal the pairs into nt tiles: the k-th of the d pairs of a row goes to
+    // tile floor(k nt / d) or the next one with room, rows of many pairs
+    // first, so every row is spread evenly and a tile holds few lanes of one
+    // row (each repeat costs a scatter round).  Tiles stay in order along
+    // every row, so each row's pairs keep their adjacency (cell ascending)
+    // order; when that cannot be kept, the rows are swept instead, one pair
+    // per row per sweep, filling tile after tile.
+    const int nt = (int)((npairs + 15) / 16);
+    std::vector<std::vector<int64_t>> tiles(nt);  // adjacency positions
+    bool even = true;
+    {
+      std::vector<int64_t> order(nr);
+      for (int64_t q = 0; q < nr; ++q) order[q] = q;
+      std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+        return ap[r0 + x + 1] - ap[r0 + x] > ap[r0 + y + 1] - ap[r0 + y];
+      });
+      for (int64_t oi = 0; oi < nr && even; ++oi) {
+        const int64_t g = r0 + order[oi], d = ap[g + 1] - ap[g];
+        int last = 0;
+        for (int64_t k = 0; k < d; ++k) {
+          int t = std::max<int>(last, (int)(k * nt / d));
+          while (t < nt && tiles[t].size() >= 16) ++t;
+          if (t == nt) {
+            even = false;
+            break;
           }
+          tiles[t].push_back(ap[g] + k);
+          last = t;
         }
       }
-      for (; filled < 16; ++filled) {
+    }
+    if (!even) {
+      for (auto &v : tiles) v.clear();
+      std::vector<int64_t> cursor(nr, 0);
+      int64_t left = npairs;
+      for (int t = 0; t < nt; ++t)
+        while (tiles[t].size() < 16 && left > 0)
+          for (int64_t q = 0; q < nr && tiles[t].size() < 16; ++q) {
+            const int64_t g = r0 + q;
+            if (cursor[q] < ap[g + 1] - ap[g]) {
+              tiles[t].push_back(ap[g] + cursor[q]++);
+              --left;
+            }
+          }
+    }
+    int32_t pre = 0;  // real lanes before each tile, one byte per tile
+    for (int t = 0, acc = 0; t < nt; ++t) {
+      pre |= acc << (8 * t);
+      acc += (int)tiles[t].size();
+    }
+    tk.pre = pre;
+    for (int t = 0; t < nt; ++t) {
+      // a tile's lanes in row order, then adjacency order within a row
+      std::vector<int64_t> &v = tiles[t];
+      std::sort(v.begin(), v.end());
+      uint8_t maxr = 0;
+      const size_t first = lanes.size();
+      int64_t prev_row = -1;
+      uint8_t rnd = 0;
+      for (int64_t pos : v) {
+        // row of adjacency position pos: the rows are ascending in pos
+        const int64_t g = std::upper_bound(ap.begin() + r0, ap.begin() + r + 1, pos) - ap.begin() - 1;
+        rnd = (g == prev_row) ? (uint8_t)(rnd + 1) : (uint8_t)0;
+        prev_row = g;
+        const int64_t ent = adj[pos];
+        FusedLane L;
+        L.cell = (int32_t)(ent >> 8);
+        L.j = (uint8_t)(ent & 255);
+        L.rowoff = (uint16_t)(rp[g] - rp[r0]);
+        L.round = rnd;
+        maxr = std::max(maxr, rnd);
+        lanes.push_back(L);
+      }
+      // idle lanes take round 15, which no busy lane of a tile that has idle
+      // lanes reaches (at most 15 busy lanes: rounds 0..14)
+      for (size_t u = v.size(); u < 16; ++u) {
         FusedLane L;
         L.cell = -1;
         L.j = 0;
         L.rowoff = 0;
-        L.round = 0;
+        L.round = 15;
         lanes.push_back(L);
       }
-      // a tile has 16 lanes, so rounds fit 4 bits; every lane also carries
-      // the tile's last round
-      uint8_t maxr = 0;
-      for (size_t u = lanes.size() - 16; u < lanes.size(); ++u) maxr = std::max(maxr, lanes[u].round);
-      for (size_t u = lanes.size() - 16; u < lanes.size(); ++u) lanes[u].round |= (uint8_t)(maxr << 4);
-      ++nt;
+      // every lane also carries the tile's last round
+      for (size_t u = first; u < lanes.size(); ++u) lanes[u].round |= (uint8_t)(maxr << 4);
     }
     tk.nt = nt;
     tasks.push_back(tk);
@@ -390,6 +438,34 @@ __global__ __launch_bounds__(256) void k_ranks(const int32_t *dofmap, int64_t n_
       else hi = mid;
     }
     rank[e * rstride + j] = (uint16_t)lo;
+  }
+}
+
+// Ranks in fused-schedule order: for the pair of schedule index p (tile
+// column n of task tile t: p = p0 + pre[t] + n) and lane-order entry e (row tile mt = e/16,
+// K-slot kb = e%16/4, output r = e%4 of the instruction, i.e. local row
+// i = 16 mt + row(kb, r)), the LDS byte offset of the entry inside the
+// owning wave's row buffer: rowoff + rank of dof(K, i) in row dof(K, j), or,
+// for padding rows i >= n_phi, the private slot FUSED_SPAN + 16 kb + n of
+// that lane.  One workgroup per task.
+__global__ __launch_bounds__(64) void k_slot_ranks(const FusedTask *tasks, const FusedLane *lanes,
+                                                   const uint16_t *rank, int n_phi, int rstride,
+                                                   bool f64rows, int elt, uint16_t *srank) {
+  const FusedTask tk = tasks[blockIdx.x];
+  const int nent = tk.nt * 16 * rstride;
+  for (int u = threadIdx.x; u < nent; u += 64) {
+    const int slot = u / rstride, e = u - slot * rstride;
+    const FusedLane L = lanes[(size_t)tk.t0 * 16 + slot];
+    if (L.cell < 0) continue;  // the pairs of a tile fill its first lanes
+    const int n = slot & 15, mt = e >> 4, kb = (e & 15) >> 2, r = e & 3;
+    const int pair = tk.p0 + ((tk.pre >> (8 * (slot >> 4))) & 0xff) + n;
+    const int i = mt * 16 + (f64rows ? kb + 4 * r : 4 * kb + r);
+    int off;
+    if (i < n_phi)
+      off = L.rowoff + rank[((size_t)L.cell * n_phi + L.j) * rstride + i];
+    else
+      off = FUSED_SPAN + 16 * kb + n;
+    srank[(size_t)pair * rstride + e] = (uint16_t)(off * elt);
   }
 }
 
@@ -634,6 +710,12 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
           return FE_EHIP;
         h.ntasks = (int32_t)tasks.size();
         h.ntiles = (int32_t)(lanes.size() / 16);
+        hipLaunchKernelGGL(k_slot_ranks, dim3((unsigned)tasks.size()), dim3(64), 0, s,
+                           (const FusedTask *)(pb + P.off_tasks),
+                           (const FusedLane *)(pb + P.off_lanes), (const uint16_t *)rank, n_phi,
+                           P.rstride, forms[0].precision == FE_FP64, (int)elt,
+                           (uint16_t *)(pb + P.off_srank));
+        if (hipGetLastError() != hipSuccess || !sync_ok(s)) return FE_EHIP;
       }
     }
     if (hipMemcpy(hdr_d, &h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess) return FE_EHIP;
@@ -662,7 +744,7 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
       a.tasks = (const FusedTask *)(pb + P.off_tasks);
       a.ntasks = mats[0].schedule;
       a.lanes = (const FusedLane *)(pb + P.off_lanes);
-      a.rank = rank;
+      a.srank = (const uint16_t *)(pb + P.off_srank);
       a.rstride = P.rstride;
       a.values = mats[f].values;
       a.stream = stream;

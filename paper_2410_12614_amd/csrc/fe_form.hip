@@ -57,7 +57,7 @@ fe_status compute_layout(const fe_form_desc *f, FormLayout *L) {
   tile_choice(L->n_phi, 1, &L->mt, &jc);
   if (jc == 0) return FE_EUNSUPPORTED;
   L->elt_bytes = mfma16 ? 2 : (f->precision == FE_FP64 ? 8 : 4);
-  L->tab_bytes = (f->precision == FE_FP64) ? 8 : 4;
+  L->tab_bytes = (f->precision == FE_FP64) ? 8 : (f->precision == FE_FP16_ACC32 ? 2 : 4);
   L->vtab_bytes = (f->precision == FE_FP16_ACC32 || f->precision == FE_BF16_ACC32) ? 4 : 8;
   size_t off = HEADER_BYTES;
   const size_t afrag = (size_t)L->mt * L->nks * 64 * L->kpl * L->elt_bytes;
@@ -158,16 +158,24 @@ extern "C" fe_status fe_form_prepare(const fe_form_desc *f, void *form_buf, size
             size_t idx = (frag_slot(mt, s, qc, L.mt, L.ndt) * 64 + lane) * L.kpl + e;
             store_elt(L.prec, h.data(), L.off_afrag, L.off_afrag_lo, idx, v);
           }
-  // weighted table w_q B_t(q, j), [t][j][n_q_pad]
+  // weighted table w_q B_t(q, j), [t][j][n_q_pad]; in FP16 storage (the
+  // storage precision that also forms H) scaled by an exact power of two so
+  // that its largest entry lies in [2^14, 2^15)
   double max_wb = 0.0;
+  for (int t = 0; t < L.nd; ++t)
+    for (int j = 0; j < nphi; ++j)
+      for (int q = 0; q < nq; ++q) max_wb = std::max(max_wb, std::fabs(w[q] * Bop(t, q, j)));
+  double w_scale = 1.0;
+  if (L.tab_bytes == 2 && max_wb > 0.0) w_scale = std::ldexp(1.0, 14 - std::ilogb(max_wb));
+  hdr.w_scale = w_scale;
   for (int t = 0; t < L.ndt; ++t)
     for (int j = 0; j < nphi; ++j)
       for (int q = 0; q < L.n_q_pad; ++q) {
         double v = 0.0;
         if (q < nq && t < L.nd) v = w[q] * Bop(t, q, j);
-        max_wb = std::max(max_wb, std::fabs(v));
         size_t idx = ((size_t)t * nphi + j) * L.n_q_pad + q;
         if (L.tab_bytes == 8) put<double>(h.data(), L.off_wtab, idx, v);
+        else if (L.tab_bytes == 2) put<_Float16>(h.data(), L.off_wtab, idx, (_Float16)(v * w_scale));
         else put<float>(h.data(), L.off_wtab, idx, (float)v);
       }
   double leb = 0.0;

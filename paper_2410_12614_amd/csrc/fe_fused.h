@@ -39,7 +39,7 @@ struct FusedArgs {
   const FusedTask *tasks;
   int ntasks;
   const FusedLane *lanes;
-  const uint16_t *rank;   // [n_cells][n_phi][rstride]: rank of dof(K, i) in row dof(K, j) at [K][j][i]
+  const uint16_t *srank;  // [pairs][rstride], schedule order: LDS byte offsets of a lane's outputs
   void *values;
   int n_phi, n_q_pad, nks, rstride;
 };
@@ -56,7 +56,8 @@ __global__ __launch_bounds__(256) void k_form_geo(const double *coords, int64_t 
   if (c >= n_cells) return;
   double G[3][3], adet;
   const bool ok = cell_geometry(d, coords + c * (d + 1) * d, G, adet);
-  T Gp[3][3], inv;
+  typename P::hreal Gp[3][3];
+  T inv;
   cell_factors<P>(hdr, nd, true, ok, G, adet, 1.0, Gp, inv);
   FormGeo<T> r;
   r.g[0] = Gp[0][0];
@@ -91,14 +92,11 @@ __device__ __forceinline__ T shfl_t(T v, int src) {
 template <class P, int MT, int NDT, bool STAGE_A, int NW>
 __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
   typedef typename P::real T;
+  typedef typename P::hreal HT;  // weighted table and H formation
   typedef typename P::acc ACC;
   typedef typename P::frag FRAG;
   typedef FormGeo<T> GEO;
   constexpr int KPL = P::KPL;
-  // output rows 4 kb + r (r < 4) of the single-precision-output instructions
-  // are consecutive, so a lane's four ranks are one 8-byte load; the FP64
-  // instruction holds rows kb + 4 r
-  constexpr bool CONSEC = sizeof(T) == 4;
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int n = lane & 15, kb = lane >> 4;
@@ -110,13 +108,13 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
   // one base plus constant offsets.  Rows are padded by 16 bytes: the 16
   // lanes of a K-slot read 16 different rows j at the same offset, which
   // would fall into the same LDS banks with a power-of-two row stride.
-  constexpr int WPAD = 16 / sizeof(T);
+  constexpr int WPAD = 16 / sizeof(HT);
   const int jstride = NDT * n_q_pad + WPAD;
   const size_t frag_bytes = STAGE_A ? (size_t)MT * nks * 64 * sizeof(FRAG) : 0;
-  const size_t wtab_bytes = (size_t)nphi * jstride * sizeof(T);
+  const size_t wtab_bytes = (size_t)nphi * jstride * sizeof(HT);
   unsigned char *s_af = smem;
   unsigned char *s_afl = smem + frag_bytes;
-  T *s_wt = (T *)(smem + frag_bytes * (P::SPLIT ? 2 : 1));
+  HT *s_wt = (HT *)(smem + frag_bytes * (P::SPLIT ? 2 : 1));
   T *rowbuf = (T *)(smem + frag_bytes * (P::SPLIT ? 2 : 1) + wtab_bytes) +
               (size_t)wave * (FUSED_SPAN + 64);
 
@@ -129,7 +127,7 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
   {
     // global table [t][j][n_q_pad], copied by 16-byte pieces (one piece never
     // straddles two K-steps: a K-step is 16, 32 or 128 bytes)
-    constexpr int E = 16 / sizeof(T);
+    constexpr int E = 16 / sizeof(HT);
     const int per_row = n_q_pad / E;
     const int nrows = NDT * nphi;
     for (int u = tid; u < nrows * per_row; u += NW * 64) {
@@ -162,7 +160,7 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
   }
 
   while (task < ntasks) {
-    const int nt = tk.nt, span = tk.span;
+    const int nt = tk.nt, span = tk.span, p0 = tk.p0, pre = tk.pre;
     const int64_t base = tk.base;
     const int cw0 = lw0, cw1 = lw1;
     const GEO cg = gg;
@@ -170,45 +168,44 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
     const bool has_next = next < ntasks;
     if (has_next) tk = a.tasks[next];
 
-    for (int t = lane; t < span; t += 64) rowbuf[t] = 0;
+    {
+      constexpr int E4 = 16 / sizeof(T);  // elements per 16-byte store
+      const int n16 = (span + E4 - 1) / E4;
+      for (int t = lane; t < n16; t += 64) ((uint4 *)rowbuf)[t] = uint4{0, 0, 0, 0};
+    }
 
     for (int tl = 0; tl < nt; ++tl) {
       // this lane's column: slot 16 tl + n of the task
       const int src = 16 * tl + n;
       const int cell = __shfl(cw0, src);
       const int w1 = __shfl(cw1, src);
-      const int roff = w1 & 0xffff, jv = (w1 >> 16) & 0xff, rnd = (w1 >> 24) & 0xf;
-      T Gs[3][3];
+      const int jv = (w1 >> 16) & 0xff, rnd = (w1 >> 24) & 0xf;
+      HT Gs[3][3];  // values of the half type when H is formed in half: exact
       {
-        const T g0 = shfl_t(cg.g[0], src), g1 = shfl_t(cg.g[1], src), g2 = shfl_t(cg.g[2], src);
-        const T g3 = shfl_t(cg.g[3], src), g4 = shfl_t(cg.g[4], src), g5 = shfl_t(cg.g[5], src);
+        const HT g0 = (HT)shfl_t(cg.g[0], src), g1 = (HT)shfl_t(cg.g[1], src);
+        const HT g2 = (HT)shfl_t(cg.g[2], src), g3 = (HT)shfl_t(cg.g[3], src);
+        const HT g4 = (HT)shfl_t(cg.g[4], src), g5 = (HT)shfl_t(cg.g[5], src);
         Gs[0][0] = g0; Gs[0][1] = g1; Gs[0][2] = g2;
         Gs[1][0] = g1; Gs[1][1] = g3; Gs[1][2] = g4;
         Gs[2][0] = g2; Gs[2][1] = g4; Gs[2][2] = g5;
       }
       const T inv = shfl_t(cg.inv, src);
 
-      // positions of this tile's outputs inside their rows, loaded before the
-      // contraction so that their latency hides behind it; padding entries
-      // (i >= n_phi) hold 0xffff
-      int rv[MT][4];
+      // LDS byte offsets of this lane's outputs inside the row buffer, in
+      // lane order (four per row tile: one 8-byte load), loaded before the
+      // contraction so that their latency hides behind it.  Padding rows
+      // point at the lane's private slot; idle lanes never scatter.
+      int addr[MT][4];
       {
-        const uint16_t *rk = a.rank + ((size_t)(cell < 0 ? 0 : cell) * nphi + jv) * a.rstride;
+        const int pair = cell < 0 ? 0 : p0 + ((pre >> (8 * tl)) & 0xff) + n;
+        const uint16_t *rk = a.srank + (size_t)pair * a.rstride + 4 * kb;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-          if constexpr (CONSEC) {
-            const uint2 u = *(const uint2 *)(rk + mt * 16 + 4 * kb);
-            rv[mt][0] = (int)(u.x & 0xffff);
-            rv[mt][1] = (int)(u.x >> 16);
-            rv[mt][2] = (int)(u.y & 0xffff);
-            rv[mt][3] = (int)(u.y >> 16);
-          } else {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) rv[mt][q] = (int)rk[mt * 16 + P::row(kb, q)];
-          }
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (cell < 0 || rv[mt][q] == 0xffff) rv[mt][q] = -1;
+          const uint2 u = *(const uint2 *)(rk + mt * 16);
+          addr[mt][0] = (int)(u.x & 0xffff);
+          addr[mt][1] = (int)(u.x >> 16);
+          addr[mt][2] = (int)(u.y & 0xffff);
+          addr[mt][3] = (int)(u.y >> 16);
         }
       }
       // next task's lane records, behind the first tile's contraction
@@ -230,35 +227,15 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
         if constexpr (P::SPLIT) acc2[mt] = ACC{0, 0, 0, 0};
       }
       // K = (s, q) walked q-chunk outer, s inner, as in the cell kernel
-      const T *wcol = s_wt + (size_t)jv * jstride + kb * KPL;
+      const HT *wcol = s_wt + (size_t)jv * jstride + kb * KPL;
       for (int qc = 0; qc < nqc; ++qc) {
-        T wv[NDT][KPL];
+        if constexpr (P::H16) {
+          half8_t wv[NDT];
 #pragma unroll
-        for (int t = 0; t < NDT; ++t) load_w<T, KPL>(wcol + (qc * NDT + t) * P::KSTEP, wv[t]);
+          for (int t = 0; t < NDT; ++t) wv[t] = *(const half8_t *)(wcol + (qc * NDT + t) * P::KSTEP);
 #pragma unroll
-        for (int s = 0; s < NDT; ++s) {
-          T h[KPL];
-          form_h<T, NDT, KPL>(Gs[s], wv, h);
-          if constexpr (P::SPLIT) {
-            FRAG hh, hl;
-            P::pack2(h, hh, hl);
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-              const size_t fi = frag_slot(mt, s, qc, MT, NDT) * 64 + lane;
-              FRAG af, al;
-              if constexpr (STAGE_A) {
-                af = lds_frag<P>(s_af, fi);
-                al = lds_frag<P>(s_afl, fi);
-              } else {
-                af = P::load(a.afrag, fi);
-                al = P::load(a.afrag_lo, fi);
-              }
-              acc[mt] = P::mma(af, hh, acc[mt]);
-              acc2[mt] = P::mma(af, hl, acc2[mt]);
-              acc2[mt] = P::mma(al, hh, acc2[mt]);
-            }
-          } else {
-            const FRAG hf = P::pack(h);
+          for (int s = 0; s < NDT; ++s) {
+            const half8_t hf = form_h16<NDT>(Gs[s], wv);
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
               const size_t fi = frag_slot(mt, s, qc, MT, NDT) * 64 + lane;
@@ -266,6 +243,44 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
               if constexpr (STAGE_A) af = lds_frag<P>(s_af, fi);
               else af = P::load(a.afrag, fi);
               acc[mt] = P::mma(af, hf, acc[mt]);
+            }
+          }
+        } else {
+          T wv[NDT][KPL];
+#pragma unroll
+          for (int t = 0; t < NDT; ++t) load_w<T, KPL>(wcol + (qc * NDT + t) * P::KSTEP, wv[t]);
+#pragma unroll
+          for (int s = 0; s < NDT; ++s) {
+            T h[KPL];
+            form_h<T, NDT, KPL>(Gs[s], wv, h);
+            if constexpr (P::SPLIT) {
+              FRAG hh, hl;
+              P::pack2(h, hh, hl);
+#pragma unroll
+              for (int mt = 0; mt < MT; ++mt) {
+                const size_t fi = frag_slot(mt, s, qc, MT, NDT) * 64 + lane;
+                FRAG af, al;
+                if constexpr (STAGE_A) {
+                  af = lds_frag<P>(s_af, fi);
+                  al = lds_frag<P>(s_afl, fi);
+                } else {
+                  af = P::load(a.afrag, fi);
+                  al = P::load(a.afrag_lo, fi);
+                }
+                acc[mt] = P::mma(af, hh, acc[mt]);
+                acc2[mt] = P::mma(af, hl, acc2[mt]);
+                acc2[mt] = P::mma(al, hh, acc2[mt]);
+              }
+            } else {
+              const FRAG hf = P::pack(h);
+#pragma unroll
+              for (int mt = 0; mt < MT; ++mt) {
+                const size_t fi = frag_slot(mt, s, qc, MT, NDT) * 64 + lane;
+                FRAG af;
+                if constexpr (STAGE_A) af = lds_frag<P>(s_af, fi);
+                else af = P::load(a.afrag, fi);
+                acc[mt] = P::mma(af, hf, acc[mt]);
+              }
             }
           }
         }
@@ -278,9 +293,8 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
       }
 
       // scatter into the owned rows, one round per repeated row; within a
-      // round every lane adds to a different entry.  Padding rows and idle
-      // lanes update a private slot of the lane instead (no branch per entry).
-      int addr[MT][4];
+      // round every lane adds to a different entry (padding rows update the
+      // lane's private slot instead: no branch per entry)
       T val[MT][4];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
@@ -288,10 +302,9 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
         for (int q = 0; q < 4; ++q) {
           T v = acc[mt][q];
           if constexpr (P::SPLIT) v += acc2[mt][q] * (T)(1.0 / 2048.0);
-          const bool ok = rv[mt][q] >= 0;
-          addr[mt][q] = ok ? roff + rv[mt][q] : FUSED_SPAN + lane;
-          val[mt][q] = ok ? v * inv : (T)0;
+          val[mt][q] = v * inv;
         }
+      unsigned char *rb = (unsigned char *)rowbuf;
       // the tile's last round, the same in every lane record of the tile
       const int maxr = __builtin_amdgcn_readfirstlane((int)((unsigned)w1 >> 28));
       for (int r = 0; r <= maxr; ++r) {
@@ -302,11 +315,11 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) old[mt][q] = rowbuf[addr[mt][q]];
+            for (int q = 0; q < 4; ++q) old[mt][q] = *(const T *)(rb + addr[mt][q]);
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) rowbuf[addr[mt][q]] = old[mt][q] + val[mt][q];
+            for (int q = 0; q < 4; ++q) *(T *)(rb + addr[mt][q]) = old[mt][q] + val[mt][q];
         }
       }
     }
@@ -339,6 +352,8 @@ static fe_status launch_fused_one(const FusedArgs &k, size_t smem, hipStream_t s
 template <class P, int MT, int NDT>
 static fe_status launch_fused_nw(const FusedArgs &k, const FormLayout &L, hipStream_t s) {
   // the most waves per workgroup that fit, B^T fragments staged when they fit
+  if (fused_lds(L, 16, true) <= FUSED_LDS_BUDGET)
+    return launch_fused_one<P, MT, NDT, true, 16>(k, fused_lds(L, 16, true), s);
   if (fused_lds(L, 12, true) <= FUSED_LDS_BUDGET)
     return launch_fused_one<P, MT, NDT, true, 12>(k, fused_lds(L, 12, true), s);
   if (fused_lds(L, 8, true) <= FUSED_LDS_BUDGET)
@@ -371,7 +386,7 @@ fe_status launch_fused_impl(const FusedLaunch &a) {
   k.tasks = a.tasks;
   k.ntasks = (int)a.ntasks;
   k.lanes = a.lanes;
-  k.rank = a.rank;
+  k.srank = a.srank;
   k.values = a.values;
   k.n_phi = L.n_phi;
   k.n_q_pad = L.n_q_pad;

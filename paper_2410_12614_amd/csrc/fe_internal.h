@@ -36,7 +36,7 @@ struct FormLayout {
   int d, nd, ndt, n_phi, n_q, prec, form, has_coeff;
   int kstep, kpl, n_q_pad, k_pad, nks, mt;
   int elt_bytes;  // bytes per operand element in afrag
-  int tab_bytes;  // 4 (float tables) or 8 (double tables, FP64 mode)
+  int tab_bytes;  // weighted table: 2 (half, FP16 mode), 4 (float) or 8 (double, FP64 mode)
   int vtab_bytes; // value table for the coefficient: 8 unless FP16/BF16 storage
   size_t off_afrag, off_afrag_lo, off_wtab, off_vtab, total;
 };
@@ -48,6 +48,7 @@ struct FormHeader {
   double max_wb;    // max |w_q B_t(q, j)|
   double lebesgue;  // max_q sum_k |phi_k(X_q)|
   double b_scale;   // exact power of two applied to the B^T operand (FP16/BF16 modes)
+  double w_scale;   // exact power of two applied to the weighted table (FP16 mode)
 };
 
 constexpr int32_t FORM_MAGIC = 0x46453335;  // "FE35"
@@ -88,11 +89,13 @@ constexpr int FUSED_SPAN = 1024;    // CSR entries per task (LDS row buffer of o
 constexpr int FUSED_TILE_MAX = 4;   // tiles per task: one lane record per lane of a wave
 
 struct FusedTask {
-  int32_t r0, r1;  // rows [r0, r1)
+  int32_t r0;      // first row
+  int32_t pre;     // byte t: pairs in the tiles before tile t of the task
   int32_t t0, nt;  // tiles [t0, t0 + nt)
   int64_t base;    // row_ptr[r0]: first CSR entry of the task
   int32_t span;    // row_ptr[r1] - row_ptr[r0]
-  int32_t pad;
+  int32_t p0;      // schedule index of the task's first (cell, j) pair; the
+                   // pairs of a tile fill its first lanes
 };
 
 struct FusedLane {
@@ -100,7 +103,7 @@ struct FusedLane {
   uint16_t rowoff;  // offset of the row inside the task's CSR span
   uint8_t j;        // local index of the row's dof in the cell
   uint8_t round;    // low 4 bits: earlier lanes of the tile holding the same
-                    // row; high 4 bits: the largest such count in the tile
+                    // row (15: idle lane); high 4 bits: the tile's last round
 };
 
 // Per-cell, per-form factors of H from the geometry pass: the symmetric
@@ -124,7 +127,7 @@ struct FusedLaunch {
   const FusedTask *tasks;
   int64_t ntasks;         // tasks of the schedule (from the FILL phase)
   const FusedLane *lanes;
-  const uint16_t *rank;   // [n_cells][n_phi][rstride]
+  const uint16_t *srank;  // [pairs][rstride]: LDS byte offsets, see fe_fused.h
   int rstride;
   void *values;
   void *stream;
@@ -138,7 +141,8 @@ inline size_t fused_lds(const FormLayout &L, int nw, bool with_frags) {
   const size_t rows = (size_t)nw * (FUSED_SPAN + 64) * real;  // + a private slot per lane
   const size_t frags =
       with_frags ? (size_t)L.mt * L.nks * 64 * frag * (L.prec == FE_SPLITFP16_ACC32 ? 2 : 1) : 0;
-  const size_t wtab = (size_t)L.n_phi * (L.ndt * L.n_q_pad + 16 / real) * real;
+  const size_t tab = L.tab_bytes;
+  const size_t wtab = (size_t)L.n_phi * (L.ndt * L.n_q_pad + 16 / tab) * tab;
   return rows + frags + wtab;
 }
 constexpr size_t FUSED_LDS_BUDGET = 156 * 1024;
