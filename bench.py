@@ -9,7 +9,11 @@ matrices share one CSR pattern (912,673 rows, 67,338,433 nnz each).
 
 One step = one FE_NUMERIC call of the library: cell kernels of both forms
 (geometry, H formation, matrix-core contraction) and the deterministic CSR
-assembly of both matrices, inputs resident in HBM.  The mixed FP16/FP32
+assembly of both matrices, inputs resident in HBM.  The step runs a
+geometry pass and one fused pass over the row-ownership schedule that
+computes and writes both matrices; the two halves are also timed on their
+own (FE_NUMERIC_GEOMETRY, FE_NUMERIC_FUSED) for the roofline of the fused
+pass.  The mixed FP16/FP32
 path is the reported value; the plain FP64 path is timed beside it on the
 same mesh, and the relative Frobenius error of the mixed result against the
 FP64 result is reported (the FP64 path itself matches the FP64 CPU oracle
@@ -31,6 +35,14 @@ sys.path.insert(0, ROOT)
 # Peaks used for roofline fractions (MI355X published figures).
 PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "split": 2500.0, "fp32": 157.3, "fp64": 78.6}
+# vector ALU: 256 CUs x 4 SIMDs x 32 packed flops x 2.4 GHz (the published
+# fp32 vector figure; packed half runs at the same lane-pair rate)
+PEAK_VALU_TFLOPS = 157.3
+
+# Measured HBM traffic of the fused pass (rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# scaled by a plain copy) and the sources it was measured with.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_pass_c2_fp16_traffic.txt")
+KERNEL_SOURCES = ["fe_fused.h", "fe_cell_kernel.h", "fe_internal.h", "fe_cell_fp16.hip", "fe_csr.hip"]
 
 WORKLOAD = ("P4 Lagrange mass+stiffness, 24^3 x 6 jittered Kuhn tetrahedra (82,944 cells, "
             "35 dofs/cell), 5% flattened to aspect 1e3, 125-point collapsed Gauss-Jacobi rule")
@@ -46,6 +58,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-sample-cells", type=int, default=0,
                     help="cells of the oracle baseline sample (0 = the whole mesh)")
+    ap.add_argument("--cpu-reps", type=int, default=3, help="oracle passes over the sample")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB elementwise copy (x * 1.0), the reference "
                          "kernel for scaling hardware byte counters")
@@ -69,9 +82,10 @@ def time_steps(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def cpu_baseline(mesh, sample_cells):
+def cpu_baseline(mesh, sample_cells, reps):
     """The FP64 oracle (numeric phase: local matrices of both forms + CSR
-    assembly) on the first ``sample_cells`` cells, OpenMP over host cores."""
+    assembly) on the first ``sample_cells`` cells, ``reps`` passes, OpenMP
+    over the host cores."""
     import oracle
     n = mesh.n_cells if sample_cells <= 0 else min(sample_cells, mesh.n_cells)
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
@@ -79,13 +93,44 @@ def cpu_baseline(mesh, sample_cells):
     cc, dm = mesh.cell_coords[:n], mesh.dofmap[:n]
     rp, ci = oracle.csr_pattern(dm, mesh.n_dofs)          # symbolic: not timed
     t0 = time.perf_counter()
-    for form in ("mass", "stiffness"):
-        A = oracle.local_matrices(form, cc, mesh.degree, 8, nthreads=threads, tab=tab)
-        oracle.assemble(dm, A, mesh.n_dofs, rp, ci)
-    dt = time.perf_counter() - t0
+    for _ in range(reps):
+        for form in ("mass", "stiffness"):
+            A = oracle.local_matrices(form, cc, mesh.degree, 8, nthreads=threads, tab=tab)
+            oracle.assemble(dm, A, mesh.n_dofs, rp, ci)
+            del A
+    dt = (time.perf_counter() - t0) / reps
     return {"value": n / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} of {mesh.n_cells} cells (first n), both forms, local matrices + CSR "
-                      f"assembly (FP64, {threads} OpenMP threads), {dt:.1f} s"}
+                      f"assembly (FP64, {threads} OpenMP threads), {reps} passes of {dt:.1f} s"}
+
+
+def sources_digest():
+    """SHA-256 over the sources of the fused pass (traffic is reported only
+    for the code it was measured on)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2410_12614_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """(fetch + write bytes per launch of the fused pass, digest) from the
+    committed counter summary, or None when absent or measured on other code."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("sources_sha256") != sources_digest():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
@@ -122,15 +167,11 @@ def main():
     if any(s != 0 for s in st):
         raise RuntimeError(f"device status {st}")
 
-    # per-form split of the fused step (each single-form assembly = geometry
-    # pass + that form's fused kernel) and the unfused path for comparison
+    # the two halves of the step, and the unfused path for comparison
     n_phi = mesh.n_phi
     nnz = asm.nnz
-    ms_form = {}
-    for f in forms:
-        a1 = api.Assembly(mv, [api.form_desc(3, 4, 8, f, prec)])
-        ms_form[f] = time_steps(a1.numeric, args.steps, args.warmup)
-        del a1
+    ms_geo = time_steps(lambda: asm.numeric(part="geometry"), args.steps, args.warmup)
+    ms_fused = time_steps(lambda: asm.numeric(part="fused"), args.steps, args.warmup)
     ms_gather_path = time_steps(lambda: asm.numeric(gather=True), max(3, args.steps // 4), 1)
 
     result = {}
@@ -149,30 +190,40 @@ def main():
         result["rel_err_vs_fp64"] = errs
         del asm64, v64
 
-    # roofline of the dominant kernel: the fused kernel of the costlier form.
-    # Algorithmic work per cell (per form): 2 n_phi^2 K matrix-core flops
-    # (K = n_q for mass, 3 n_q for stiffness) and, written once, the form's
-    # CSR values plus the cell's coordinates and dof map.
-    kq = {"mass": 125, "stiffness": 3 * 125}
-    kern = {}
-    for f in forms:
-        flops = 2 * n_phi ** 2 * kq[f] * mesh.n_cells
-        nbytes = (96 + 4 * n_phi) * mesh.n_cells + 4 * nnz
-        t = ms_form[f] / 1e3
-        kern[f"fused_{f}"] = {"ms": ms_form[f], "alg_flops": flops, "alg_bytes": nbytes,
-                              "tflops": flops / t / 1e12, "gbs": nbytes / t / 1e9}
-    kern["unfused_step"] = {"ms": ms_gather_path}
-    dom = max(("fused_mass", "fused_stiffness"), key=lambda k: kern[k]["ms"])
-    kd = kern[dom]
-    t_mfma = kd["alg_flops"] / (PEAK_MFMA_TFLOPS[prec] * 1e12)
-    t_hbm = kd["alg_bytes"] / (PEAK_HBM_GBS * 1e9)
-    if t_hbm >= t_mfma:
-        roof = {"bound": "hbm", "achieved": kd["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": kd["gbs"] / PEAK_HBM_GBS, "traffic": None, "kernel": dom}
+    # Roofline of the dominant kernel: the fused pass (both forms).  Its
+    # algorithmic work per launch: matrix-core flops 2 n_phi^2 K per cell and
+    # form (K = n_q mass, 3 n_q stiffness); H formation d^2 n_q n_phi FMAs per
+    # cell for stiffness, n_q n_phi for mass; bytes: each cell's coordinates
+    # (96) and dof map (4 n_phi) read once, each form's CSR values (4 nnz)
+    # written once.
+    n_q = 125
+    kq = {"mass": n_q, "stiffness": 3 * n_q}
+    flops = sum(2 * n_phi ** 2 * kq[f] * mesh.n_cells for f in forms)
+    valu = sum(2 * (9 if f == "stiffness" else 1) * n_q * n_phi * mesh.n_cells for f in forms)
+    nbytes = (96 + 4 * n_phi) * mesh.n_cells + len(forms) * 4 * nnz
+    t = ms_fused / 1e3
+    kern = {"fused_pass": {"ms": ms_fused, "alg_flops": flops, "alg_valu_flops": valu,
+                           "alg_bytes": nbytes, "tflops": flops / t / 1e12,
+                           "gbs": nbytes / t / 1e9},
+            "geometry_pass": {"ms": ms_geo},
+            "unfused_step": {"ms": ms_gather_path}}
+    ideal = {"hbm": nbytes / (PEAK_HBM_GBS * 1e9),
+             "mfma": flops / (PEAK_MFMA_TFLOPS[prec] * 1e12),
+             "alu": valu / (PEAK_VALU_TFLOPS * 1e12)}
+    bound = max(ideal, key=ideal.get)
+    traffic = measured_traffic() if prec == "fp16" else None
+    if bound == "hbm":
+        roof = {"bound": "hbm", "achieved": nbytes / t / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    elif bound == "mfma":
+        roof = {"bound": "mfma", "achieved": flops / t / 1e12, "peak": PEAK_MFMA_TFLOPS[prec],
+                "unit": "TFLOP/s"}
     else:
-        pk = PEAK_MFMA_TFLOPS[prec]
-        roof = {"bound": "mfma", "achieved": kd["tflops"], "peak": pk, "unit": "TFLOP/s",
-                "frac": kd["tflops"] / pk, "traffic": None, "kernel": dom}
+        roof = {"bound": "alu", "achieved": valu / t / 1e12, "peak": PEAK_VALU_TFLOPS,
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = traffic
+    roof["kernel"] = "fused_pass"
+    roof["ideal_us"] = {k: v * 1e6 for k, v in ideal.items()}
 
     line = {
         "metric": "cells/sec (kernel+CSR assembly) mixed FP16/FP32 vs FP64 at stated rel. error",
@@ -196,7 +247,7 @@ def main():
         **result,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(mesh, args.cpu_sample_cells)
+        line["cpu_baseline"] = cpu_baseline(mesh, args.cpu_sample_cells, args.cpu_reps)
     print(json.dumps(line), flush=True)
 
 

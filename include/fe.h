@@ -88,7 +88,14 @@ enum {
 enum { FE_GEOM_FP64 = 0 };
 
 /* Phases of fe_assemble_csr. */
-enum { FE_SYMBOLIC_COUNT = 0, FE_SYMBOLIC_FILL = 1, FE_NUMERIC = 2, FE_NUMERIC_GATHER = 3 };
+enum {
+  FE_SYMBOLIC_COUNT = 0,
+  FE_SYMBOLIC_FILL = 1,
+  FE_NUMERIC = 2,
+  FE_NUMERIC_GATHER = 3,
+  FE_NUMERIC_GEOMETRY = 4, /* first half of the fused FE_NUMERIC */
+  FE_NUMERIC_FUSED = 5     /* second half of the fused FE_NUMERIC */
+};
 
 typedef struct fe_form_desc {
   int32_t cell;           /* FE_TRIANGLE or FE_TETRAHEDRON                     */
@@ -222,6 +229,12 @@ fe_status fe_cell_kernels(const fe_form_desc *f, const void *form_buf, const fe_
  *       Asynchronous, never synchronises, bitwise repeatable.
  *   FE_NUMERIC_GATHER : as FE_NUMERIC but always through the workspace and
  *       the row gather (for comparison and testing).
+ *   FE_NUMERIC_GEOMETRY, FE_NUMERIC_FUSED : the two halves of the fused
+ *       FE_NUMERIC, for callers that keep the coordinates fixed over several
+ *       assemblies or time the halves: GEOMETRY writes the per-cell factor
+ *       records into the workspace, FUSED runs the fused kernels on the
+ *       records the last GEOMETRY (or FE_NUMERIC) call left in that
+ *       workspace.  FE_EUNSUPPORTED when the fused path does not apply.
  * Errors: FE_EINVAL (NULL pointers, dof entries out of range are reported
  * through the status word of the plan), FE_ESIZE, FE_EUNSUPPORTED, FE_EHIP.
  * ------------------------------------------------------------------------ */

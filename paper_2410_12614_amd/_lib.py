@@ -34,6 +34,8 @@ FE_SYMBOLIC_COUNT = 0
 FE_SYMBOLIC_FILL = 1
 FE_NUMERIC = 2
 FE_NUMERIC_GATHER = 3
+FE_NUMERIC_GEOMETRY = 4
+FE_NUMERIC_FUSED = 5
 
 # every symbol declared in include/fe.h
 EXPORTS = (

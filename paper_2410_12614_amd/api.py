@@ -160,10 +160,13 @@ class Assembly:
         check(fe_assemble_csr(self.descs, self.form_bufs, mesh, L.FE_SYMBOLIC_FILL, self.mats,
                               self.plan, None, stream), "fe_assemble_csr(FILL)")
 
-    def numeric(self, gather: bool = False) -> list:
+    def numeric(self, gather: bool = False, part: Optional[str] = None) -> list:
         """FE_NUMERIC (fused row-ownership path where it applies) or, with
-        ``gather``, FE_NUMERIC_GATHER (cell kernels + row gather)."""
+        ``gather``, FE_NUMERIC_GATHER (cell kernels + row gather); ``part``
+        "geometry" or "fused" runs one half of the fused FE_NUMERIC."""
         phase = L.FE_NUMERIC_GATHER if gather else L.FE_NUMERIC
+        if part is not None:
+            phase = {"geometry": L.FE_NUMERIC_GEOMETRY, "fused": L.FE_NUMERIC_FUSED}[part]
         check(fe_assemble_csr(self.descs, self.form_bufs, self.mesh, phase, self.mats,
                               self.plan, self.workspace, self.stream), "fe_assemble_csr(NUMERIC)")
         return self.values

@@ -41,6 +41,7 @@
 namespace fe {
 
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
@@ -274,11 +275,19 @@ __device__ __forceinline__ void cell_factors(const FormHeader *hdr, int nd, bool
 
 // H for one lane in half arithmetic: h = Gs[0] w[0] + Gs[1] w[1] + Gs[2] w[2],
 // each step one packed half operation (a product, then fused multiply-adds)
+// on pairs of entries; g2[t] holds Gs[t] in both halves.
 template <int NDT>
-__device__ __forceinline__ half8_t form_h16(const _Float16 *Gs, const half8_t (&w)[NDT]) {
-  half8_t h = w[0] * Gs[0];
+__device__ __forceinline__ half8_t form_h16(const half2_t *g2, const half8_t (&w)[NDT]) {
+  half8_t h;
 #pragma unroll
-  for (int t = 1; t < NDT; ++t) h = __builtin_elementwise_fma(w[t], (half8_t)Gs[t], h);
+  for (int p = 0; p < 4; ++p) {
+    half2_t x = half2_t{w[0][2 * p], w[0][2 * p + 1]} * g2[0];
+#pragma unroll
+    for (int t = 1; t < NDT; ++t)
+      x = __builtin_elementwise_fma(half2_t{w[t][2 * p], w[t][2 * p + 1]}, g2[t], x);
+    h[2 * p] = x[0];
+    h[2 * p + 1] = x[1];
+  }
   return h;
 }
 
@@ -460,7 +469,10 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
             for (int t = 0; t < NDT; ++t) wv[t] = *(const half8_t *)(wj + (size_t)t * nphi * n_q_pad);
 #pragma unroll
             for (int s = 0; s < NDT; ++s) {
-              half8_t hf = form_h16<NDT>(Gp[s], wv);
+              half2_t g2[NDT];
+#pragma unroll
+              for (int t = 0; t < NDT; ++t) g2[t] = half2_t{Gp[s][t], Gp[s][t]};
+              half8_t hf = form_h16<NDT>(g2, wv);
               if constexpr (COEFF) {
                 half8_t z8;
 #pragma unroll

@@ -45,18 +45,24 @@ struct PlanLayout {
       total;
   size_t scan_blocks;
   int64_t tasks_max, tiles_max;
-  int rstride;
+  int sstride;  // entries per pair of the schedule-order table
 };
 
-// Rank rows are padded to whole 16-row tiles (padding entries hold 0xffff)
-// so that the fused kernel reads a lane's four ranks with one aligned load.
-int rank_stride(int n_phi) { return (n_phi + 15) / 16 * 16; }
+// Schedule-order rank rows hold a lane's four outputs per row tile in lane
+// order, padded to a multiple of four entries so that every lane reads its
+// four with one aligned 8-byte load.  With the single-precision output
+// layout (rows 4 kb + r) entries past n_phi rounded up to four are padding
+// only and are not stored; the FP64 layout (rows kb + 4 r) keeps whole
+// 16-row tiles.
+int sched_stride(int n_phi, bool f64rows) {
+  return f64rows ? (n_phi + 15) / 16 * 16 : (n_phi + 3) / 4 * 4;
+}
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr int SCAN_TILE = 2048;  // elements per scan block (256 threads x 8)
 
-PlanLayout plan_layout(int64_t n_cells, int n_phi, int64_t n_dofs) {
+PlanLayout plan_layout(int64_t n_cells, int n_phi, int64_t n_dofs, bool f64rows) {
   PlanLayout P;
   size_t off = 256;
   P.off_adj_ptr = off;
@@ -65,11 +71,11 @@ PlanLayout plan_layout(int64_t n_cells, int n_phi, int64_t n_dofs) {
   off = a256(off + sizeof(int64_t) * n_dofs);
   P.off_adj = off;
   off = a256(off + sizeof(int64_t) * (size_t)n_cells * n_phi);
-  P.rstride = rank_stride(n_phi);
-  P.off_rank = off;
-  off = a256(off + sizeof(uint16_t) * (size_t)n_cells * n_phi * P.rstride);
+  P.sstride = sched_stride(n_phi, f64rows);
+  P.off_rank = off;  // [n_cells][n_phi][n_phi]
+  off = a256(off + sizeof(uint16_t) * (size_t)n_cells * n_phi * n_phi);
   P.off_srank = off;  // the same ranks in fused-schedule order (LDS offsets)
-  off = a256(off + sizeof(uint16_t) * (size_t)n_cells * n_phi * P.rstride);
+  off = a256(off + sizeof(uint16_t) * (size_t)n_cells * n_phi * P.sstride);
   P.scan_blocks = (size_t)(n_dofs + 1 + SCAN_TILE - 1) / SCAN_TILE;
   P.off_scan = off;
   off = a256(off + sizeof(int64_t) * (P.scan_blocks + 1));
@@ -240,7 +246,7 @@ bool build_fused_schedule(const std::vector<int64_t> &rp, const std::vector<int6
 }
 
 fe_status launch_fused(const FusedLaunch &a) {
-  switch (a.L->prec) {
+  switch (a.L[0]->prec) {
     case FE_FP64: return launch_fused_fp64(a);
     case FE_FP32: return launch_fused_fp32(a);
     case FE_FP16_ACC32: return launch_fused_fp16(a);
@@ -418,8 +424,8 @@ __global__ __launch_bounds__(256) void k_rows(const int32_t *dofmap, int n_phi,
 
 // One wave per local row (K, i): rank of every dof(K, j) inside CSR row dof(K, i).
 __global__ __launch_bounds__(256) void k_ranks(const int32_t *dofmap, int64_t n_cells, int n_phi,
-                                               int rstride, const int64_t *row_ptr,
-                                               const int32_t *col_idx, uint16_t *rank) {
+                                               const int64_t *row_ptr, const int32_t *col_idx,
+                                               uint16_t *rank) {
   const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (e >= n_cells * n_phi) return;
@@ -428,7 +434,6 @@ __global__ __launch_bounds__(256) void k_ranks(const int32_t *dofmap, int64_t n_
   const int64_t r0 = row_ptr[g];
   const int64_t len = row_ptr[g + 1] - r0;
   const int32_t *row = col_idx + r0;
-  for (int j = n_phi + lane; j < rstride; j += 64) rank[e * rstride + j] = 0xffff;
   for (int j = lane; j < n_phi; j += 64) {
     const int32_t h = dofmap[K * n_phi + j];
     int64_t lo = 0, hi = len;
@@ -437,7 +442,7 @@ __global__ __launch_bounds__(256) void k_ranks(const int32_t *dofmap, int64_t n_
       if (row[mid] < h) lo = mid + 1;
       else hi = mid;
     }
-    rank[e * rstride + j] = (uint16_t)lo;
+    rank[e * n_phi + j] = (uint16_t)lo;
   }
 }
 
@@ -449,12 +454,12 @@ __global__ __launch_bounds__(256) void k_ranks(const int32_t *dofmap, int64_t n_
 // for padding rows i >= n_phi, the private slot FUSED_SPAN + 16 kb + n of
 // that lane.  One workgroup per task.
 __global__ __launch_bounds__(64) void k_slot_ranks(const FusedTask *tasks, const FusedLane *lanes,
-                                                   const uint16_t *rank, int n_phi, int rstride,
+                                                   const uint16_t *rank, int n_phi, int sstride,
                                                    bool f64rows, int elt, uint16_t *srank) {
   const FusedTask tk = tasks[blockIdx.x];
-  const int nent = tk.nt * 16 * rstride;
+  const int nent = tk.nt * 16 * sstride;
   for (int u = threadIdx.x; u < nent; u += 64) {
-    const int slot = u / rstride, e = u - slot * rstride;
+    const int slot = u / sstride, e = u - slot * sstride;
     const FusedLane L = lanes[(size_t)tk.t0 * 16 + slot];
     if (L.cell < 0) continue;  // the pairs of a tile fill its first lanes
     const int n = slot & 15, mt = e >> 4, kb = (e & 15) >> 2, r = e & 3;
@@ -462,10 +467,10 @@ __global__ __launch_bounds__(64) void k_slot_ranks(const FusedTask *tasks, const
     const int i = mt * 16 + (f64rows ? kb + 4 * r : 4 * kb + r);
     int off;
     if (i < n_phi)
-      off = L.rowoff + rank[((size_t)L.cell * n_phi + L.j) * rstride + i];
+      off = L.rowoff + rank[((size_t)L.cell * n_phi + L.j) * n_phi + i];
     else
       off = FUSED_SPAN + 16 * kb + n;
-    srank[(size_t)pair * rstride + e] = (uint16_t)(off * elt);
+    srank[(size_t)pair * sstride + e] = (uint16_t)(off * elt);
   }
 }
 
@@ -480,7 +485,7 @@ constexpr int GATHER_GROUP = 4;
 template <class T, int NF>
 __global__ __launch_bounds__(256) void k_gather(const int64_t *adj_ptr, const int64_t *adj,
                                                 const uint16_t *rank, const int64_t *row_ptr,
-                                                int64_t n_rows, int n_phi, int rstride,
+                                                int64_t n_rows, int n_phi,
                                                 const T *A0, const T *A1, const T *A2,
                                                 const T *A3, T *V0, T *V1, T *V2, T *V3) {
   constexpr int W = GATHER_W;
@@ -511,7 +516,7 @@ __global__ __launch_bounds__(256) void k_gather(const int64_t *adj_ptr, const in
             const int64_t ent = adj[a + u];
             const size_t row = (size_t)(ent >> 8) * n_phi + (ent & 255);
             const size_t base = row * n_phi + j;
-            rk[u] = (int)rank[row * rstride + j] - w0;
+            rk[u] = (int)rank[base] - w0;
 #pragma unroll
             for (int f = 0; f < NF; ++f) v[u][f] = A[f][base];
           }
@@ -532,11 +537,11 @@ __global__ __launch_bounds__(256) void k_gather(const int64_t *adj_ptr, const in
 
 template <class T, int NF>
 fe_status launch_gather(const int64_t *adj_ptr, const int64_t *adj, const uint16_t *rank,
-                        const int64_t *row_ptr, int64_t n_rows, int n_phi, int rstride,
-                        void *const *A, void *const *V, hipStream_t s) {
+                        const int64_t *row_ptr, int64_t n_rows, int n_phi, void *const *A,
+                        void *const *V, hipStream_t s) {
   const int64_t blocks = (n_rows + 3) / 4;
   hipLaunchKernelGGL((k_gather<T, NF>), dim3((unsigned)blocks), dim3(256), 0, s, adj_ptr, adj, rank,
-                     row_ptr, n_rows, n_phi, rstride, (const T *)A[0], (const T *)A[1], (const T *)A[2],
+                     row_ptr, n_rows, n_phi, (const T *)A[0], (const T *)A[1], (const T *)A[2],
                      (const T *)A[3], (T *)V[0], (T *)V[1], (T *)V[2], (T *)V[3]);
   return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
 }
@@ -580,12 +585,14 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
   const int n_phi = L[0].n_phi;
   const int64_t n_cells = m->n_cells, n_dofs = m->n_dofs;
   const size_t elt = (forms[0].precision == FE_FP64) ? 8 : 4;
-  const PlanLayout P = plan_layout(n_cells, n_phi, n_dofs);
+  const PlanLayout P = plan_layout(n_cells, n_phi, n_dofs, forms[0].precision == FE_FP64);
   const size_t geo_offset = a256((size_t)n_forms * n_cells * n_phi * n_phi * elt);
   // per-form factor records of the fused path (FormGeo<double> is the larger)
   const size_t geo_bytes = a256(sizeof(FormGeo<double>) * (size_t)n_cells);
   const size_t ws_need = std::max<size_t>(256, geo_offset + (size_t)n_forms * geo_bytes);
-  if (!plan || ((phase == FE_NUMERIC || phase == FE_NUMERIC_GATHER) && !workspace)) {
+  const bool numeric = phase == FE_NUMERIC || phase == FE_NUMERIC_GATHER ||
+                       phase == FE_NUMERIC_GEOMETRY || phase == FE_NUMERIC_FUSED;
+  if (!plan || (numeric && !workspace)) {
     if (!plan_bytes && !ws_bytes) return FE_EINVAL;
     if (plan_bytes) *plan_bytes = P.total;
     if (ws_bytes) *ws_bytes = ws_need;
@@ -686,8 +693,7 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
     if (n_cells > 0) {
       const int64_t ne = n_cells * n_phi;
       hipLaunchKernelGGL(k_ranks, dim3((unsigned)((ne + 3) / 4)), dim3(256), 0, s, m->dofmap,
-                         n_cells, n_phi, P.rstride, (const int64_t *)row_ptr, mats[0].col_idx,
-                         rank);
+                         n_cells, n_phi, (const int64_t *)row_ptr, mats[0].col_idx, rank);
     }
     if (hipGetLastError() != hipSuccess) return FE_EHIP;
     if (!sync_ok(s)) return FE_EHIP;
@@ -713,7 +719,7 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
         hipLaunchKernelGGL(k_slot_ranks, dim3((unsigned)tasks.size()), dim3(64), 0, s,
                            (const FusedTask *)(pb + P.off_tasks),
                            (const FusedLane *)(pb + P.off_lanes), (const uint16_t *)rank, n_phi,
-                           P.rstride, forms[0].precision == FE_FP64, (int)elt,
+                           P.sstride, forms[0].precision == FE_FP64, (int)elt,
                            (uint16_t *)(pb + P.off_srank));
         if (hipGetLastError() != hipSuccess || !sync_ok(s)) return FE_EHIP;
       }
@@ -723,30 +729,54 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
     return FE_OK;
   }
 
-  if (phase != FE_NUMERIC && phase != FE_NUMERIC_GATHER) return FE_EINVAL;
+  if (!numeric) return FE_EINVAL;
   if (ws_bytes && *ws_bytes < ws_need) return FE_ESIZE;
   if (!mats[0].col_idx) return FE_EINVAL;
   for (int f = 0; f < n_forms; ++f)
     if (!form_bufs || !form_bufs[f] || !mats[f].values) return FE_EINVAL;
   if (n_cells == 0) return FE_OK;  // values of an empty pattern: nothing to write
   // fused row-ownership path when the FILL phase built its schedule
-  bool fused = phase == FE_NUMERIC && mats[0].schedule > 0;
+  bool fused = phase != FE_NUMERIC_GATHER && mats[0].schedule > 0;
   for (int f = 0; f < n_forms; ++f) fused = fused && fused_eligible(L[f]);
+  if (!fused && (phase == FE_NUMERIC_GEOMETRY || phase == FE_NUMERIC_FUSED)) return FE_EUNSUPPORTED;
   if (fused) {
-    for (int f = 0; f < n_forms; ++f) {
+    // passes: two forms share one pass when they fit it together
+    const FormLayout *pairL[2] = {&L[0], n_forms > 1 ? &L[1] : &L[0]};
+    const bool pair = n_forms == 2 && fused_pair_fits(pairL);
+    for (int f = 0; f < n_forms; f += pair ? 2 : 1) {
       FusedLaunch a;
-      a.L = &L[f];
-      a.form_buf = (const unsigned char *)form_bufs[f];
-      a.status = (int32_t *)form_bufs[f];
+      // the first form of each precision runs the geometry pass of all forms
+      // of that precision
+      a.geo_forms = 0;
+      a.run_fused = phase != FE_NUMERIC_GEOMETRY;
+      bool first = phase != FE_NUMERIC_FUSED;
+      for (int e = 0; e < f; ++e) first = first && forms[e].precision != forms[f].precision;
+      if (first)
+        for (int e = f; e < n_forms; ++e)
+          if (forms[e].precision == forms[f].precision) {
+            a.geo_bufs[a.geo_forms] = (const unsigned char *)form_bufs[e];
+            a.geo_nd[a.geo_forms] = L[e].nd;
+            a.geo_out[a.geo_forms] = (unsigned char *)workspace + geo_offset + e * geo_bytes;
+            ++a.geo_forms;
+          }
+      a.nforms = pair ? 2 : 1;
+      // a pair runs the form with more derivative slabs first: the next
+      // task's factors are then held only during the lighter form
+      const bool swap = pair && L[f].ndt < L[f + 1].ndt;
+      for (int e = 0; e < a.nforms; ++e) {
+        const int g = f + (swap ? 1 - e : e);
+        a.L[e] = &L[g];
+        a.form_buf[e] = (const unsigned char *)form_bufs[g];
+        a.geo[e] = (unsigned char *)workspace + geo_offset + g * geo_bytes;
+        a.values[e] = mats[g].values;
+      }
       a.coords = m->cell_coords;
       a.n_cells = n_cells;
-      a.geo = (unsigned char *)workspace + geo_offset + f * geo_bytes;
       a.tasks = (const FusedTask *)(pb + P.off_tasks);
       a.ntasks = mats[0].schedule;
       a.lanes = (const FusedLane *)(pb + P.off_lanes);
       a.srank = (const uint16_t *)(pb + P.off_srank);
-      a.rstride = P.rstride;
-      a.values = mats[f].values;
+      a.rstride = P.sstride;
       a.stream = stream;
       fe_status st = launch_fused(a);
       if (st != FE_OK) return st;
@@ -778,17 +808,17 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
   fe_status st = FE_EINVAL;
   if (elt == 8) {
     switch (n_forms) {
-      case 1: st = launch_gather<double, 1>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, P.rstride, Aloc, V, s); break;
-      case 2: st = launch_gather<double, 2>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, P.rstride, Aloc, V, s); break;
-      case 3: st = launch_gather<double, 3>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, P.rstride, Aloc, V, s); break;
-      case 4: st = launch_gather<double, 4>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, P.rstride, Aloc, V, s); break;
+      case 1: st = launch_gather<double, 1>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
+      case 2: st = launch_gather<double, 2>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
+      case 3: st = launch_gather<double, 3>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
+      case 4: st = launch_gather<double, 4>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
     }
   } else {
     switch (n_forms) {
-      case 1: st = launch_gather<float, 1>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, P.rstride, Aloc, V, s); break;
-      case 2: st = launch_gather<float, 2>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, P.rstride, Aloc, V, s); break;
-      case 3: st = launch_gather<float, 3>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, P.rstride, Aloc, V, s); break;
-      case 4: st = launch_gather<float, 4>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, P.rstride, Aloc, V, s); break;
+      case 1: st = launch_gather<float, 1>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
+      case 2: st = launch_gather<float, 2>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
+      case 3: st = launch_gather<float, 3>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
+      case 4: st = launch_gather<float, 4>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
     }
   }
   return st;

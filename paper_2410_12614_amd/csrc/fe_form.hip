@@ -206,7 +206,8 @@ namespace fe {
 // The fused path needs the weighted table staged in LDS next to the row
 // buffers (see fe_fused.h): 8 waves x FUSED_SPAN values + table (+ fragments).
 bool fused_eligible(const FormLayout &L) {
-  return !L.has_coeff && fused_lds(L, 4, false) <= FUSED_LDS_BUDGET;
+  const FormLayout *one[1] = {&L};
+  return !L.has_coeff && fused_lds(one, 1, 4, false) <= FUSED_LDS_BUDGET;
 }
 
 fe_status launch_cell(const CellLaunch &a) {

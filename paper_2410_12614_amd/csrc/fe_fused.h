@@ -26,50 +26,69 @@
 // records); the task record, lane records and factors of a wave's next task
 // are loaded while the current task computes.  The lane records of a task
 // sit one per lane and reach the lanes of a tile by cross-lane permutes.
+// Two forms of one precision (mass and stiffness) can share one pass: each
+// task then computes and writes the first form's rows, then the second's,
+// and the schedule is read from HBM once.
 #pragma once
 
 #include "fe_cell_kernel.h"
 
 namespace fe {
 
-struct FusedArgs {
+// One form of a fused pass.
+struct FusedForm {
   const unsigned char *afrag, *afrag_lo;
   const void *wtab;
   const void *geo;        // FormGeo<T>[n_cells]
+  void *values;
+  int n_q_pad, nks;
+};
+
+struct FusedArgs {
+  FusedForm f[2];
   const FusedTask *tasks;
   int ntasks;
   const FusedLane *lanes;
   const uint16_t *srank;  // [pairs][rstride], schedule order: LDS byte offsets of a lane's outputs
-  void *values;
-  int n_phi, n_q_pad, nks, rstride;
+                          // (lane order, four per row tile; entries past rstride are padding)
+  int n_phi, rstride;
 };
 
-// Geometry pass: FP64 geometry of every cell (Section 4.2) and the factors of
-// H of one form, with the arithmetic of the cell kernel.
+// Geometry pass: FP64 geometry of every cell (Section 4.2), once, and the
+// factors of H of up to four forms of one precision, with the arithmetic of
+// the cell kernel.
+struct GeoTargets {
+  int nforms;
+  int nd[4];
+  const FormHeader *hdr[4];
+  void *out[4];
+  int32_t *status[4];
+};
+
 template <class P>
 __global__ __launch_bounds__(256) void k_form_geo(const double *coords, int64_t n_cells, int d,
-                                                   int nd, const FormHeader *hdr,
-                                                   FormGeo<typename P::real> *geo,
-                                                   int32_t *status) {
+                                                   GeoTargets g) {
   typedef typename P::real T;
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n_cells) return;
   double G[3][3], adet;
   const bool ok = cell_geometry(d, coords + c * (d + 1) * d, G, adet);
-  typename P::hreal Gp[3][3];
-  T inv;
-  cell_factors<P>(hdr, nd, true, ok, G, adet, 1.0, Gp, inv);
-  FormGeo<T> r;
-  r.g[0] = Gp[0][0];
-  r.g[1] = Gp[0][1];
-  r.g[2] = Gp[0][2];
-  r.g[3] = Gp[1][1];
-  r.g[4] = Gp[1][2];
-  r.g[5] = Gp[2][2];
-  r.inv = inv;
-  r.pad = 0;
-  geo[c] = r;
-  if (!ok) atomicOr(status, STATUS_DEGENERATE);
+  for (int f = 0; f < g.nforms; ++f) {
+    typename P::hreal Gp[3][3];
+    T inv;
+    cell_factors<P>(g.hdr[f], g.nd[f], true, ok, G, adet, 1.0, Gp, inv);
+    FormGeo<T> r;
+    r.g[0] = Gp[0][0];
+    r.g[1] = Gp[0][1];
+    r.g[2] = Gp[0][2];
+    r.g[3] = Gp[1][1];
+    r.g[4] = Gp[1][2];
+    r.g[5] = Gp[2][2];
+    r.inv = inv;
+    r.pad = 0;
+    ((FormGeo<T> *)g.out[f])[c] = r;
+    if (!ok) atomicOr(g.status[f], STATUS_DEGENERATE);
+  }
 }
 
 __device__ __forceinline__ int lane_word1(const FusedLane &l) {
@@ -89,58 +108,243 @@ __device__ __forceinline__ T shfl_t(T v, int src) {
   }
 }
 
+// LDS copy of one form's tables.  The weighted table holds one row per j
+// with (chunk qc, slab t, K-slot entries) in the order the K loop reads
+// them, so that a lane's reads are one base plus constant offsets.  Rows are
+// padded by 16 bytes: the 16 lanes of a K-slot read 16 different rows j at
+// the same offset, which would fall into the same LDS banks with a
+// power-of-two row stride.
+template <class P>
+struct FormLds {
+  const unsigned char *af, *afl;
+  const typename P::hreal *wt;
+  int jstride;
+};
+
 template <class P, int MT, int NDT, bool STAGE_A, int NW>
-__global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
-  typedef typename P::real T;
-  typedef typename P::hreal HT;  // weighted table and H formation
-  typedef typename P::acc ACC;
+__device__ __forceinline__ unsigned char *stage_form(unsigned char *base, const FusedForm &F,
+                                                     int nphi, int tid, FormLds<P> &out) {
+  typedef typename P::hreal HT;
   typedef typename P::frag FRAG;
-  typedef FormGeo<T> GEO;
-  constexpr int KPL = P::KPL;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int n = lane & 15, kb = lane >> 4;
-  const int nphi = a.n_phi, n_q_pad = a.n_q_pad, nks = a.nks;
-  const int nqc = n_q_pad / P::KSTEP;
-
-  // Staged weighted table, one row per j holding (chunk qc, slab t, K-slot
-  // entries) in the order the K loop reads them, so that a lane's reads are
-  // one base plus constant offsets.  Rows are padded by 16 bytes: the 16
-  // lanes of a K-slot read 16 different rows j at the same offset, which
-  // would fall into the same LDS banks with a power-of-two row stride.
+  const size_t frag_bytes = STAGE_A ? (size_t)MT * F.nks * 64 * sizeof(FRAG) : 0;
+  unsigned char *s_af = base;
+  unsigned char *s_afl = base + frag_bytes;
+  HT *s_wt = (HT *)(base + frag_bytes * (P::SPLIT ? 2 : 1));
   constexpr int WPAD = 16 / sizeof(HT);
-  const int jstride = NDT * n_q_pad + WPAD;
-  const size_t frag_bytes = STAGE_A ? (size_t)MT * nks * 64 * sizeof(FRAG) : 0;
-  const size_t wtab_bytes = (size_t)nphi * jstride * sizeof(HT);
-  unsigned char *s_af = smem;
-  unsigned char *s_afl = smem + frag_bytes;
-  HT *s_wt = (HT *)(smem + frag_bytes * (P::SPLIT ? 2 : 1));
-  T *rowbuf = (T *)(smem + frag_bytes * (P::SPLIT ? 2 : 1) + wtab_bytes) +
-              (size_t)wave * (FUSED_SPAN + 64);
-
+  const int jstride = NDT * F.n_q_pad + WPAD;
   if constexpr (STAGE_A) {
     const size_t n16 = frag_bytes / 16;
-    for (size_t t = tid; t < n16; t += NW * 64) ((uint4 *)s_af)[t] = ((const uint4 *)a.afrag)[t];
+    for (size_t t = tid; t < n16; t += NW * 64) ((uint4 *)s_af)[t] = ((const uint4 *)F.afrag)[t];
     if constexpr (P::SPLIT)
-      for (size_t t = tid; t < n16; t += NW * 64) ((uint4 *)s_afl)[t] = ((const uint4 *)a.afrag_lo)[t];
+      for (size_t t = tid; t < n16; t += NW * 64) ((uint4 *)s_afl)[t] = ((const uint4 *)F.afrag_lo)[t];
   }
   {
     // global table [t][j][n_q_pad], copied by 16-byte pieces (one piece never
     // straddles two K-steps: a K-step is 16, 32 or 128 bytes)
     constexpr int E = 16 / sizeof(HT);
-    const int per_row = n_q_pad / E;
+    const int per_row = F.n_q_pad / E;
     const int nrows = NDT * nphi;
     for (int u = tid; u < nrows * per_row; u += NW * 64) {
       const int row = u / per_row, q = (u - row * per_row) * E;
       const int t = row / nphi, j = row - t * nphi;
       const int qc = q / P::KSTEP, qq = q - qc * P::KSTEP;
       *(uint4 *)(s_wt + (size_t)j * jstride + (qc * NDT + t) * P::KSTEP + qq) =
-          ((const uint4 *)a.wtab)[u];
+          ((const uint4 *)F.wtab)[u];
     }
   }
+  out.af = STAGE_A ? s_af : F.afrag;
+  out.afl = STAGE_A ? s_afl : F.afrag_lo;
+  out.wt = s_wt;
+  out.jstride = jstride;
+  return (unsigned char *)(s_wt + (size_t)nphi * jstride);
+}
+
+// Lane record and factors of one tile column, handed over by cross-lane
+// permutes from the lane holding slot src of the task.
+template <class T>
+struct Column {
+  int cell, jv, rnd, maxr;
+};
+
+// One tile of one form: LDS offsets of the outputs, H formed per K-slice
+// and contracted on the matrix cores, then added into the row buffer in
+// rounds.  `after_k` runs between the contraction and the scatter (used to
+// issue the next task's loads).
+template <class P, int MT, int NDT, bool STAGE_A, class AfterK>
+__device__ __forceinline__ void fused_tile(const FormLds<P> &S, const FusedForm &F,
+                                           const FormGeo<typename P::real> &cg, int src,
+                                           const Column<typename P::real> &col,
+                                           const uint16_t *rk, int rstride, int lane, int kb,
+                                           typename P::real *rowbuf, AfterK after_k) {
+  typedef typename P::real T;
+  typedef typename P::hreal HT;
+  typedef typename P::acc ACC;
+  typedef typename P::frag FRAG;
+  constexpr int KPL = P::KPL;
+  const int nqc = F.n_q_pad / P::KSTEP;
+
+  HT Gs[3][3];  // values of the half type when H is formed in half: exact
+  {
+    const HT g0 = (HT)shfl_t(cg.g[0], src);
+    HT g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0;
+    if constexpr (NDT > 1) {
+      g1 = (HT)shfl_t(cg.g[1], src);
+      g2 = (HT)shfl_t(cg.g[2], src);
+      g3 = (HT)shfl_t(cg.g[3], src);
+      g4 = (HT)shfl_t(cg.g[4], src);
+      g5 = (HT)shfl_t(cg.g[5], src);
+    }
+    Gs[0][0] = g0; Gs[0][1] = g1; Gs[0][2] = g2;
+    Gs[1][0] = g1; Gs[1][1] = g3; Gs[1][2] = g4;
+    Gs[2][0] = g2; Gs[2][1] = g4; Gs[2][2] = g5;
+  }
+  const T inv = shfl_t(cg.inv, src);
+
+  // LDS byte offsets of this lane's outputs inside the row buffer, in lane
+  // order (four per row tile: one 8-byte load), loaded before the
+  // contraction so that their latency hides behind it.  Padding rows point
+  // at the lane's private slot; idle lanes never scatter.
+  int addr[MT][4];
+  {
+    const int dummy = FUSED_SPAN * (int)sizeof(T) + lane * (int)sizeof(T);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      // entries past the stored width are padding rows
+      uint2 u = {(unsigned)(dummy | dummy << 16), (unsigned)(dummy | dummy << 16)};
+      if (mt * 16 + 4 * kb < rstride) u = *(const uint2 *)(rk + mt * 16);
+      addr[mt][0] = (int)(u.x & 0xffff);
+      addr[mt][1] = (int)(u.x >> 16);
+      addr[mt][2] = (int)(u.y & 0xffff);
+      addr[mt][3] = (int)(u.y >> 16);
+    }
+  }
+
+  ACC acc[MT];
+  ACC acc2[P::SPLIT ? MT : 1];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    acc[mt] = ACC{0, 0, 0, 0};
+    if constexpr (P::SPLIT) acc2[mt] = ACC{0, 0, 0, 0};
+  }
+  // geometry factors of H in both halves of a register (half path)
+  half2_t g2[NDT][NDT];
+#pragma unroll
+  for (int s = 0; s < NDT; ++s)
+#pragma unroll
+    for (int t = 0; t < NDT; ++t) {
+      if constexpr (P::H16) g2[s][t] = half2_t{(_Float16)Gs[s][t], (_Float16)Gs[s][t]};
+      else g2[s][t] = half2_t{0, 0};
+    }
+  // K = (s, q) walked q-chunk outer, s inner, as in the cell kernel
+  const HT *wcol = S.wt + (size_t)col.jv * S.jstride + kb * KPL;
+  for (int qc = 0; qc < nqc; ++qc) {
+    if constexpr (P::H16) {
+      // the chunk's table reads first, then per s its fragments, H and the
+      // contraction
+      half8_t wv[NDT];
+#pragma unroll
+      for (int t = 0; t < NDT; ++t) wv[t] = *(const half8_t *)(wcol + (qc * NDT + t) * P::KSTEP);
+#pragma unroll
+      for (int s = 0; s < NDT; ++s) {
+        FRAG af[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const size_t fi = frag_slot(mt, s, qc, MT, NDT) * 64 + lane;
+          if constexpr (STAGE_A) af[mt] = lds_frag<P>(S.af, fi);
+          else af[mt] = P::load(S.af, fi);
+        }
+        const half8_t hf = form_h16<NDT>(g2[s], wv);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt] = P::mma(af[mt], hf, acc[mt]);
+      }
+    } else {
+      T wv[NDT][KPL];
+#pragma unroll
+      for (int t = 0; t < NDT; ++t) load_w<T, KPL>(wcol + (qc * NDT + t) * P::KSTEP, wv[t]);
+#pragma unroll
+      for (int s = 0; s < NDT; ++s) {
+        T h[KPL];
+        form_h<T, NDT, KPL>(Gs[s], wv, h);
+        if constexpr (P::SPLIT) {
+          FRAG hh, hl;
+          P::pack2(h, hh, hl);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const size_t fi = frag_slot(mt, s, qc, MT, NDT) * 64 + lane;
+            FRAG af, al;
+            if constexpr (STAGE_A) {
+              af = lds_frag<P>(S.af, fi);
+              al = lds_frag<P>(S.afl, fi);
+            } else {
+              af = P::load(S.af, fi);
+              al = P::load(S.afl, fi);
+            }
+            acc[mt] = P::mma(af, hh, acc[mt]);
+            acc2[mt] = P::mma(af, hl, acc2[mt]);
+            acc2[mt] = P::mma(al, hh, acc2[mt]);
+          }
+        } else {
+          const FRAG hf = P::pack(h);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const size_t fi = frag_slot(mt, s, qc, MT, NDT) * 64 + lane;
+            FRAG af;
+            if constexpr (STAGE_A) af = lds_frag<P>(S.af, fi);
+            else af = P::load(S.af, fi);
+            acc[mt] = P::mma(af, hf, acc[mt]);
+          }
+        }
+      }
+    }
+  }
+
+  after_k();
+
+  // scatter into the owned rows, one round per repeated row; within a
+  // round every lane adds to a different entry (padding rows update the
+  // lane's private slot instead: no branch per entry)
+  T val[MT][4];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      T v = acc[mt][q];
+      if constexpr (P::SPLIT) v += acc2[mt][q] * (T)(1.0 / 2048.0);
+      val[mt][q] = v * inv;
+    }
+  unsigned char *rb = (unsigned char *)rowbuf;
+  for (int r = 0; r <= col.maxr; ++r) {
+    if (col.rnd == r) {
+      // read all, then write all: a lane's entries are distinct and the
+      // lanes of one round hold distinct rows
+      T old[MT][4];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) old[mt][q] = *(const T *)(rb + addr[mt][q]);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *(T *)(rb + addr[mt][q]) = old[mt][q] + val[mt][q];
+    }
+  }
+}
+
+template <class P, int MT, int NDT0, int NDT1, int NF, bool STAGE_A, int NW>
+__global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
+  typedef typename P::real T;
+  typedef FormGeo<T> GEO;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int n = lane & 15, kb = lane >> 4;
+  const int nphi = a.n_phi;
+
+  FormLds<P> S0, S1;
+  unsigned char *end = stage_form<P, MT, NDT0, STAGE_A, NW>(smem, a.f[0], nphi, tid, S0);
+  if constexpr (NF == 2) end = stage_form<P, MT, NDT1, STAGE_A, NW>(end, a.f[1], nphi, tid, S1);
+  T *rowbuf = (T *)end + (size_t)wave * (FUSED_SPAN + 64);
   __syncthreads();
 
-  const GEO *geo = (const GEO *)a.geo;
   const int ntasks = a.ntasks;
   const int stride = gridDim.x * NW;
   int task = blockIdx.x * NW + wave;
@@ -148,7 +352,9 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
   // lane record (two words) and factors of slot `lane` of the wave's task
   FusedTask tk{};
   int lw0 = -1, lw1 = 0;
-  GEO gg{};
+  GEO gg[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) gg[f] = GEO{};
   if (task < ntasks) {
     tk = a.tasks[task];
     if (lane < tk.nt * 16) {
@@ -156,182 +362,79 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
       lw0 = l.cell;
       lw1 = lane_word1(l);
     }
-    if (lw0 >= 0) gg = geo[lw0];
+    if (lw0 >= 0)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) gg[f] = ((const GEO *)a.f[f].geo)[lw0];
   }
 
   while (task < ntasks) {
     const int nt = tk.nt, span = tk.span, p0 = tk.p0, pre = tk.pre;
     const int64_t base = tk.base;
     const int cw0 = lw0, cw1 = lw1;
-    const GEO cg = gg;
+    GEO cg[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) cg[f] = gg[f];
     const int next = task + stride;
     const bool has_next = next < ntasks;
     if (has_next) tk = a.tasks[next];
 
-    {
-      constexpr int E4 = 16 / sizeof(T);  // elements per 16-byte store
-      const int n16 = (span + E4 - 1) / E4;
-      for (int t = lane; t < n16; t += 64) ((uint4 *)rowbuf)[t] = uint4{0, 0, 0, 0};
-    }
-
-    for (int tl = 0; tl < nt; ++tl) {
-      // this lane's column: slot 16 tl + n of the task
-      const int src = 16 * tl + n;
-      const int cell = __shfl(cw0, src);
-      const int w1 = __shfl(cw1, src);
-      const int jv = (w1 >> 16) & 0xff, rnd = (w1 >> 24) & 0xf;
-      HT Gs[3][3];  // values of the half type when H is formed in half: exact
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
       {
-        const HT g0 = (HT)shfl_t(cg.g[0], src), g1 = (HT)shfl_t(cg.g[1], src);
-        const HT g2 = (HT)shfl_t(cg.g[2], src), g3 = (HT)shfl_t(cg.g[3], src);
-        const HT g4 = (HT)shfl_t(cg.g[4], src), g5 = (HT)shfl_t(cg.g[5], src);
-        Gs[0][0] = g0; Gs[0][1] = g1; Gs[0][2] = g2;
-        Gs[1][0] = g1; Gs[1][1] = g3; Gs[1][2] = g4;
-        Gs[2][0] = g2; Gs[2][1] = g4; Gs[2][2] = g5;
+        constexpr int E4 = 16 / sizeof(T);  // elements per 16-byte store
+        const int n16 = (span + E4 - 1) / E4;
+        for (int t = lane; t < n16; t += 64) ((uint4 *)rowbuf)[t] = uint4{0, 0, 0, 0};
       }
-      const T inv = shfl_t(cg.inv, src);
-
-      // LDS byte offsets of this lane's outputs inside the row buffer, in
-      // lane order (four per row tile: one 8-byte load), loaded before the
-      // contraction so that their latency hides behind it.  Padding rows
-      // point at the lane's private slot; idle lanes never scatter.
-      int addr[MT][4];
-      {
-        const int pair = cell < 0 ? 0 : p0 + ((pre >> (8 * tl)) & 0xff) + n;
+      for (int tl = 0; tl < nt; ++tl) {
+        // this lane's column: slot 16 tl + n of the task
+        const int src = 16 * tl + n;
+        Column<T> col;
+        col.cell = __shfl(cw0, src);
+        const int w1 = __shfl(cw1, src);
+        col.jv = (w1 >> 16) & 0xff;
+        col.rnd = (w1 >> 24) & 0xf;
+        // the tile's last round, the same in every lane record of the tile
+        col.maxr = __builtin_amdgcn_readfirstlane((int)((unsigned)w1 >> 28));
+        const int pair = col.cell < 0 ? 0 : p0 + ((pre >> (8 * tl)) & 0xff) + n;
         const uint16_t *rk = a.srank + (size_t)pair * a.rstride + 4 * kb;
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const uint2 u = *(const uint2 *)(rk + mt * 16);
-          addr[mt][0] = (int)(u.x & 0xffff);
-          addr[mt][1] = (int)(u.x >> 16);
-          addr[mt][2] = (int)(u.y & 0xffff);
-          addr[mt][3] = (int)(u.y >> 16);
-        }
-      }
-      // next task's lane records, behind the first tile's contraction
-      if (tl == 0 && has_next) {
-        lw0 = -1;
-        lw1 = 0;
-        if (lane < tk.nt * 16) {
-          const FusedLane l = a.lanes[(size_t)tk.t0 * 16 + lane];
-          lw0 = l.cell;
-          lw1 = lane_word1(l);
-        }
-      }
-
-      ACC acc[MT];
-      ACC acc2[P::SPLIT ? MT : 1];
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        acc[mt] = ACC{0, 0, 0, 0};
-        if constexpr (P::SPLIT) acc2[mt] = ACC{0, 0, 0, 0};
-      }
-      // K = (s, q) walked q-chunk outer, s inner, as in the cell kernel
-      const HT *wcol = s_wt + (size_t)jv * jstride + kb * KPL;
-      for (int qc = 0; qc < nqc; ++qc) {
-        if constexpr (P::H16) {
-          half8_t wv[NDT];
-#pragma unroll
-          for (int t = 0; t < NDT; ++t) wv[t] = *(const half8_t *)(wcol + (qc * NDT + t) * P::KSTEP);
-#pragma unroll
-          for (int s = 0; s < NDT; ++s) {
-            const half8_t hf = form_h16<NDT>(Gs[s], wv);
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-              const size_t fi = frag_slot(mt, s, qc, MT, NDT) * 64 + lane;
-              FRAG af;
-              if constexpr (STAGE_A) af = lds_frag<P>(s_af, fi);
-              else af = P::load(a.afrag, fi);
-              acc[mt] = P::mma(af, hf, acc[mt]);
-            }
-          }
-        } else {
-          T wv[NDT][KPL];
-#pragma unroll
-          for (int t = 0; t < NDT; ++t) load_w<T, KPL>(wcol + (qc * NDT + t) * P::KSTEP, wv[t]);
-#pragma unroll
-          for (int s = 0; s < NDT; ++s) {
-            T h[KPL];
-            form_h<T, NDT, KPL>(Gs[s], wv, h);
-            if constexpr (P::SPLIT) {
-              FRAG hh, hl;
-              P::pack2(h, hh, hl);
-#pragma unroll
-              for (int mt = 0; mt < MT; ++mt) {
-                const size_t fi = frag_slot(mt, s, qc, MT, NDT) * 64 + lane;
-                FRAG af, al;
-                if constexpr (STAGE_A) {
-                  af = lds_frag<P>(s_af, fi);
-                  al = lds_frag<P>(s_afl, fi);
-                } else {
-                  af = P::load(a.afrag, fi);
-                  al = P::load(a.afrag_lo, fi);
-                }
-                acc[mt] = P::mma(af, hh, acc[mt]);
-                acc2[mt] = P::mma(af, hl, acc2[mt]);
-                acc2[mt] = P::mma(al, hh, acc2[mt]);
-              }
-            } else {
-              const FRAG hf = P::pack(h);
-#pragma unroll
-              for (int mt = 0; mt < MT; ++mt) {
-                const size_t fi = frag_slot(mt, s, qc, MT, NDT) * 64 + lane;
-                FRAG af;
-                if constexpr (STAGE_A) af = lds_frag<P>(s_af, fi);
-                else af = P::load(a.afrag, fi);
-                acc[mt] = P::mma(af, hf, acc[mt]);
-              }
-            }
+        // the next task's lane records and then its factors, behind the
+        // first tile's contraction
+        if (f == 0 && tl == 0 && has_next) {
+          lw0 = -1;
+          lw1 = 0;
+          if (lane < tk.nt * 16) {
+            const FusedLane l = a.lanes[(size_t)tk.t0 * 16 + lane];
+            lw0 = l.cell;
+            lw1 = lane_word1(l);
           }
         }
+        // (the factors are held only from the last form's first tile on)
+        auto after_k = [&]() {
+          if (f == NF - 1 && tl == 0 && has_next) {
+#pragma unroll
+            for (int e = 0; e < NF; ++e) gg[e] = GEO{};
+            if (lw0 >= 0)
+#pragma unroll
+              for (int e = 0; e < NF; ++e) gg[e] = ((const GEO *)a.f[e].geo)[lw0];
+          }
+        };
+        if (f == 0)
+          fused_tile<P, MT, NDT0, STAGE_A>(S0, a.f[0], cg[0], src, col, rk, a.rstride, lane, kb,
+                                            rowbuf, after_k);
+        else if constexpr (NF == 2)
+          fused_tile<P, MT, NDT1, STAGE_A>(S1, a.f[1], cg[NF - 1], src, col, rk, a.rstride, lane,
+                                            kb, rowbuf, after_k);
       }
-
-      // next task's factors: its lane records have arrived by now
-      if (tl == 0 && has_next) {
-        gg = GEO{};
-        if (lw0 >= 0) gg = geo[lw0];
-      }
-
-      // scatter into the owned rows, one round per repeated row; within a
-      // round every lane adds to a different entry (padding rows update the
-      // lane's private slot instead: no branch per entry)
-      T val[MT][4];
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          T v = acc[mt][q];
-          if constexpr (P::SPLIT) v += acc2[mt][q] * (T)(1.0 / 2048.0);
-          val[mt][q] = v * inv;
-        }
-      unsigned char *rb = (unsigned char *)rowbuf;
-      // the tile's last round, the same in every lane record of the tile
-      const int maxr = __builtin_amdgcn_readfirstlane((int)((unsigned)w1 >> 28));
-      for (int r = 0; r <= maxr; ++r) {
-        if (rnd == r) {
-          // read all, then write all: a lane's entries are distinct and the
-          // lanes of one round hold distinct rows
-          T old[MT][4];
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) old[mt][q] = *(const T *)(rb + addr[mt][q]);
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) *(T *)(rb + addr[mt][q]) = old[mt][q] + val[mt][q];
-        }
-      }
+      T *V = (T *)a.f[f].values + base;
+      for (int t = lane; t < span; t += 64) V[t] = rowbuf[t];
     }
-    T *V = (T *)a.values + base;
-    for (int t = lane; t < span; t += 64) V[t] = rowbuf[t];
     task = next;
   }
 }
 
-template <class P, int MT, int NDT, bool SA, int NW>
+template <class P, int MT, int NDT0, int NDT1, int NF, bool SA, int NW>
 static fe_status launch_fused_one(const FusedArgs &k, size_t smem, hipStream_t s) {
-  auto kern = fused_kernel<P, MT, NDT, SA, NW>;
+  auto kern = fused_kernel<P, MT, NDT0, NDT1, NF, SA, NW>;
   if (smem > 65536 && hipFuncSetAttribute((const void *)kern,
                                           hipFuncAttributeMaxDynamicSharedMemorySize,
                                           (int)smem) != hipSuccess)
@@ -349,53 +452,84 @@ static fe_status launch_fused_one(const FusedArgs &k, size_t smem, hipStream_t s
   return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
 }
 
-template <class P, int MT, int NDT>
-static fe_status launch_fused_nw(const FusedArgs &k, const FormLayout &L, hipStream_t s) {
-  // the most waves per workgroup that fit, B^T fragments staged when they fit
-  if (fused_lds(L, 16, true) <= FUSED_LDS_BUDGET)
-    return launch_fused_one<P, MT, NDT, true, 16>(k, fused_lds(L, 16, true), s);
-  if (fused_lds(L, 12, true) <= FUSED_LDS_BUDGET)
-    return launch_fused_one<P, MT, NDT, true, 12>(k, fused_lds(L, 12, true), s);
-  if (fused_lds(L, 8, true) <= FUSED_LDS_BUDGET)
-    return launch_fused_one<P, MT, NDT, true, 8>(k, fused_lds(L, 8, true), s);
-  if (fused_lds(L, 8, false) <= FUSED_LDS_BUDGET)
-    return launch_fused_one<P, MT, NDT, false, 8>(k, fused_lds(L, 8, false), s);
-  if (fused_lds(L, 4, false) <= FUSED_LDS_BUDGET)
-    return launch_fused_one<P, MT, NDT, false, 4>(k, fused_lds(L, 4, false), s);
+template <class P, int MT, int NDT0, int NDT1, int NF>
+static fe_status launch_fused_nw(const FusedArgs &k, const FormLayout *const *L, hipStream_t s) {
+  // the most waves per workgroup that fit, B^T fragments staged when they
+  // fit (a pass over two forms needs them staged with at least 8 waves)
+  if constexpr (NF == 2) {
+    if (fused_lds(L, NF, 16, true) <= FUSED_LDS_BUDGET)
+      return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 16>(k, fused_lds(L, NF, 16, true), s);
+    if (fused_lds(L, NF, 12, true) <= FUSED_LDS_BUDGET)
+      return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 12>(k, fused_lds(L, NF, 12, true), s);
+    if (fused_lds(L, NF, 8, true) <= FUSED_LDS_BUDGET)
+      return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 8>(k, fused_lds(L, NF, 8, true), s);
+    return FE_EUNSUPPORTED;
+  }
+  if (fused_lds(L, NF, 16, true) <= FUSED_LDS_BUDGET)
+    return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 16>(k, fused_lds(L, NF, 16, true), s);
+  if (fused_lds(L, NF, 12, true) <= FUSED_LDS_BUDGET)
+    return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 12>(k, fused_lds(L, NF, 12, true), s);
+  if (fused_lds(L, NF, 8, true) <= FUSED_LDS_BUDGET)
+    return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 8>(k, fused_lds(L, NF, 8, true), s);
+  if (fused_lds(L, NF, 8, false) <= FUSED_LDS_BUDGET)
+    return launch_fused_one<P, MT, NDT0, NDT1, NF, false, 8>(k, fused_lds(L, NF, 8, false), s);
+  if (fused_lds(L, NF, 4, false) <= FUSED_LDS_BUDGET)
+    return launch_fused_one<P, MT, NDT0, NDT1, NF, false, 4>(k, fused_lds(L, NF, 4, false), s);
   return FE_EUNSUPPORTED;
 }
 
 template <class P>
 fe_status launch_fused_impl(const FusedLaunch &a) {
   typedef typename P::real T;
-  const FormLayout &L = *a.L;
+  const FormLayout *const *L = a.L;
   hipStream_t s = (hipStream_t)a.stream;
-  if (!fused_eligible(L)) return FE_EUNSUPPORTED;
-  if (a.n_cells > 0) {
+  for (int f = 0; f < a.nforms; ++f)
+    if (!fused_eligible(*L[f])) return FE_EUNSUPPORTED;
+  if (a.nforms == 2 && !fused_pair_fits(L)) return FE_EUNSUPPORTED;
+  if (a.n_cells > 0 && a.geo_forms > 0) {
+    GeoTargets g;
+    g.nforms = a.geo_forms;
+    for (int f = 0; f < a.geo_forms; ++f) {
+      g.nd[f] = a.geo_nd[f];
+      g.hdr[f] = (const FormHeader *)a.geo_bufs[f];
+      g.out[f] = a.geo_out[f];
+      g.status[f] = (int32_t *)a.geo_bufs[f];
+    }
     hipLaunchKernelGGL(k_form_geo<P>, dim3((unsigned)((a.n_cells + 255) / 256)), dim3(256), 0, s,
-                       a.coords, a.n_cells, L.d, L.nd, (const FormHeader *)a.form_buf,
-                       (FormGeo<T> *)a.geo, a.status);
+                       a.coords, a.n_cells, L[0]->d, g);
     if (hipGetLastError() != hipSuccess) return FE_EHIP;
   }
-  if (a.ntasks <= 0) return FE_OK;
+  if (a.ntasks <= 0 || !a.run_fused) return FE_OK;
   FusedArgs k;
-  k.afrag = a.form_buf + L.off_afrag;
-  k.afrag_lo = a.form_buf + L.off_afrag_lo;
-  k.wtab = a.form_buf + L.off_wtab;
-  k.geo = a.geo;
+  for (int f = 0; f < 2; ++f) {
+    const int e = f < a.nforms ? f : 0;
+    k.f[f].afrag = a.form_buf[e] + L[e]->off_afrag;
+    k.f[f].afrag_lo = a.form_buf[e] + L[e]->off_afrag_lo;
+    k.f[f].wtab = a.form_buf[e] + L[e]->off_wtab;
+    k.f[f].geo = a.geo[e];
+    k.f[f].values = a.values[e];
+    k.f[f].n_q_pad = L[e]->n_q_pad;
+    k.f[f].nks = L[e]->nks;
+  }
   k.tasks = a.tasks;
   k.ntasks = (int)a.ntasks;
   k.lanes = a.lanes;
   k.srank = a.srank;
-  k.values = a.values;
-  k.n_phi = L.n_phi;
-  k.n_q_pad = L.n_q_pad;
-  k.nks = L.nks;
+  k.n_phi = L[0]->n_phi;
   k.rstride = a.rstride;
-#define FE_FL(M)                                               \
-  if (L.mt == M) {                                             \
-    if (L.ndt == 1) return launch_fused_nw<P, M, 1>(k, L, s);  \
-    return launch_fused_nw<P, M, 3>(k, L, s);                  \
+  const int mt = L[0]->mt;
+  const int d0 = L[0]->ndt, d1 = a.nforms == 2 ? L[1]->ndt : 1;
+#define FE_FL(M)                                                                         \
+  if (mt == M) {                                                                         \
+    if (a.nforms == 1) {                                                                 \
+      if (d0 == 1) return launch_fused_nw<P, M, 1, 1, 1>(k, L, s);                       \
+      return launch_fused_nw<P, M, 3, 1, 1>(k, L, s);                                    \
+    }                                                                                    \
+    if constexpr (M <= 4) {                                                              \
+      if (d0 == 1 && d1 == 3) return launch_fused_nw<P, M, 1, 3, 2>(k, L, s);            \
+      if (d0 == 3 && d1 == 1) return launch_fused_nw<P, M, 3, 1, 2>(k, L, s);            \
+    }                                                                                    \
+    return FE_EUNSUPPORTED;                                                              \
   }
   FE_FL(1) FE_FL(2) FE_FL(3) FE_FL(4) FE_FL(6) FE_FL(8) FE_FL(11)
 #undef FE_FL

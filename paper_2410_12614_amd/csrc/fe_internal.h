@@ -118,35 +118,58 @@ struct FormGeo {
 };
 
 struct FusedLaunch {
-  const FormLayout *L;
-  const unsigned char *form_buf;
-  int32_t *status;        // device status word (inside form_buf)
+  // one pass over the schedule computes one form, or two forms of one
+  // precision one after the other per task (the schedule-order ranks, lane
+  // records and task records are then read from HBM once)
+  int nforms;
+  const FormLayout *L[2];
+  const unsigned char *form_buf[2];
+  void *geo[2];           // workspace: n_cells FormGeo records per form
+  void *values[2];
   const double *coords;   // device [n_cells][d+1][d]
   int64_t n_cells;
-  void *geo;              // workspace: n_cells FormGeo records
+  // geometry pass: when geo_forms > 0 this launch first writes the records
+  // of geo_forms forms of this precision
+  int geo_forms;
+  bool run_fused;         // false: geometry pass only
+  const unsigned char *geo_bufs[4];  // their form buffers (header, status word)
+  int geo_nd[4];
+  void *geo_out[4];
   const FusedTask *tasks;
   int64_t ntasks;         // tasks of the schedule (from the FILL phase)
   const FusedLane *lanes;
   const uint16_t *srank;  // [pairs][rstride]: LDS byte offsets, see fe_fused.h
   int rstride;
-  void *values;
   void *stream;
 };
-// LDS of the fused kernel with nw waves per workgroup: the weighted table
-// (always staged: it is read per lane with 16 different rows per K-slot),
-// the B^T fragments if staged, and one row buffer per wave.
-inline size_t fused_lds(const FormLayout &L, int nw, bool with_frags) {
-  const size_t real = (L.prec == FE_FP64) ? 8 : 4;
-  const size_t frag = (L.elt_bytes == 2) ? 16 : L.elt_bytes;
-  const size_t rows = (size_t)nw * (FUSED_SPAN + 64) * real;  // + a private slot per lane
-  const size_t frags =
-      with_frags ? (size_t)L.mt * L.nks * 64 * frag * (L.prec == FE_SPLITFP16_ACC32 ? 2 : 1) : 0;
-  const size_t tab = L.tab_bytes;
-  const size_t wtab = (size_t)L.n_phi * (L.ndt * L.n_q_pad + 16 / tab) * tab;
-  return rows + frags + wtab;
+
+// LDS of the fused kernel with nw waves per workgroup over nforms forms: per
+// form the weighted table (always staged: it is read per lane with 16
+// different rows per K-slot) and the B^T fragments if staged, and one row
+// buffer (plus a private slot per lane) per wave.
+inline size_t fused_lds(const FormLayout *const *L, int nforms, int nw, bool with_frags) {
+  const size_t real = (L[0]->prec == FE_FP64) ? 8 : 4;
+  size_t bytes = (size_t)nw * (FUSED_SPAN + 64) * real;
+  for (int f = 0; f < nforms; ++f) {
+    const FormLayout &F = *L[f];
+    const size_t frag = (F.elt_bytes == 2) ? 16 : F.elt_bytes;
+    if (with_frags)
+      bytes += (size_t)F.mt * F.nks * 64 * frag * (F.prec == FE_SPLITFP16_ACC32 ? 2 : 1);
+    const size_t tab = F.tab_bytes;
+    bytes += (size_t)F.n_phi * (F.ndt * F.n_q_pad + 16 / tab) * tab;
+  }
+  return bytes;
 }
 constexpr size_t FUSED_LDS_BUDGET = 156 * 1024;
 bool fused_eligible(const FormLayout &L);
+
+// Can two forms share one fused pass: same precision and degree, one mass
+// and one stiffness form with at most 4 row tiles, and both forms' tables
+// next to the row buffers of at least 8 waves?
+inline bool fused_pair_fits(const FormLayout *const *L) {
+  return L[0]->n_phi == L[1]->n_phi && L[0]->prec == L[1]->prec && L[0]->mt <= 4 &&
+         L[0]->ndt != L[1]->ndt && fused_lds(L, 2, 8, true) <= FUSED_LDS_BUDGET;
+}
 fe_status launch_fused_fp64(const FusedLaunch &a);
 fe_status launch_fused_fp32(const FusedLaunch &a);
 fe_status launch_fused_fp16(const FusedLaunch &a);

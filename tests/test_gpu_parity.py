@@ -164,6 +164,32 @@ def test_numeric_is_bitwise_repeatable():
         assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("prec", ["fp16", "fp64"])
+def test_numeric_halves_equal_numeric(prec):
+    """FE_NUMERIC_GEOMETRY then FE_NUMERIC_FUSED (twice, the second reusing
+    the records) give exactly the values of FE_NUMERIC; the halves are
+    refused where the fused path does not apply."""
+    mesh = mesh_of("c2s")
+    descs = [api.form_desc(3, 4, 8, f, prec) for f in ("mass", "stiffness")]
+    mv = api.MeshView.from_numpy(mesh.cell_coords, mesh.dofmap, mesh.n_dofs)
+    asm = api.Assembly(mv, descs)
+    ref = [v.clone() for v in asm.numeric()]
+    for v in asm.values:
+        v.fill_(float("nan"))
+    asm.numeric(part="geometry")
+    for _ in range(2):
+        got = asm.numeric(part="fused")
+        torch.cuda.synchronize()
+        for x, y in zip(ref, got):
+            assert torch.equal(x, y)
+    mesh3 = mesh_of("c3s")
+    mv3 = api.MeshView.from_numpy(mesh3.cell_coords, mesh3.dofmap, mesh3.n_dofs, mesh3.coeff)
+    asm3 = api.Assembly(mv3, [api.form_desc(3, 6, 14, "stiffness", prec, has_coeff=True)])
+    with pytest.raises(L.FeError) as e:
+        asm3.numeric(part="fused")
+    assert e.value.status == L.FE_EUNSUPPORTED
+
+
 def test_degenerate_cell_sets_status_and_nan():
     mesh = config_mesh("c2", n=1, degree=2, flatten=0.0)
     coords = mesh.cell_coords.copy()
