@@ -735,36 +735,47 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
   for (int f = 0; f < n_forms; ++f)
     if (!form_bufs || !form_bufs[f] || !mats[f].values) return FE_EINVAL;
   if (n_cells == 0) return FE_OK;  // values of an empty pattern: nothing to write
-  // fused row-ownership path when the FILL phase built its schedule
-  bool fused = phase != FE_NUMERIC_GATHER && mats[0].schedule > 0;
-  for (int f = 0; f < n_forms; ++f) fused = fused && fused_eligible(L[f]);
-  if (!fused && (phase == FE_NUMERIC_GEOMETRY || phase == FE_NUMERIC_FUSED)) return FE_EUNSUPPORTED;
-  if (fused) {
+  // Forms whose tables fit on chip take the fused row-ownership path when the
+  // FILL phase built its schedule; the others (coefficient forms, tables too
+  // large) take the cell kernels and the row gather.
+  bool on_fused[4] = {false, false, false, false};
+  int n_fused = 0;
+  for (int f = 0; f < n_forms; ++f) {
+    on_fused[f] = phase != FE_NUMERIC_GATHER && mats[0].schedule > 0 && fused_eligible(L[f]);
+    n_fused += on_fused[f] ? 1 : 0;
+  }
+  if ((phase == FE_NUMERIC_GEOMETRY || phase == FE_NUMERIC_FUSED) && n_fused < n_forms)
+    return FE_EUNSUPPORTED;
+  {
+    int fl[4], nf = 0;
+    for (int f = 0; f < n_forms; ++f)
+      if (on_fused[f]) fl[nf++] = f;
     // passes: two forms share one pass when they fit it together
-    const FormLayout *pairL[2] = {&L[0], n_forms > 1 ? &L[1] : &L[0]};
-    const bool pair = n_forms == 2 && fused_pair_fits(pairL);
-    for (int f = 0; f < n_forms; f += pair ? 2 : 1) {
+    const FormLayout *pairL[2] = {&L[fl[0]], nf > 1 ? &L[fl[1]] : &L[fl[0]]};
+    const bool pair = nf == 2 && fused_pair_fits(pairL);
+    for (int i = 0; i < nf; i += pair ? 2 : 1) {
+      const int f = fl[i];
       FusedLaunch a;
-      // the first form of each precision runs the geometry pass of all forms
-      // of that precision
+      // the first fused form of each precision runs the geometry pass of all
+      // fused forms of that precision
       a.geo_forms = 0;
       a.run_fused = phase != FE_NUMERIC_GEOMETRY;
       bool first = phase != FE_NUMERIC_FUSED;
-      for (int e = 0; e < f; ++e) first = first && forms[e].precision != forms[f].precision;
+      for (int e = 0; e < i; ++e) first = first && forms[fl[e]].precision != forms[f].precision;
       if (first)
-        for (int e = f; e < n_forms; ++e)
-          if (forms[e].precision == forms[f].precision) {
-            a.geo_bufs[a.geo_forms] = (const unsigned char *)form_bufs[e];
-            a.geo_nd[a.geo_forms] = L[e].nd;
-            a.geo_out[a.geo_forms] = (unsigned char *)workspace + geo_offset + e * geo_bytes;
+        for (int e = i; e < nf; ++e)
+          if (forms[fl[e]].precision == forms[f].precision) {
+            a.geo_bufs[a.geo_forms] = (const unsigned char *)form_bufs[fl[e]];
+            a.geo_nd[a.geo_forms] = L[fl[e]].nd;
+            a.geo_out[a.geo_forms] = (unsigned char *)workspace + geo_offset + fl[e] * geo_bytes;
             ++a.geo_forms;
           }
       a.nforms = pair ? 2 : 1;
       // a pair runs the form with more derivative slabs first: the next
       // task's factors are then held only during the lighter form
-      const bool swap = pair && L[f].ndt < L[f + 1].ndt;
+      const bool swap = pair && L[fl[0]].ndt < L[fl[1]].ndt;
       for (int e = 0; e < a.nforms; ++e) {
-        const int g = f + (swap ? 1 - e : e);
+        const int g = fl[i + (swap ? 1 - e : e)];
         a.L[e] = &L[g];
         a.form_buf[e] = (const unsigned char *)form_bufs[g];
         a.geo[e] = (unsigned char *)workspace + geo_offset + g * geo_bytes;
@@ -781,14 +792,17 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
       fe_status st = launch_fused(a);
       if (st != FE_OK) return st;
     }
-    return FE_OK;
   }
+  if (n_fused == n_forms) return FE_OK;
+  // cell kernels into the workspace, then one row gather over these forms
   void *Aloc[4] = {nullptr, nullptr, nullptr, nullptr};
   void *V[4] = {nullptr, nullptr, nullptr, nullptr};
   const size_t stride = (size_t)n_cells * n_phi * n_phi * elt;
+  int ng = 0;
   for (int f = 0; f < n_forms; ++f) {
-    Aloc[f] = (unsigned char *)workspace + f * stride;
-    V[f] = mats[f].values;
+    if (on_fused[f]) continue;
+    Aloc[ng] = (unsigned char *)workspace + f * stride;
+    V[ng] = mats[f].values;
     fe_mesh_view mv = *m;
     CellLaunch a;
     a.L = &L[f];
@@ -800,21 +814,22 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
     a.n_dofs = n_dofs;
     a.coeff = forms[f].has_coeff ? mv.coeff : nullptr;
     if (forms[f].has_coeff && !mv.coeff) return FE_EINVAL;
-    a.A_local = Aloc[f];
+    a.A_local = Aloc[ng];
     a.stream = stream;
     fe_status st = launch_cell(a);
     if (st != FE_OK) return st;
+    ++ng;
   }
   fe_status st = FE_EINVAL;
   if (elt == 8) {
-    switch (n_forms) {
+    switch (ng) {
       case 1: st = launch_gather<double, 1>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
       case 2: st = launch_gather<double, 2>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
       case 3: st = launch_gather<double, 3>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
       case 4: st = launch_gather<double, 4>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
     }
   } else {
-    switch (n_forms) {
+    switch (ng) {
       case 1: st = launch_gather<float, 1>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
       case 2: st = launch_gather<float, 2>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
       case 3: st = launch_gather<float, 3>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;

@@ -206,8 +206,11 @@ namespace fe {
 // The fused path needs the weighted table staged in LDS next to the row
 // buffers (see fe_fused.h): 8 waves x FUSED_SPAN values + table (+ fragments).
 bool fused_eligible(const FormLayout &L) {
+  // the tables (fragments included) must sit on chip next to the row
+  // buffers of at least 8 waves; otherwise the cell kernels and the row
+  // gather are faster
   const FormLayout *one[1] = {&L};
-  return !L.has_coeff && fused_lds(one, 1, 4, false) <= FUSED_LDS_BUDGET;
+  return !L.has_coeff && fused_lds(one, 1, 8, true) <= FUSED_LDS_BUDGET;
 }
 
 fe_status launch_cell(const CellLaunch &a) {

@@ -454,27 +454,14 @@ static fe_status launch_fused_one(const FusedArgs &k, size_t smem, hipStream_t s
 
 template <class P, int MT, int NDT0, int NDT1, int NF>
 static fe_status launch_fused_nw(const FusedArgs &k, const FormLayout *const *L, hipStream_t s) {
-  // the most waves per workgroup that fit, B^T fragments staged when they
-  // fit (a pass over two forms needs them staged with at least 8 waves)
-  if constexpr (NF == 2) {
-    if (fused_lds(L, NF, 16, true) <= FUSED_LDS_BUDGET)
-      return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 16>(k, fused_lds(L, NF, 16, true), s);
-    if (fused_lds(L, NF, 12, true) <= FUSED_LDS_BUDGET)
-      return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 12>(k, fused_lds(L, NF, 12, true), s);
-    if (fused_lds(L, NF, 8, true) <= FUSED_LDS_BUDGET)
-      return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 8>(k, fused_lds(L, NF, 8, true), s);
-    return FE_EUNSUPPORTED;
-  }
+  // the most waves per workgroup that fit with the B^T fragments staged
+  // (at least 8: see fused_eligible)
   if (fused_lds(L, NF, 16, true) <= FUSED_LDS_BUDGET)
     return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 16>(k, fused_lds(L, NF, 16, true), s);
   if (fused_lds(L, NF, 12, true) <= FUSED_LDS_BUDGET)
     return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 12>(k, fused_lds(L, NF, 12, true), s);
   if (fused_lds(L, NF, 8, true) <= FUSED_LDS_BUDGET)
     return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 8>(k, fused_lds(L, NF, 8, true), s);
-  if (fused_lds(L, NF, 8, false) <= FUSED_LDS_BUDGET)
-    return launch_fused_one<P, MT, NDT0, NDT1, NF, false, 8>(k, fused_lds(L, NF, 8, false), s);
-  if (fused_lds(L, NF, 4, false) <= FUSED_LDS_BUDGET)
-    return launch_fused_one<P, MT, NDT0, NDT1, NF, false, 4>(k, fused_lds(L, NF, 4, false), s);
   return FE_EUNSUPPORTED;
 }
 

@@ -164,13 +164,14 @@ def test_numeric_is_bitwise_repeatable():
         assert torch.equal(x, y)
 
 
-@pytest.mark.parametrize("prec", ["fp16", "fp64"])
-def test_numeric_halves_equal_numeric(prec):
+@pytest.mark.parametrize("prec,forms", [("fp16", ("mass", "stiffness")), ("fp64", ("mass",))])
+def test_numeric_halves_equal_numeric(prec, forms):
     """FE_NUMERIC_GEOMETRY then FE_NUMERIC_FUSED (twice, the second reusing
     the records) give exactly the values of FE_NUMERIC; the halves are
-    refused where the fused path does not apply."""
+    refused where the fused path does not apply (a coefficient form, or
+    FP64 stiffness, whose tables do not fit on chip)."""
     mesh = mesh_of("c2s")
-    descs = [api.form_desc(3, 4, 8, f, prec) for f in ("mass", "stiffness")]
+    descs = [api.form_desc(3, 4, 8, f, prec) for f in forms]
     mv = api.MeshView.from_numpy(mesh.cell_coords, mesh.dofmap, mesh.n_dofs)
     asm = api.Assembly(mv, descs)
     ref = [v.clone() for v in asm.numeric()]
@@ -188,6 +189,11 @@ def test_numeric_halves_equal_numeric(prec):
     with pytest.raises(L.FeError) as e:
         asm3.numeric(part="fused")
     assert e.value.status == L.FE_EUNSUPPORTED
+    if prec == "fp64":
+        asm_k = api.Assembly(mv, [api.form_desc(3, 4, 8, "stiffness", "fp64")])
+        with pytest.raises(L.FeError) as e:
+            asm_k.numeric(part="geometry")
+        assert e.value.status == L.FE_EUNSUPPORTED
 
 
 def test_degenerate_cell_sets_status_and_nan():
