@@ -447,30 +447,57 @@ __global__ __launch_bounds__(256) void k_ranks(const int32_t *dofmap, int64_t n_
 }
 
 // Ranks in fused-schedule order: for the pair of schedule index p (tile
-// column n of task tile t: p = p0 + pre[t] + n) and lane-order entry e (row tile mt = e/16,
-// K-slot kb = e%16/4, output r = e%4 of the instruction, i.e. local row
-// i = 16 mt + row(kb, r)), the LDS byte offset of the entry inside the
-// owning wave's row buffer: rowoff + rank of dof(K, i) in row dof(K, j), or,
-// for padding rows i >= n_phi, the private slot FUSED_SPAN + 16 kb + n of
-// that lane.  One workgroup per task.
+// column n of task tile t: p = p0 + pre[t] + n) and lane-order entry e
+// (row tile mt = e/16, K-slot kb = e%16/4, output r = e%4 of the instruction,
+// i.e. local row i = 16 mt + row(kb, r)), the LDS byte offset of the entry
+// inside the owning wave's row buffer: rowoff + rank of dof(K, i) in row
+// dof(K, j), or, for padding rows i >= n_phi, the private slot
+// FUSED_SPAN + 16 kb + n of that lane.  Bit 15 marks the first contribution
+// to its entry in the order the fused kernel applies them (tile, then
+// round): that one is stored rather than added, so the row buffer needs no
+// clearing.  One workgroup per task.
+constexpr uint16_t SRANK_FIRST = 0x8000;
+
 __global__ __launch_bounds__(64) void k_slot_ranks(const FusedTask *tasks, const FusedLane *lanes,
                                                    const uint16_t *rank, int n_phi, int sstride,
                                                    bool f64rows, int elt, uint16_t *srank) {
+  __shared__ int owner[FUSED_SPAN];
   const FusedTask tk = tasks[blockIdx.x];
   const int nent = tk.nt * 16 * sstride;
+  for (int u = threadIdx.x; u < FUSED_SPAN; u += 64) owner[u] = 0x7fffffff;
+  __syncthreads();
+  // pass 1: the earliest (tile, round) contributing to every entry
   for (int u = threadIdx.x; u < nent; u += 64) {
     const int slot = u / sstride, e = u - slot * sstride;
     const FusedLane L = lanes[(size_t)tk.t0 * 16 + slot];
     if (L.cell < 0) continue;  // the pairs of a tile fill its first lanes
+    const int mt = e >> 4, kb = (e & 15) >> 2, r = e & 3;
+    const int i = mt * 16 + (f64rows ? kb + 4 * r : 4 * kb + r);
+    if (i < n_phi) {
+      const int pos = L.rowoff + rank[((size_t)L.cell * n_phi + L.j) * n_phi + i];
+      atomicMin(&owner[pos], (slot >> 4) * 16 + (L.round & 15));
+    }
+  }
+  __syncthreads();
+  // pass 2: offsets and first-contribution marks
+  for (int u = threadIdx.x; u < nent; u += 64) {
+    const int slot = u / sstride, e = u - slot * sstride;
+    const FusedLane L = lanes[(size_t)tk.t0 * 16 + slot];
+    if (L.cell < 0) continue;
     const int n = slot & 15, mt = e >> 4, kb = (e & 15) >> 2, r = e & 3;
     const int pair = tk.p0 + ((tk.pre >> (8 * (slot >> 4))) & 0xff) + n;
     const int i = mt * 16 + (f64rows ? kb + 4 * r : 4 * kb + r);
     int off;
-    if (i < n_phi)
-      off = L.rowoff + rank[((size_t)L.cell * n_phi + L.j) * n_phi + i];
-    else
+    bool first;
+    if (i < n_phi) {
+      const int pos = L.rowoff + rank[((size_t)L.cell * n_phi + L.j) * n_phi + i];
+      off = pos;
+      first = owner[pos] == (slot >> 4) * 16 + (L.round & 15);
+    } else {
       off = FUSED_SPAN + 16 * kb + n;
-    srank[(size_t)pair * sstride + e] = (uint16_t)(off * elt);
+      first = true;
+    }
+    srank[(size_t)pair * sstride + e] = (uint16_t)(off * elt) | (first ? SRANK_FIRST : 0);
   }
 }
 

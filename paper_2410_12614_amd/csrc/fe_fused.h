@@ -166,16 +166,17 @@ struct Column {
   int cell, jv, rnd, maxr;
 };
 
-// One tile of one form: LDS offsets of the outputs, H formed per K-slice
-// and contracted on the matrix cores, then added into the row buffer in
-// rounds.  `after_k` runs between the contraction and the scatter (used to
+// TT tiles (1 or 2) of one form: LDS offsets of the outputs, H formed per
+// K-slice and contracted on the matrix cores (the tiles share every B^T
+// fragment read), then added into the row buffer in rounds, tile after
+// tile.  `after_k` runs between the contraction and the scatter (used to
 // issue the next task's loads).
-template <class P, int MT, int NDT, bool STAGE_A, class AfterK>
-__device__ __forceinline__ void fused_tile(const FormLds<P> &S, const FusedForm &F,
-                                           const FormGeo<typename P::real> &cg, int src,
-                                           const Column<typename P::real> &col,
-                                           const uint16_t *rk, int rstride, int lane, int kb,
-                                           typename P::real *rowbuf, AfterK after_k) {
+template <class P, int MT, int NDT, bool STAGE_A, int TT, class AfterK>
+__device__ __forceinline__ void fused_tiles(const FormLds<P> &S, const FusedForm &F,
+                                            const FormGeo<typename P::real> &cg, const int *src,
+                                            const Column<typename P::real> *col,
+                                            const uint16_t *const *rk, int rstride, int lane,
+                                            int kb, typename P::real *rowbuf, AfterK after_k) {
   typedef typename P::real T;
   typedef typename P::hreal HT;
   typedef typename P::acc ACC;
@@ -183,67 +184,81 @@ __device__ __forceinline__ void fused_tile(const FormLds<P> &S, const FusedForm 
   constexpr int KPL = P::KPL;
   const int nqc = F.n_q_pad / P::KSTEP;
 
-  HT Gs[3][3];  // values of the half type when H is formed in half: exact
-  {
-    const HT g0 = (HT)shfl_t(cg.g[0], src);
+  HT Gs[TT][3][3];  // values of the half type when H is formed in half: exact
+  T inv[TT];
+#pragma unroll
+  for (int u = 0; u < TT; ++u) {
+    const HT g0 = (HT)shfl_t(cg.g[0], src[u]);
     HT g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0;
     if constexpr (NDT > 1) {
-      g1 = (HT)shfl_t(cg.g[1], src);
-      g2 = (HT)shfl_t(cg.g[2], src);
-      g3 = (HT)shfl_t(cg.g[3], src);
-      g4 = (HT)shfl_t(cg.g[4], src);
-      g5 = (HT)shfl_t(cg.g[5], src);
+      g1 = (HT)shfl_t(cg.g[1], src[u]);
+      g2 = (HT)shfl_t(cg.g[2], src[u]);
+      g3 = (HT)shfl_t(cg.g[3], src[u]);
+      g4 = (HT)shfl_t(cg.g[4], src[u]);
+      g5 = (HT)shfl_t(cg.g[5], src[u]);
     }
-    Gs[0][0] = g0; Gs[0][1] = g1; Gs[0][2] = g2;
-    Gs[1][0] = g1; Gs[1][1] = g3; Gs[1][2] = g4;
-    Gs[2][0] = g2; Gs[2][1] = g4; Gs[2][2] = g5;
+    Gs[u][0][0] = g0; Gs[u][0][1] = g1; Gs[u][0][2] = g2;
+    Gs[u][1][0] = g1; Gs[u][1][1] = g3; Gs[u][1][2] = g4;
+    Gs[u][2][0] = g2; Gs[u][2][1] = g4; Gs[u][2][2] = g5;
+    inv[u] = shfl_t(cg.inv, src[u]);
   }
-  const T inv = shfl_t(cg.inv, src);
 
   // LDS byte offsets of this lane's outputs inside the row buffer, in lane
   // order (four per row tile: one 8-byte load), loaded before the
   // contraction so that their latency hides behind it.  Padding rows point
   // at the lane's private slot; idle lanes never scatter.
-  int addr[MT][4];
+  int addr[TT][MT][4];
   {
-    const int dummy = FUSED_SPAN * (int)sizeof(T) + lane * (int)sizeof(T);
+    // (bit 15 of an offset marks the first contribution to its entry)
+    const int dummy = (FUSED_SPAN * (int)sizeof(T) + lane * (int)sizeof(T)) | 0x8000;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      // entries past the stored width are padding rows
-      uint2 u = {(unsigned)(dummy | dummy << 16), (unsigned)(dummy | dummy << 16)};
-      if (mt * 16 + 4 * kb < rstride) u = *(const uint2 *)(rk + mt * 16);
-      addr[mt][0] = (int)(u.x & 0xffff);
-      addr[mt][1] = (int)(u.x >> 16);
-      addr[mt][2] = (int)(u.y & 0xffff);
-      addr[mt][3] = (int)(u.y >> 16);
-    }
+    for (int u = 0; u < TT; ++u)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        // entries past the stored width are padding rows
+        uint2 w = {(unsigned)(dummy | dummy << 16), (unsigned)(dummy | dummy << 16)};
+        if (mt * 16 + 4 * kb < rstride) w = *(const uint2 *)(rk[u] + mt * 16);
+        addr[u][mt][0] = (int)(w.x & 0xffff);
+        addr[u][mt][1] = (int)(w.x >> 16);
+        addr[u][mt][2] = (int)(w.y & 0xffff);
+        addr[u][mt][3] = (int)(w.y >> 16);
+      }
   }
 
-  ACC acc[MT];
-  ACC acc2[P::SPLIT ? MT : 1];
+  ACC acc[TT][MT];
+  ACC acc2[P::SPLIT ? TT : 1][P::SPLIT ? MT : 1];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-    acc[mt] = ACC{0, 0, 0, 0};
-    if constexpr (P::SPLIT) acc2[mt] = ACC{0, 0, 0, 0};
-  }
-  // geometry factors of H in both halves of a register (half path)
-  half2_t g2[NDT][NDT];
+  for (int u = 0; u < TT; ++u)
 #pragma unroll
-  for (int s = 0; s < NDT; ++s)
-#pragma unroll
-    for (int t = 0; t < NDT; ++t) {
-      if constexpr (P::H16) g2[s][t] = half2_t{(_Float16)Gs[s][t], (_Float16)Gs[s][t]};
-      else g2[s][t] = half2_t{0, 0};
+    for (int mt = 0; mt < MT; ++mt) {
+      acc[u][mt] = ACC{0, 0, 0, 0};
+      if constexpr (P::SPLIT) acc2[u][mt] = ACC{0, 0, 0, 0};
     }
+  // geometry factors of H in both halves of a register (half path)
+  half2_t g2[TT][NDT][NDT];
+#pragma unroll
+  for (int u = 0; u < TT; ++u)
+#pragma unroll
+    for (int s = 0; s < NDT; ++s)
+#pragma unroll
+      for (int t = 0; t < NDT; ++t) {
+        if constexpr (P::H16) g2[u][s][t] = half2_t{(_Float16)Gs[u][s][t], (_Float16)Gs[u][s][t]};
+        else g2[u][s][t] = half2_t{0, 0};
+      }
   // K = (s, q) walked q-chunk outer, s inner, as in the cell kernel
-  const HT *wcol = S.wt + (size_t)col.jv * S.jstride + kb * KPL;
+  const HT *wcol[TT];
+#pragma unroll
+  for (int u = 0; u < TT; ++u) wcol[u] = S.wt + (size_t)col[u].jv * S.jstride + kb * KPL;
   for (int qc = 0; qc < nqc; ++qc) {
     if constexpr (P::H16) {
       // the chunk's table reads first, then per s its fragments, H and the
       // contraction
-      half8_t wv[NDT];
+      half8_t wv[TT][NDT];
 #pragma unroll
-      for (int t = 0; t < NDT; ++t) wv[t] = *(const half8_t *)(wcol + (qc * NDT + t) * P::KSTEP);
+      for (int u = 0; u < TT; ++u)
+#pragma unroll
+        for (int t = 0; t < NDT; ++t)
+          wv[u][t] = *(const half8_t *)(wcol[u] + (qc * NDT + t) * P::KSTEP);
 #pragma unroll
       for (int s = 0; s < NDT; ++s) {
         FRAG af[MT];
@@ -253,45 +268,50 @@ __device__ __forceinline__ void fused_tile(const FormLds<P> &S, const FusedForm 
           if constexpr (STAGE_A) af[mt] = lds_frag<P>(S.af, fi);
           else af[mt] = P::load(S.af, fi);
         }
-        const half8_t hf = form_h16<NDT>(g2[s], wv);
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) acc[mt] = P::mma(af[mt], hf, acc[mt]);
+        for (int u = 0; u < TT; ++u) {
+          const half8_t hf = form_h16<NDT>(g2[u][s], wv[u]);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) acc[u][mt] = P::mma(af[mt], hf, acc[u][mt]);
+        }
       }
     } else {
-      T wv[NDT][KPL];
+      T wv[TT][NDT][KPL];
 #pragma unroll
-      for (int t = 0; t < NDT; ++t) load_w<T, KPL>(wcol + (qc * NDT + t) * P::KSTEP, wv[t]);
+      for (int u = 0; u < TT; ++u)
+#pragma unroll
+        for (int t = 0; t < NDT; ++t) load_w<T, KPL>(wcol[u] + (qc * NDT + t) * P::KSTEP, wv[u][t]);
 #pragma unroll
       for (int s = 0; s < NDT; ++s) {
-        T h[KPL];
-        form_h<T, NDT, KPL>(Gs[s], wv, h);
-        if constexpr (P::SPLIT) {
-          FRAG hh, hl;
-          P::pack2(h, hh, hl);
+        FRAG af[MT], al[P::SPLIT ? MT : 1];
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt) {
-            const size_t fi = frag_slot(mt, s, qc, MT, NDT) * 64 + lane;
-            FRAG af, al;
-            if constexpr (STAGE_A) {
-              af = lds_frag<P>(S.af, fi);
-              al = lds_frag<P>(S.afl, fi);
-            } else {
-              af = P::load(S.af, fi);
-              al = P::load(S.afl, fi);
-            }
-            acc[mt] = P::mma(af, hh, acc[mt]);
-            acc2[mt] = P::mma(af, hl, acc2[mt]);
-            acc2[mt] = P::mma(al, hh, acc2[mt]);
+        for (int mt = 0; mt < MT; ++mt) {
+          const size_t fi = frag_slot(mt, s, qc, MT, NDT) * 64 + lane;
+          if constexpr (STAGE_A) {
+            af[mt] = lds_frag<P>(S.af, fi);
+            if constexpr (P::SPLIT) al[mt] = lds_frag<P>(S.afl, fi);
+          } else {
+            af[mt] = P::load(S.af, fi);
+            if constexpr (P::SPLIT) al[mt] = P::load(S.afl, fi);
           }
-        } else {
-          const FRAG hf = P::pack(h);
+        }
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt) {
-            const size_t fi = frag_slot(mt, s, qc, MT, NDT) * 64 + lane;
-            FRAG af;
-            if constexpr (STAGE_A) af = lds_frag<P>(S.af, fi);
-            else af = P::load(S.af, fi);
-            acc[mt] = P::mma(af, hf, acc[mt]);
+        for (int u = 0; u < TT; ++u) {
+          T h[KPL];
+          form_h<T, NDT, KPL>(Gs[u][s], wv[u], h);
+          if constexpr (P::SPLIT) {
+            FRAG hh, hl;
+            P::pack2(h, hh, hl);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+              acc[u][mt] = P::mma(af[mt], hh, acc[u][mt]);
+              acc2[u][mt] = P::mma(af[mt], hl, acc2[u][mt]);
+              acc2[u][mt] = P::mma(al[mt], hh, acc2[u][mt]);
+            }
+          } else {
+            const FRAG hf = P::pack(h);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[u][mt] = P::mma(af[mt], hf, acc[u][mt]);
           }
         }
       }
@@ -300,37 +320,46 @@ __device__ __forceinline__ void fused_tile(const FormLds<P> &S, const FusedForm 
 
   after_k();
 
-  // scatter into the owned rows, one round per repeated row; within a
-  // round every lane adds to a different entry (padding rows update the
-  // lane's private slot instead: no branch per entry)
-  T val[MT][4];
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      T v = acc[mt][q];
-      if constexpr (P::SPLIT) v += acc2[mt][q] * (T)(1.0 / 2048.0);
-      val[mt][q] = v * inv;
-    }
+  // scatter into the owned rows, tile after tile, one round per repeated
+  // row; within a round every lane adds to a different entry (padding rows
+  // update the lane's private slot instead: no branch per entry)
   unsigned char *rb = (unsigned char *)rowbuf;
-  for (int r = 0; r <= col.maxr; ++r) {
-    if (col.rnd == r) {
-      // read all, then write all: a lane's entries are distinct and the
-      // lanes of one round hold distinct rows
-      T old[MT][4];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
+  for (int u = 0; u < TT; ++u) {
+    T val[MT][4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) old[mt][q] = *(const T *)(rb + addr[mt][q]);
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
+      for (int q = 0; q < 4; ++q) {
+        T v = acc[u][mt][q];
+        if constexpr (P::SPLIT) v += acc2[u][mt][q] * (T)(1.0 / 2048.0);
+        val[mt][q] = v * inv[u];
+      }
+    for (int r = 0; r <= col[u].maxr; ++r) {
+      if (col[u].rnd == r) {
+        // read all, then write all: a lane's entries are distinct and the
+        // lanes of one round hold distinct rows.  The first contribution to
+        // an entry is stored as it is (0 + v = v exactly: v is never -0), so
+        // only the later ones read.
+        T old[MT][4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) *(T *)(rb + addr[mt][q]) = old[mt][q] + val[mt][q];
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            old[mt][q] = 0;
+            if (!(addr[u][mt][q] & 0x8000)) old[mt][q] = *(const T *)(rb + addr[u][mt][q]);
+          }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            *(T *)(rb + (addr[u][mt][q] & 0x7fff)) = old[mt][q] + val[mt][q];
+      }
     }
   }
 }
 
-template <class P, int MT, int NDT0, int NDT1, int NF, bool STAGE_A, int NW>
+template <class P, int MT, int NDT0, int NDT1, int NF, bool STAGE_A, int NW, int TT>
 __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
   typedef typename P::real T;
   typedef FormGeo<T> GEO;
@@ -380,25 +409,28 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
 
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      {
-        constexpr int E4 = 16 / sizeof(T);  // elements per 16-byte store
-        const int n16 = (span + E4 - 1) / E4;
-        for (int t = lane; t < n16; t += 64) ((uint4 *)rowbuf)[t] = uint4{0, 0, 0, 0};
-      }
-      for (int tl = 0; tl < nt; ++tl) {
-        // this lane's column: slot 16 tl + n of the task
-        const int src = 16 * tl + n;
-        Column<T> col;
-        col.cell = __shfl(cw0, src);
-        const int w1 = __shfl(cw1, src);
-        col.jv = (w1 >> 16) & 0xff;
-        col.rnd = (w1 >> 24) & 0xf;
-        // the tile's last round, the same in every lane record of the tile
-        col.maxr = __builtin_amdgcn_readfirstlane((int)((unsigned)w1 >> 28));
-        const int pair = col.cell < 0 ? 0 : p0 + ((pre >> (8 * tl)) & 0xff) + n;
-        const uint16_t *rk = a.srank + (size_t)pair * a.rstride + 4 * kb;
+      for (int tl = 0; tl < nt;) {
+        // tiles processed together: two while at least two remain
+        const int tt = (TT == 2 && tl + 1 < nt) ? 2 : 1;
+        int src[2];
+        Column<T> col[2];
+        const uint16_t *rk[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int t = tl + (u < tt ? u : 0);
+          // this lane's column: slot 16 t + n of the task
+          src[u] = 16 * t + n;
+          col[u].cell = __shfl(cw0, src[u]);
+          const int w1 = __shfl(cw1, src[u]);
+          col[u].jv = (w1 >> 16) & 0xff;
+          col[u].rnd = (w1 >> 24) & 0xf;
+          // the tile's last round, the same in every lane record of the tile
+          col[u].maxr = __builtin_amdgcn_readfirstlane((int)((unsigned)w1 >> 28));
+          const int pair = col[u].cell < 0 ? 0 : p0 + ((pre >> (8 * t)) & 0xff) + n;
+          rk[u] = a.srank + (size_t)pair * a.rstride + 4 * kb;
+        }
         // the next task's lane records and then its factors, behind the
-        // first tile's contraction
+        // first tiles' contraction
         if (f == 0 && tl == 0 && has_next) {
           lw0 = -1;
           lw1 = 0;
@@ -408,7 +440,7 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
             lw1 = lane_word1(l);
           }
         }
-        // (the factors are held only from the last form's first tile on)
+        // (the factors are held only from the last form's first tiles on)
         auto after_k = [&]() {
           if (f == NF - 1 && tl == 0 && has_next) {
 #pragma unroll
@@ -418,12 +450,24 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
               for (int e = 0; e < NF; ++e) gg[e] = ((const GEO *)a.f[e].geo)[lw0];
           }
         };
-        if (f == 0)
-          fused_tile<P, MT, NDT0, STAGE_A>(S0, a.f[0], cg[0], src, col, rk, a.rstride, lane, kb,
-                                            rowbuf, after_k);
-        else if constexpr (NF == 2)
-          fused_tile<P, MT, NDT1, STAGE_A>(S1, a.f[1], cg[NF - 1], src, col, rk, a.rstride, lane,
-                                            kb, rowbuf, after_k);
+        if (tt == 2) {
+          if constexpr (TT == 2) {
+            if (f == 0)
+              fused_tiles<P, MT, NDT0, STAGE_A, 2>(S0, a.f[0], cg[0], src, col, rk, a.rstride,
+                                                   lane, kb, rowbuf, after_k);
+            else if constexpr (NF == 2)
+              fused_tiles<P, MT, NDT1, STAGE_A, 2>(S1, a.f[1], cg[NF - 1], src, col, rk,
+                                                   a.rstride, lane, kb, rowbuf, after_k);
+          }
+        } else {
+          if (f == 0)
+            fused_tiles<P, MT, NDT0, STAGE_A, 1>(S0, a.f[0], cg[0], src, col, rk, a.rstride, lane,
+                                                 kb, rowbuf, after_k);
+          else if constexpr (NF == 2)
+            fused_tiles<P, MT, NDT1, STAGE_A, 1>(S1, a.f[1], cg[NF - 1], src, col, rk, a.rstride,
+                                                 lane, kb, rowbuf, after_k);
+        }
+        tl += tt;
       }
       T *V = (T *)a.f[f].values + base;
       for (int t = lane; t < span; t += 64) V[t] = rowbuf[t];
@@ -432,9 +476,9 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
   }
 }
 
-template <class P, int MT, int NDT0, int NDT1, int NF, bool SA, int NW>
+template <class P, int MT, int NDT0, int NDT1, int NF, bool SA, int NW, int TT>
 static fe_status launch_fused_one(const FusedArgs &k, size_t smem, hipStream_t s) {
-  auto kern = fused_kernel<P, MT, NDT0, NDT1, NF, SA, NW>;
+  auto kern = fused_kernel<P, MT, NDT0, NDT1, NF, SA, NW, TT>;
   if (smem > 65536 && hipFuncSetAttribute((const void *)kern,
                                           hipFuncAttributeMaxDynamicSharedMemorySize,
                                           (int)smem) != hipSuccess)
@@ -454,14 +498,16 @@ static fe_status launch_fused_one(const FusedArgs &k, size_t smem, hipStream_t s
 
 template <class P, int MT, int NDT0, int NDT1, int NF>
 static fe_status launch_fused_nw(const FusedArgs &k, const FormLayout *const *L, hipStream_t s) {
-  // the most waves per workgroup that fit with the B^T fragments staged
-  // (at least 8: see fused_eligible)
+  // one tile per step with the most waves per workgroup that fit with the
+  // fragments staged (at least 8: see fused_eligible); measured on the
+  // benchmark workload, 16 waves with one tile per step beat 12 waves with
+  // two tiles sharing each fragment read
   if (fused_lds(L, NF, 16, true) <= FUSED_LDS_BUDGET)
-    return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 16>(k, fused_lds(L, NF, 16, true), s);
+    return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 16, 1>(k, fused_lds(L, NF, 16, true), s);
   if (fused_lds(L, NF, 12, true) <= FUSED_LDS_BUDGET)
-    return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 12>(k, fused_lds(L, NF, 12, true), s);
+    return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 12, 1>(k, fused_lds(L, NF, 12, true), s);
   if (fused_lds(L, NF, 8, true) <= FUSED_LDS_BUDGET)
-    return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 8>(k, fused_lds(L, NF, 8, true), s);
+    return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 8, 1>(k, fused_lds(L, NF, 8, true), s);
   return FE_EUNSUPPORTED;
 }
 
