@@ -322,3 +322,40 @@ def test_full_size_c2_sampled_rows(prec):
     rows = list(rng.choice(mesh.n_dofs, 16, replace=False))
     rows += list(np.unique(mesh.dofmap[mesh.flattened[:4]].ravel())[:8])
     _sampled_rows_check(mesh, ("mass", "stiffness"), prec, 8, None, rows, asm, vals)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "fp64"])
+def test_full_size_c3_sampled_rows(prec):
+    """The weighted-stiffness workload at full size (196,608 P6 cells, 512
+    quadrature points, FE coefficient): pattern size and sortedness, and 12
+    seeded rows against the oracle computed row by row (only those rows are
+    copied back)."""
+    mesh = config_mesh("c3")
+    say(f"[full c3] {prec}")
+    desc = api.form_desc(3, 6, 14, "stiffness", prec, has_coeff=True)
+    mv = api.MeshView.from_numpy(mesh.cell_coords, mesh.dofmap, mesh.n_dofs, mesh.coeff)
+    asm = api.Assembly(mv, [desc])
+    (vals,) = asm.numeric()
+    torch.cuda.synchronize()
+    assert all(s == 0 for s in asm.status())
+    assert asm.nnz == 1094564353
+    rp_d = asm.row_ptr
+    assert int(rp_d[0]) == 0 and bool((rp_d[1:] > rp_d[:-1]).all())
+    rp = rp_d.cpu().numpy()
+    rng = np.random.default_rng(7)
+    rows = [int(g) for g in rng.choice(mesh.n_dofs, 12, replace=False)]
+
+    picked = []
+    for g in rows:
+        seg = asm.col_idx[rp[g]:rp[g + 1]]
+        assert bool((seg[1:] > seg[:-1]).all())
+        picked.append(vals[rp[g]:rp[g + 1]].double().cpu().numpy())
+    full = {g: v for g, v in zip(rows, picked)}
+
+    class V:      # CSR values view that serves only the sampled rows
+        def __getitem__(self, sl):
+            g = int(np.searchsorted(rp, sl.start, side="right") - 1)
+            assert rp[g] == sl.start and rp[g + 1] == sl.stop
+            return full[g]
+
+    _sampled_rows_check(mesh, ("stiffness",), prec, 14, mesh.coeff, rows, asm, [V()])
