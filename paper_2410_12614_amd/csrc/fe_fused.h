@@ -31,6 +31,8 @@
 // and the schedule is read from HBM once.
 #pragma once
 
+#include <type_traits>
+
 #include "fe_cell_kernel.h"
 
 namespace fe {
@@ -166,26 +168,14 @@ struct Column {
   int cell, jv, rnd, maxr;
 };
 
-// TT tiles (1 or 2) of one form: LDS offsets of the outputs, H formed per
-// K-slice and contracted on the matrix cores (the tiles share every B^T
-// fragment read), then added into the row buffer in rounds, tile after
-// tile.  `after_k` runs between the contraction and the scatter (used to
-// issue the next task's loads).
-template <class P, int MT, int NDT, bool STAGE_A, int TT, class AfterK>
-__device__ __forceinline__ void fused_tiles(const FormLds<P> &S, const FusedForm &F,
-                                            const FormGeo<typename P::real> &cg, const int *src,
-                                            const Column<typename P::real> *col,
-                                            const uint16_t *const *rk, int rstride, int lane,
-                                            int kb, typename P::real *rowbuf, AfterK after_k) {
-  typedef typename P::real T;
+// Factors of H of TT tile columns (slots src[u]), from the lanes holding
+// the task's records: the scaled geometry tensor (of the half type when H is
+// formed in half: exact) and the exact inverse scale.
+template <class P, int NDT, int TT>
+__device__ __forceinline__ void tile_factors(const FormGeo<typename P::real> &cg, const int *src,
+                                             typename P::hreal (&Gs)[TT][3][3],
+                                             typename P::real (&inv)[TT]) {
   typedef typename P::hreal HT;
-  typedef typename P::acc ACC;
-  typedef typename P::frag FRAG;
-  constexpr int KPL = P::KPL;
-  const int nqc = F.n_q_pad / P::KSTEP;
-
-  HT Gs[TT][3][3];  // values of the half type when H is formed in half: exact
-  T inv[TT];
 #pragma unroll
   for (int u = 0; u < TT; ++u) {
     const HT g0 = (HT)shfl_t(cg.g[0], src[u]);
@@ -202,31 +192,46 @@ __device__ __forceinline__ void fused_tiles(const FormLds<P> &S, const FusedForm
     Gs[u][2][0] = g2; Gs[u][2][1] = g4; Gs[u][2][2] = g5;
     inv[u] = shfl_t(cg.inv, src[u]);
   }
+}
 
-  // LDS byte offsets of this lane's outputs inside the row buffer, in lane
-  // order (four per row tile: one 8-byte load), loaded before the
-  // contraction so that their latency hides behind it.  Padding rows point
-  // at the lane's private slot; idle lanes never scatter.
-  int addr[TT][MT][4];
-  {
-    // (bit 15 of an offset marks the first contribution to its entry)
-    const int dummy = (FUSED_SPAN * (int)sizeof(T) + lane * (int)sizeof(T)) | 0x8000;
+// LDS byte offsets (in units of the row-buffer element) of this lane's
+// outputs inside the row buffer, in lane order (four per row tile: one
+// 8-byte load).  Padding rows point at the lane's private slot; bit 15 marks
+// the first contribution to an entry.
+template <class T, int MT, int TT>
+__device__ __forceinline__ void tile_addr(const uint16_t *const *rk, int rstride, int lane,
+                                          int kb, int (&addr)[TT][MT][4]) {
+  const int dummy = (FUSED_SPAN * (int)sizeof(T) + lane * (int)sizeof(T)) | 0x8000;
 #pragma unroll
-    for (int u = 0; u < TT; ++u)
+  for (int u = 0; u < TT; ++u)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        // entries past the stored width are padding rows
-        uint2 w = {(unsigned)(dummy | dummy << 16), (unsigned)(dummy | dummy << 16)};
-        if (mt * 16 + 4 * kb < rstride) w = *(const uint2 *)(rk[u] + mt * 16);
-        addr[u][mt][0] = (int)(w.x & 0xffff);
-        addr[u][mt][1] = (int)(w.x >> 16);
-        addr[u][mt][2] = (int)(w.y & 0xffff);
-        addr[u][mt][3] = (int)(w.y >> 16);
-      }
-  }
+    for (int mt = 0; mt < MT; ++mt) {
+      // entries past the stored width are padding rows
+      uint2 w = {(unsigned)(dummy | dummy << 16), (unsigned)(dummy | dummy << 16)};
+      if (mt * 16 + 4 * kb < rstride) w = *(const uint2 *)(rk[u] + mt * 16);
+      addr[u][mt][0] = (int)(w.x & 0xffff);
+      addr[u][mt][1] = (int)(w.x >> 16);
+      addr[u][mt][2] = (int)(w.y & 0xffff);
+      addr[u][mt][3] = (int)(w.y >> 16);
+    }
+}
 
-  ACC acc[TT][MT];
-  ACC acc2[P::SPLIT ? TT : 1][P::SPLIT ? MT : 1];
+// Contraction of TT tiles of one form: H formed per K-slice in registers
+// from the staged weighted table (rows jv[u]), against the staged B^T
+// fragments (every fragment read serves all TT tiles).  K = (s, q) is
+// walked q-chunk outer, s inner, as in the cell kernel.
+template <class P, int MT, int NDT, bool STAGE_A, int TT>
+__device__ __forceinline__ void tile_contract(const FormLds<P> &S, const FusedForm &F,
+                                              const typename P::hreal (&Gs)[TT][3][3],
+                                              const int *jv, int lane, int kb,
+                                              typename P::acc (&acc)[TT][MT],
+                                              typename P::acc (&acc2)[P::SPLIT ? TT : 1][P::SPLIT ? MT : 1]) {
+  typedef typename P::real T;
+  typedef typename P::hreal HT;
+  typedef typename P::acc ACC;
+  typedef typename P::frag FRAG;
+  constexpr int KPL = P::KPL;
+  const int nqc = F.n_q_pad / P::KSTEP;
 #pragma unroll
   for (int u = 0; u < TT; ++u)
 #pragma unroll
@@ -245,10 +250,9 @@ __device__ __forceinline__ void fused_tiles(const FormLds<P> &S, const FusedForm
         if constexpr (P::H16) g2[u][s][t] = half2_t{(_Float16)Gs[u][s][t], (_Float16)Gs[u][s][t]};
         else g2[u][s][t] = half2_t{0, 0};
       }
-  // K = (s, q) walked q-chunk outer, s inner, as in the cell kernel
   const HT *wcol[TT];
 #pragma unroll
-  for (int u = 0; u < TT; ++u) wcol[u] = S.wt + (size_t)col[u].jv * S.jstride + kb * KPL;
+  for (int u = 0; u < TT; ++u) wcol[u] = S.wt + (size_t)jv[u] * S.jstride + kb * KPL;
   for (int qc = 0; qc < nqc; ++qc) {
     if constexpr (P::H16) {
       // the chunk's table reads first, then per s its fragments, H and the
@@ -317,24 +321,58 @@ __device__ __forceinline__ void fused_tiles(const FormLds<P> &S, const FusedForm
       }
     }
   }
+}
+
+// The tile's results of one accumulator set, unscaled: val = acc (+ 2^-11
+// acc2 for the split pair) times the exact inverse scale.
+template <class P, int MT, int TT>
+__device__ __forceinline__ void tile_values(const typename P::acc (&acc)[TT][MT],
+                                            const typename P::acc (&acc2)[P::SPLIT ? TT : 1][P::SPLIT ? MT : 1],
+                                            int u, typename P::real inv,
+                                            typename P::real (&val)[MT][4]) {
+  typedef typename P::real T;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      T v = acc[u][mt][q];
+      if constexpr (P::SPLIT) v += acc2[u][mt][q] * (T)(1.0 / 2048.0);
+      val[mt][q] = v * inv;
+    }
+}
+
+// TT tiles (1 or 2) of one form: factors, output offsets, contraction, then
+// the scatter into the row buffer, tile after tile, one round per repeated
+// row; within a round every lane adds to a different entry (padding rows
+// update the lane's private slot instead: no branch per entry).  `after_k`
+// runs between the contraction and the scatter (used to issue the next
+// task's loads).
+template <class P, int MT, int NDT, bool STAGE_A, int TT, class AfterK>
+__device__ __forceinline__ void fused_tiles(const FormLds<P> &S, const FusedForm &F,
+                                            const FormGeo<typename P::real> &cg, const int *src,
+                                            const Column<typename P::real> *col,
+                                            const uint16_t *const *rk, int rstride, int lane,
+                                            int kb, typename P::real *rowbuf, AfterK after_k) {
+  typedef typename P::real T;
+  typename P::hreal Gs[TT][3][3];
+  T inv[TT];
+  tile_factors<P, NDT, TT>(cg, src, Gs, inv);
+  int addr[TT][MT][4];
+  tile_addr<T, MT, TT>(rk, rstride, lane, kb, addr);
+  int jv[TT];
+#pragma unroll
+  for (int u = 0; u < TT; ++u) jv[u] = col[u].jv;
+  typename P::acc acc[TT][MT];
+  typename P::acc acc2[P::SPLIT ? TT : 1][P::SPLIT ? MT : 1];
+  tile_contract<P, MT, NDT, STAGE_A, TT>(S, F, Gs, jv, lane, kb, acc, acc2);
 
   after_k();
 
-  // scatter into the owned rows, tile after tile, one round per repeated
-  // row; within a round every lane adds to a different entry (padding rows
-  // update the lane's private slot instead: no branch per entry)
   unsigned char *rb = (unsigned char *)rowbuf;
 #pragma unroll
   for (int u = 0; u < TT; ++u) {
     T val[MT][4];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        T v = acc[u][mt][q];
-        if constexpr (P::SPLIT) v += acc2[u][mt][q] * (T)(1.0 / 2048.0);
-        val[mt][q] = v * inv[u];
-      }
+    tile_values<P, MT, TT>(acc, acc2, u, inv[u], val);
     for (int r = 0; r <= col[u].maxr; ++r) {
       if (col[u].rnd == r) {
         // read all, then write all: a lane's entries are distinct and the
@@ -359,10 +397,76 @@ __device__ __forceinline__ void fused_tiles(const FormLds<P> &S, const FusedForm
   }
 }
 
-template <class P, int MT, int NDT0, int NDT1, int NF, bool STAGE_A, int NW, int TT>
+// One tile of two forms sharing one row buffer of value pairs (form 0,
+// form 1) per entry: both contractions, then one scatter of the pairs, so
+// the scatter's LDS operations serve both forms.  The offsets of the
+// schedule-order ranks count single values and are doubled here.
+template <class P, int MT, int NDT0, int NDT1, bool STAGE_A, class AfterK>
+__device__ __forceinline__ void fused_tile_pair(const FormLds<P> &S0, const FormLds<P> &S1,
+                                                const FusedForm &F0, const FusedForm &F1,
+                                                const FormGeo<typename P::real> &cg0,
+                                                const FormGeo<typename P::real> &cg1, int src,
+                                                const Column<typename P::real> &col,
+                                                const uint16_t *rk, int rstride, int lane, int kb,
+                                                typename P::real *rowbuf, AfterK after_k) {
+  typedef typename P::real T;
+  typedef typename P::acc ACC;
+  int addr[1][MT][4];
+  tile_addr<T, MT, 1>(&rk, rstride, lane, kb, addr);
+  const int jv[1] = {col.jv};
+  T val0[MT][4], val1[MT][4];
+  {
+    typename P::hreal Gs[1][3][3];
+    T inv[1];
+    tile_factors<P, NDT0, 1>(cg0, &src, Gs, inv);
+    ACC acc[1][MT];
+    ACC acc2[P::SPLIT ? 1 : 1][P::SPLIT ? MT : 1];
+    tile_contract<P, MT, NDT0, STAGE_A, 1>(S0, F0, Gs, jv, lane, kb, acc, acc2);
+    tile_values<P, MT, 1>(acc, acc2, 0, inv[0], val0);
+  }
+  {
+    typename P::hreal Gs[1][3][3];
+    T inv[1];
+    tile_factors<P, NDT1, 1>(cg1, &src, Gs, inv);
+    ACC acc[1][MT];
+    ACC acc2[P::SPLIT ? 1 : 1][P::SPLIT ? MT : 1];
+    tile_contract<P, MT, NDT1, STAGE_A, 1>(S1, F1, Gs, jv, lane, kb, acc, acc2);
+    tile_values<P, MT, 1>(acc, acc2, 0, inv[0], val1);
+  }
+
+  after_k();
+
+  typedef typename std::conditional<sizeof(T) == 4, float2, double2>::type T2;
+  unsigned char *rb = (unsigned char *)rowbuf;
+  for (int r = 0; r <= col.maxr; ++r) {
+    if (col.rnd == r) {
+      T2 old[MT][4];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          old[mt][q] = T2{0, 0};
+          if (!(addr[0][mt][q] & 0x8000))
+            old[mt][q] = *(const T2 *)(rb + 2 * addr[0][mt][q]);
+        }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          *(T2 *)(rb + 2 * (addr[0][mt][q] & 0x7fff)) =
+              T2{old[mt][q].x + val0[mt][q], old[mt][q].y + val1[mt][q]};
+    }
+  }
+}
+
+// PR: the two forms share one row buffer of value pairs and one pass over
+// each task's tiles (fused_tile_pair); else each form runs its own pass over
+// the tiles with its own row buffer contents.
+template <class P, int MT, int NDT0, int NDT1, int NF, bool STAGE_A, int NW, int TT, bool PR>
 __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
   typedef typename P::real T;
   typedef FormGeo<T> GEO;
+  static_assert(!PR || (NF == 2 && TT == 1), "paired rows need two forms, one tile per step");
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int n = lane & 15, kb = lane >> 4;
@@ -371,7 +475,7 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
   FormLds<P> S0, S1;
   unsigned char *end = stage_form<P, MT, NDT0, STAGE_A, NW>(smem, a.f[0], nphi, tid, S0);
   if constexpr (NF == 2) end = stage_form<P, MT, NDT1, STAGE_A, NW>(end, a.f[1], nphi, tid, S1);
-  T *rowbuf = (T *)end + (size_t)wave * (FUSED_SPAN + 64);
+  T *rowbuf = (T *)end + (size_t)wave * (FUSED_SPAN + 64) * (PR ? 2 : 1);
   __syncthreads();
 
   const int ntasks = a.ntasks;
@@ -408,7 +512,7 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
     if (has_next) tk = a.tasks[next];
 
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
+    for (int f = 0; f < (PR ? 1 : NF); ++f) {
       for (int tl = 0; tl < nt;) {
         // tiles processed together: two while at least two remain
         const int tt = (TT == 2 && tl + 1 < nt) ? 2 : 1;
@@ -442,7 +546,7 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
         }
         // (the factors are held only from the last form's first tiles on)
         auto after_k = [&]() {
-          if (f == NF - 1 && tl == 0 && has_next) {
+          if ((PR || f == NF - 1) && tl == 0 && has_next) {
 #pragma unroll
             for (int e = 0; e < NF; ++e) gg[e] = GEO{};
             if (lw0 >= 0)
@@ -450,7 +554,11 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
               for (int e = 0; e < NF; ++e) gg[e] = ((const GEO *)a.f[e].geo)[lw0];
           }
         };
-        if (tt == 2) {
+        if constexpr (PR) {
+          fused_tile_pair<P, MT, NDT0, NDT1, STAGE_A>(S0, S1, a.f[0], a.f[1], cg[0], cg[NF - 1],
+                                                      src[0], col[0], rk[0], a.rstride, lane, kb,
+                                                      rowbuf, after_k);
+        } else if (tt == 2) {
           if constexpr (TT == 2) {
             if (f == 0)
               fused_tiles<P, MT, NDT0, STAGE_A, 2>(S0, a.f[0], cg[0], src, col, rk, a.rstride,
@@ -469,16 +577,27 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
         }
         tl += tt;
       }
-      T *V = (T *)a.f[f].values + base;
-      for (int t = lane; t < span; t += 64) V[t] = rowbuf[t];
+      if constexpr (PR) {
+        typedef typename std::conditional<sizeof(T) == 4, float2, double2>::type T2;
+        T *V0 = (T *)a.f[0].values + base;
+        T *V1 = (T *)a.f[NF - 1].values + base;
+        for (int t = lane; t < span; t += 64) {
+          const T2 v = ((const T2 *)rowbuf)[t];
+          V0[t] = v.x;
+          V1[t] = v.y;
+        }
+      } else {
+        T *V = (T *)a.f[f].values + base;
+        for (int t = lane; t < span; t += 64) V[t] = rowbuf[t];
+      }
     }
     task = next;
   }
 }
 
-template <class P, int MT, int NDT0, int NDT1, int NF, bool SA, int NW, int TT>
+template <class P, int MT, int NDT0, int NDT1, int NF, bool SA, int NW, int TT, bool PR = false>
 static fe_status launch_fused_one(const FusedArgs &k, size_t smem, hipStream_t s) {
-  auto kern = fused_kernel<P, MT, NDT0, NDT1, NF, SA, NW, TT>;
+  auto kern = fused_kernel<P, MT, NDT0, NDT1, NF, SA, NW, TT, PR>;
   if (smem > 65536 && hipFuncSetAttribute((const void *)kern,
                                           hipFuncAttributeMaxDynamicSharedMemorySize,
                                           (int)smem) != hipSuccess)
@@ -498,10 +617,17 @@ static fe_status launch_fused_one(const FusedArgs &k, size_t smem, hipStream_t s
 
 template <class P, int MT, int NDT0, int NDT1, int NF>
 static fe_status launch_fused_nw(const FusedArgs &k, const FormLayout *const *L, hipStream_t s) {
-  // one tile per step with the most waves per workgroup that fit with the
-  // fragments staged (at least 8: see fused_eligible); measured on the
-  // benchmark workload, 16 waves with one tile per step beat 12 waves with
-  // two tiles sharing each fragment read
+  // A pair shares one row buffer of value pairs (one scatter for both
+  // forms) when that fits with 8 waves.  Otherwise one tile per step with
+  // the most waves per workgroup that fit with the fragments staged (at
+  // least 8: see fused_eligible); measured on the benchmark workload, 16
+  // waves with one tile per step beat 12 waves with two tiles sharing each
+  // fragment read.
+  if constexpr (NF == 2) {
+    const size_t pr = fused_lds(L, NF, 8, true) + (size_t)8 * (FUSED_SPAN + 64) * sizeof(typename P::real);
+    if (pr <= FUSED_LDS_BUDGET)
+      return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 8, 1, true>(k, pr, s);
+  }
   if (fused_lds(L, NF, 16, true) <= FUSED_LDS_BUDGET)
     return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 16, 1>(k, fused_lds(L, NF, 16, true), s);
   if (fused_lds(L, NF, 12, true) <= FUSED_LDS_BUDGET)
