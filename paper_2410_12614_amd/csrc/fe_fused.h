@@ -397,64 +397,72 @@ __device__ __forceinline__ void fused_tiles(const FormLds<P> &S, const FusedForm
   }
 }
 
-// One tile of two forms sharing one row buffer of value pairs (form 0,
-// form 1) per entry: both contractions, then one scatter of the pairs, so
-// the scatter's LDS operations serve both forms.  The offsets of the
+// TT tiles (1 or 2) of two forms sharing one row buffer of value pairs
+// (form 0, form 1) per entry: all contractions (the tiles share every
+// fragment read), then, tile after tile, one scatter of the pairs, so the
+// scatter's LDS operations serve both forms.  The offsets of the
 // schedule-order ranks count single values and are doubled here.
-template <class P, int MT, int NDT0, int NDT1, bool STAGE_A, class AfterK>
+template <class P, int MT, int NDT0, int NDT1, bool STAGE_A, int TT, class AfterK>
 __device__ __forceinline__ void fused_tile_pair(const FormLds<P> &S0, const FormLds<P> &S1,
                                                 const FusedForm &F0, const FusedForm &F1,
                                                 const FormGeo<typename P::real> &cg0,
-                                                const FormGeo<typename P::real> &cg1, int src,
-                                                const Column<typename P::real> &col,
-                                                const uint16_t *rk, int rstride, int lane, int kb,
-                                                typename P::real *rowbuf, AfterK after_k) {
+                                                const FormGeo<typename P::real> &cg1,
+                                                const int *src, const Column<typename P::real> *col,
+                                                const uint16_t *const *rk, int rstride, int lane,
+                                                int kb, typename P::real *rowbuf, AfterK after_k) {
   typedef typename P::real T;
   typedef typename P::acc ACC;
-  int addr[1][MT][4];
-  tile_addr<T, MT, 1>(&rk, rstride, lane, kb, addr);
-  const int jv[1] = {col.jv};
-  T val0[MT][4], val1[MT][4];
+  int addr[TT][MT][4];
+  tile_addr<T, MT, TT>(rk, rstride, lane, kb, addr);
+  int jv[TT];
+#pragma unroll
+  for (int u = 0; u < TT; ++u) jv[u] = col[u].jv;
+  T val0[TT][MT][4], val1[TT][MT][4];
   {
-    typename P::hreal Gs[1][3][3];
-    T inv[1];
-    tile_factors<P, NDT0, 1>(cg0, &src, Gs, inv);
-    ACC acc[1][MT];
-    ACC acc2[P::SPLIT ? 1 : 1][P::SPLIT ? MT : 1];
-    tile_contract<P, MT, NDT0, STAGE_A, 1>(S0, F0, Gs, jv, lane, kb, acc, acc2);
-    tile_values<P, MT, 1>(acc, acc2, 0, inv[0], val0);
+    typename P::hreal Gs[TT][3][3];
+    T inv[TT];
+    tile_factors<P, NDT0, TT>(cg0, src, Gs, inv);
+    ACC acc[TT][MT];
+    ACC acc2[P::SPLIT ? TT : 1][P::SPLIT ? MT : 1];
+    tile_contract<P, MT, NDT0, STAGE_A, TT>(S0, F0, Gs, jv, lane, kb, acc, acc2);
+#pragma unroll
+    for (int u = 0; u < TT; ++u) tile_values<P, MT, TT>(acc, acc2, u, inv[u], val0[u]);
   }
   {
-    typename P::hreal Gs[1][3][3];
-    T inv[1];
-    tile_factors<P, NDT1, 1>(cg1, &src, Gs, inv);
-    ACC acc[1][MT];
-    ACC acc2[P::SPLIT ? 1 : 1][P::SPLIT ? MT : 1];
-    tile_contract<P, MT, NDT1, STAGE_A, 1>(S1, F1, Gs, jv, lane, kb, acc, acc2);
-    tile_values<P, MT, 1>(acc, acc2, 0, inv[0], val1);
+    typename P::hreal Gs[TT][3][3];
+    T inv[TT];
+    tile_factors<P, NDT1, TT>(cg1, src, Gs, inv);
+    ACC acc[TT][MT];
+    ACC acc2[P::SPLIT ? TT : 1][P::SPLIT ? MT : 1];
+    tile_contract<P, MT, NDT1, STAGE_A, TT>(S1, F1, Gs, jv, lane, kb, acc, acc2);
+#pragma unroll
+    for (int u = 0; u < TT; ++u) tile_values<P, MT, TT>(acc, acc2, u, inv[u], val1[u]);
   }
 
   after_k();
 
   typedef typename std::conditional<sizeof(T) == 4, float2, double2>::type T2;
   unsigned char *rb = (unsigned char *)rowbuf;
-  for (int r = 0; r <= col.maxr; ++r) {
-    if (col.rnd == r) {
-      T2 old[MT][4];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
+  for (int u = 0; u < TT; ++u) {
+    for (int r = 0; r <= col[u].maxr; ++r) {
+      if (col[u].rnd == r) {
+        T2 old[MT][4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          old[mt][q] = T2{0, 0};
-          if (!(addr[0][mt][q] & 0x8000))
-            old[mt][q] = *(const T2 *)(rb + 2 * addr[0][mt][q]);
-        }
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
+          for (int q = 0; q < 4; ++q) {
+            old[mt][q] = T2{0, 0};
+            if (!(addr[u][mt][q] & 0x8000))
+              old[mt][q] = *(const T2 *)(rb + 2 * addr[u][mt][q]);
+          }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          *(T2 *)(rb + 2 * (addr[0][mt][q] & 0x7fff)) =
-              T2{old[mt][q].x + val0[mt][q], old[mt][q].y + val1[mt][q]};
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            *(T2 *)(rb + 2 * (addr[u][mt][q] & 0x7fff)) =
+                T2{old[mt][q].x + val0[u][mt][q], old[mt][q].y + val1[u][mt][q]};
+      }
     }
   }
 }
@@ -466,7 +474,7 @@ template <class P, int MT, int NDT0, int NDT1, int NF, bool STAGE_A, int NW, int
 __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
   typedef typename P::real T;
   typedef FormGeo<T> GEO;
-  static_assert(!PR || (NF == 2 && TT == 1), "paired rows need two forms, one tile per step");
+  static_assert(!PR || NF == 2, "paired rows need two forms");
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int n = lane & 15, kb = lane >> 4;
@@ -555,9 +563,16 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
           }
         };
         if constexpr (PR) {
-          fused_tile_pair<P, MT, NDT0, NDT1, STAGE_A>(S0, S1, a.f[0], a.f[1], cg[0], cg[NF - 1],
-                                                      src[0], col[0], rk[0], a.rstride, lane, kb,
-                                                      rowbuf, after_k);
+          if (tt == 2) {
+            if constexpr (TT == 2)
+              fused_tile_pair<P, MT, NDT0, NDT1, STAGE_A, 2>(S0, S1, a.f[0], a.f[1], cg[0],
+                                                             cg[NF - 1], src, col, rk, a.rstride,
+                                                             lane, kb, rowbuf, after_k);
+          } else {
+            fused_tile_pair<P, MT, NDT0, NDT1, STAGE_A, 1>(S0, S1, a.f[0], a.f[1], cg[0],
+                                                           cg[NF - 1], src, col, rk, a.rstride,
+                                                           lane, kb, rowbuf, after_k);
+          }
         } else if (tt == 2) {
           if constexpr (TT == 2) {
             if (f == 0)
@@ -618,15 +633,18 @@ static fe_status launch_fused_one(const FusedArgs &k, size_t smem, hipStream_t s
 template <class P, int MT, int NDT0, int NDT1, int NF>
 static fe_status launch_fused_nw(const FusedArgs &k, const FormLayout *const *L, hipStream_t s) {
   // A pair shares one row buffer of value pairs (one scatter for both
-  // forms) when that fits with 8 waves.  Otherwise one tile per step with
-  // the most waves per workgroup that fit with the fragments staged (at
-  // least 8: see fused_eligible); measured on the benchmark workload, 16
-  // waves with one tile per step beat 12 waves with two tiles sharing each
-  // fragment read.
+  // forms) when that fits with 8 waves, two tiles per step where their
+  // accumulators fit the register file (measured on the benchmark workload,
+  // P4 mass + stiffness in FP16: 457 us against 472 us with one tile; the
+  // split and FP64 pairs spill with two and take one).  Otherwise one tile
+  // per step with the most waves per workgroup that fit with the fragments
+  // staged (at least 8: see fused_eligible); there 16 waves with one tile
+  // per step beat 12 waves with two tiles sharing each fragment read.
   if constexpr (NF == 2) {
     const size_t pr = fused_lds(L, NF, 8, true) + (size_t)8 * (FUSED_SPAN + 64) * sizeof(typename P::real);
+    constexpr int PTT = (P::SPLIT || sizeof(typename P::real) == 8) ? 1 : 2;
     if (pr <= FUSED_LDS_BUDGET)
-      return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 8, 1, true>(k, pr, s);
+      return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 8, PTT, true>(k, pr, s);
   }
   if (fused_lds(L, NF, 16, true) <= FUSED_LDS_BUDGET)
     return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 16, 1>(k, fused_lds(L, NF, 16, true), s);
