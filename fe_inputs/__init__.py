@@ -14,6 +14,7 @@ from .meshes import (  # noqa: F401
     dg_dofmap,
     lattice_multi_indices,
     nodal_values,
+    normal_vector,
     config_mesh,
     CONFIGS,
 )

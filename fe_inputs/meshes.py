@@ -227,6 +227,12 @@ def kappa_c3(x: np.ndarray) -> np.ndarray:
     return np.exp(np.sin(2 * np.pi * x[:, 0]) * np.cos(2 * np.pi * x[:, 1]) * x[:, 2])
 
 
+def normal_vector(n: int, seed: int) -> np.ndarray:
+    """n samples of N(0, 1) from numpy's PCG64 stream ``seed``, rounded to FP32
+    (the FE functions u, v of the action and adjoint workload)."""
+    return np.random.default_rng(seed).standard_normal(n).astype(np.float32)
+
+
 # Workload recipes.  Sizes follow the five benchmark configurations; ``scale``
 # replaces the box count for reduced test sizes.
 CONFIGS = {
@@ -236,6 +242,10 @@ CONFIGS = {
                flatten=0.05, flatten_seed=1, forms=("mass", "stiffness"), coeff=None),
     "c3": dict(d=3, n=32, degree=6, quad_degree=14, jitter=0.25, seed=0,
                flatten=0.0, forms=("stiffness",), coeff="kappa"),
+    # action y = A(kappa) u and its adjoint on the c3 mesh and coefficient,
+    # u and v drawn by normal_vector with seeds 3 and 4
+    "c5": dict(d=3, n=32, degree=6, quad_degree=14, jitter=0.25, seed=0,
+               flatten=0.0, forms=("stiffness",), coeff="kappa", u_seed=3, v_seed=4),
 }
 
 

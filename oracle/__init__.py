@@ -22,6 +22,12 @@ Parts and what pins them (tests under ``tests/test_oracle_*.py``):
 * ``oracle_fe.c`` assembly (Section 3.3) -- pinned by brute-force dense
   assembly on tiny meshes, nnz counts, and exact polynomial integrals
   u^T M v, u^T K v.
+* ``oracle_fe.c`` actions (Algorithm 2) and the coefficient adjoint -- pinned
+  by the assembled matrix times the vector (Algorithm 1 route), mass and
+  stiffness actions on constants (|Omega|, zero), the exact integral of
+  w grad u . grad v for polynomials, the Euler identity
+  sum_m z_m g_m = v^T A(z) u, brute force g_m = v^T A(e_m) u, and central
+  finite differences of the patch functional.
 """
 from __future__ import annotations
 
@@ -73,6 +79,13 @@ def _load():
         lib.oracle_assemble.argtypes = [ctypes.c_int64, ctypes.c_int, P, P, ctypes.c_int64, P,
                                         P, P]
         lib.oracle_assemble.restype = ctypes.c_int
+        lib.oracle_local_vectors.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, P,
+                                             ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P,
+                                             P, P, ctypes.c_int]
+        lib.oracle_local_vectors.restype = ctypes.c_int
+        lib.oracle_assemble_vector.argtypes = [ctypes.c_int64, ctypes.c_int, P, P,
+                                               ctypes.c_int64, P]
+        lib.oracle_assemble_vector.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -161,3 +174,62 @@ def assemble_form(form: str, mesh, quad_degree: int, nthreads: int = 0, coeff=No
     A = local_matrices(form, mesh.cell_coords, mesh.degree, quad_degree, mesh.dofmap,
                        coeff, nthreads)
     return assemble(mesh.dofmap, A, mesh.n_dofs)
+
+
+def local_vectors(form: str, cell_coords: np.ndarray, degree: int, quad_degree: int,
+                  dofmap: np.ndarray, u: np.ndarray, coeff: Optional[np.ndarray] = None,
+                  v: Optional[np.ndarray] = None, nthreads: int = 0, tab=None):
+    """(b, g): local action vectors b_K by Algorithm 2 for the FE function u,
+    [n_cells][n_phi], and, when ``v`` is given, the local coefficient adjoint
+    g_K of f(z) = v^T A(z) u (else None), all in FP64."""
+    cc = np.ascontiguousarray(cell_coords, dtype=np.float64)
+    n_cells, _, d = cc.shape
+    if tab is None:
+        tab = tabulation(d, degree, quad_degree)
+    _, w, vals, grads = tab
+    w = np.ascontiguousarray(w); vals = np.ascontiguousarray(vals)
+    grads = np.ascontiguousarray(grads)
+    n_q, n_phi = vals.shape
+    dm = np.ascontiguousarray(dofmap, dtype=np.int32)
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    vv = None if v is None else np.ascontiguousarray(v, dtype=np.float64)
+    cf = None if coeff is None else np.ascontiguousarray(coeff, dtype=np.float64)
+    b = np.empty((n_cells, n_phi))
+    g = None if v is None else np.empty((n_cells, n_phi))
+    st = _load().oracle_local_vectors(d, FORMS[form], n_cells, _ptr(cc), n_phi, n_q, _ptr(w),
+                                      _ptr(vals), _ptr(grads), _ptr(dm), _ptr(cf), _ptr(uu),
+                                      _ptr(vv), _ptr(b), _ptr(g), int(nthreads))
+    if st != 0:
+        raise OracleError(f"oracle_local_vectors failed (status {st})")
+    return b, g
+
+
+def assemble_vector(dofmap: np.ndarray, b: np.ndarray, n_dofs: int) -> np.ndarray:
+    """v^g = L b in FP64, summed in the order cell ascending, then i."""
+    dm = np.ascontiguousarray(dofmap, dtype=np.int32)
+    bb = np.ascontiguousarray(b, dtype=np.float64)
+    out = np.empty(n_dofs)
+    st = _load().oracle_assemble_vector(dm.shape[0], dm.shape[1], _ptr(dm), _ptr(bb), n_dofs,
+                                        _ptr(out))
+    if st != 0:
+        raise OracleError(f"oracle_assemble_vector failed ({st})")
+    return out
+
+
+def action(form: str, mesh, quad_degree: int, u: np.ndarray, coeff=None, nthreads: int = 0):
+    """y = A(z) u by Algorithm 2 on every cell, then vector assembly."""
+    b, _ = local_vectors(form, mesh.cell_coords, mesh.degree, quad_degree, mesh.dofmap, u,
+                         coeff, None, nthreads)
+    return assemble_vector(mesh.dofmap, b, mesh.n_dofs)
+
+
+def vjp(form: str, mesh, quad_degree: int, u: np.ndarray, v: np.ndarray, coeff=None,
+        nthreads: int = 0):
+    """Cotangent v of y = A(z) u: (grad_u, grad_z) with grad_u = A(z)^T v
+    (= A(z) v: both forms are symmetric) and grad_z[m] = v^T (dA/dz_m) u
+    (None without a coefficient)."""
+    b, g = local_vectors(form, mesh.cell_coords, mesh.degree, quad_degree, mesh.dofmap, v,
+                         coeff, u if coeff is not None else None, nthreads)
+    gu = assemble_vector(mesh.dofmap, b, mesh.n_dofs)
+    gz = None if g is None else assemble_vector(mesh.dofmap, g, mesh.n_dofs)
+    return gu, gz

@@ -23,6 +23,20 @@
  *     ascending and unique, explicit zeros kept; values summed in FP64 in the
  *     order cell K ascending, then i, then j.
  *
+ *   - Local vectors by Algorithm 2 (Section 3.2, linear forms / actions):
+ *     the known function w is evaluated at the quadrature points as an FE
+ *     function (w_q = sum_k w_k phi_k(X_q), or its reference gradient), then
+ *     r_s = vstack_q(w_q z_q (G w_q))  (Poisson; w_q |det J| z_q w_q for mass)
+ *     and v = sum_s B_s r_s.
+ *   - The coefficient adjoint of f(z) = v^T A(z) u: f is linear in the nodal
+ *     values z, z_q = sum_k z_k phi_k(X_q), so on cell K
+ *         df/dz_k = sum_q phi_k(X_q) w_q g_q,
+ *         g_q = (grad u_h)^T G (grad v_h)   (Poisson),
+ *         g_q = |det J| u_h v_h              (mass),
+ *     with u_h, v_h evaluated at X_q as FE functions.
+ *   - Vector assembly v^g = L b (Section 3.3): local vectors summed into the
+ *     global vector in the order cell K ascending, then i.
+ *
  * Tabulations (weights, basis values and gradients at the quadrature points)
  * are inputs; the oracle's own Python side computes them.
  */
@@ -302,6 +316,137 @@ int oracle_assemble(int64_t n_cells, int n_phi, const int32_t *dofmap,
         if (pos < 0) return ORACLE_EINVAL;
         values[row_ptr[g] + pos] += A_local[((size_t)K * n_phi + i) * n_phi + j];
       }
+    }
+  return ORACLE_OK;
+}
+
+/* FE function evaluation on cell K at every quadrature point:
+ *   val[q]      = sum_k x_{L(K,k)} phi_k(X_q)
+ *   grad[t][q]  = sum_k x_{L(K,k)} d_t phi_k(X_q)   (when grad and bgrad are given)
+ * (the Lemma on FE function evaluation). */
+static void fe_eval(int d, int64_t K, int n_phi, int n_q, const double *bval,
+                    const double *bgrad, const int32_t *dofmap, const double *x,
+                    double *val, double *grad) {
+  for (int q = 0; q < n_q; ++q) {
+    double a = 0.0;
+    for (int k = 0; k < n_phi; ++k) a += x[dofmap[K * n_phi + k]] * bval[(size_t)q * n_phi + k];
+    val[q] = a;
+    if (grad && bgrad)
+      for (int t = 0; t < d; ++t) {
+        double b = 0.0;
+        for (int k = 0; k < n_phi; ++k)
+          b += x[dofmap[K * n_phi + k]] * bgrad[((size_t)t * n_q + q) * n_phi + k];
+        grad[(size_t)t * n_q + q] = b;
+      }
+  }
+}
+
+/* Local vectors of every cell by Algorithm 2 (v_out [n_cells][n_phi]) for the
+ * action of the mass or Poisson form with coefficient z (NULL: z = 1) on the
+ * global FE function u, and, when g_out != NULL, the local coefficient
+ * adjoint g_out [n_cells][n_phi] of f(z) = vv^T A(z) u (vv must then be given).
+ * Either output may be NULL. */
+int oracle_local_vectors(int d, int form, int64_t n_cells, const double *coords, int n_phi,
+                         int n_q, const double *weights, const double *bval,
+                         const double *bgrad, const int32_t *dofmap, const double *coeff,
+                         const double *u, const double *vv, double *v_out, double *g_out,
+                         int nthreads) {
+  if (d < 2 || d > 3 || n_phi < 1 || n_q < 1 || !coords || !weights || !bval || !dofmap || !u)
+    return ORACLE_EINVAL;
+  if (form != FORM_MASS && form != FORM_STIFFNESS) return ORACLE_EINVAL;
+  if (form == FORM_STIFFNESS && !bgrad) return ORACLE_EINVAL;
+  if (g_out && !vv) return ORACLE_EINVAL;
+  const int nd = (form == FORM_MASS) ? 1 : d;
+  int status = ORACLE_OK;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+  {
+    double *uq = (double *)malloc(sizeof(double) * n_q * (1 + d));
+    double *vq = (double *)malloc(sizeof(double) * n_q * (1 + d));
+    double *zq = (double *)malloc(sizeof(double) * n_q);
+    double *r = (double *)malloc(sizeof(double) * n_q * nd);
+    if (!uq || !vq || !zq || !r) {
+#pragma omp atomic write
+      status = ORACLE_ENOMEM;
+    } else {
+#pragma omp for schedule(static)
+      for (int64_t K = 0; K < n_cells; ++K) {
+        double G[9], det;
+        int st = oracle_geometry(d, coords + K * (d + 1) * d, NULL, &det, NULL, G);
+        if (st != ORACLE_OK) {
+#pragma omp atomic write
+          status = st;
+          for (int i = 0; i < n_phi; ++i) {
+            if (v_out) v_out[K * n_phi + i] = NAN;
+            if (g_out) g_out[K * n_phi + i] = NAN;
+          }
+          continue;
+        }
+        if (form == FORM_MASS) G[0] = fabs(det);
+        /* coefficient and the known functions at the quadrature points */
+        for (int q = 0; q < n_q; ++q) zq[q] = 1.0;
+        if (coeff) fe_eval(d, K, n_phi, n_q, bval, NULL, dofmap, coeff, zq, NULL);
+        fe_eval(d, K, n_phi, n_q, bval, form == FORM_STIFFNESS ? bgrad : NULL, dofmap, u, uq,
+                uq + n_q);
+        if (v_out) {
+          /* step 2: r_s(q) = w_q z_q (G grad u)_s, or w_q z_q |det J| u_q */
+          for (int s = 0; s < nd; ++s)
+            for (int q = 0; q < n_q; ++q) {
+              double a = 0.0;
+              if (form == FORM_MASS) a = G[0] * uq[q];
+              else
+                for (int t = 0; t < d; ++t) a += G[s * d + t] * uq[(size_t)(1 + t) * n_q + q];
+              r[(size_t)s * n_q + q] = weights[q] * zq[q] * a;
+            }
+          /* step 3: v = sum_s B_s r_s, B_s[i][q] = d_s phi_i(X_q) (phi_i for mass) */
+          for (int i = 0; i < n_phi; ++i) {
+            double a = 0.0;
+            for (int s = 0; s < nd; ++s)
+              for (int q = 0; q < n_q; ++q) {
+                const double b = (form == FORM_MASS) ? bval[(size_t)q * n_phi + i]
+                                                     : bgrad[((size_t)s * n_q + q) * n_phi + i];
+                a += b * r[(size_t)s * n_q + q];
+              }
+            v_out[K * n_phi + i] = a;
+          }
+        }
+        if (g_out) {
+          fe_eval(d, K, n_phi, n_q, bval, form == FORM_STIFFNESS ? bgrad : NULL, dofmap, vv, vq,
+                  vq + n_q);
+          for (int i = 0; i < n_phi; ++i) {
+            double a = 0.0;
+            for (int q = 0; q < n_q; ++q) {
+              double gq = 0.0;
+              if (form == FORM_MASS) gq = G[0] * uq[q] * vq[q];
+              else
+                for (int s = 0; s < d; ++s)
+                  for (int t = 0; t < d; ++t)
+                    gq += vq[(size_t)(1 + s) * n_q + q] * G[s * d + t] * uq[(size_t)(1 + t) * n_q + q];
+              a += bval[(size_t)q * n_phi + i] * weights[q] * gq;
+            }
+            g_out[K * n_phi + i] = a;
+          }
+        }
+      }
+    }
+    free(uq); free(vq); free(zq); free(r);
+  }
+  return status;
+}
+
+/* v^g = L b: local vectors b [n_cells][n_phi] summed into out [n_dofs] in the
+ * order cell K ascending, then i. */
+int oracle_assemble_vector(int64_t n_cells, int n_phi, const int32_t *dofmap, const double *b,
+                           int64_t n_dofs, double *out) {
+  if (!dofmap || !b || !out || n_dofs < 1) return ORACLE_EINVAL;
+  memset(out, 0, sizeof(double) * (size_t)n_dofs);
+  for (int64_t K = 0; K < n_cells; ++K)
+    for (int i = 0; i < n_phi; ++i) {
+      const int32_t g = dofmap[K * n_phi + i];
+      if (g < 0 || g >= n_dofs) return ORACLE_EINVAL;
+      out[g] += b[K * n_phi + i];
     }
   return ORACLE_OK;
 }

@@ -94,3 +94,50 @@ def test_exact_stiffness_integral_pin_is_sharp(mistake):
         assert err < 1e-13
     else:
         assert err > 1e-3
+
+
+def _local_action_sum(form, m, q, tab, u, w):
+    b, _ = oracle.local_vectors(form, m.cell_coords, m.degree, q, m.dofmap, u, tab=tab)
+    return w @ oracle.assemble_vector(m.dofmap, b, m.n_dofs)
+
+
+@pytest.mark.parametrize("mistake", ["none", "swap_slabs", "flip_sign"])
+def test_action_exact_integral_pin_is_sharp(mistake):
+    m = config_mesh("c2", n=2, flatten=0.0)
+    tab = {"none": _identity, "swap_slabs": _swap_slabs, "flip_sign": _flip_sign}[mistake](
+        oracle.tabulation(3, 4, 8))
+    u = nodal_values(m.cell_coords, m.dofmap, m.n_dofs, 4, lambda x: x[:, 0] ** 2 * x[:, 1])
+    w = nodal_values(m.cell_coords, m.dofmap, m.n_dofs, 4, lambda x: x[:, 0] * x[:, 1] * x[:, 2])
+    err = abs(_local_action_sum("stiffness", m, 8, tab, u, w) - 7.0 / 24.0)
+    assert (err < 1e-13) if mistake == "none" else (err > 1e-3)
+
+
+@pytest.mark.parametrize("mistake", ["none", "drop_weight", "shift_weights"])
+def test_mass_action_constant_pin_is_sharp(mistake):
+    m = config_mesh("c2", n=2, flatten=0.0)
+    pts, w, vals, grads = oracle.tabulation(3, 4, 8)
+    w = w.copy()
+    if mistake == "drop_weight":
+        w[0] = 0.0
+    elif mistake == "shift_weights":
+        w = np.roll(w, 1)
+    one = np.ones(m.n_dofs)
+    u = nodal_values(m.cell_coords, m.dofmap, m.n_dofs, 4, lambda x: x[:, 0] ** 4)
+    # int x^4 = 1/5 through the mass action; the constant sum alone does not
+    # see a permutation of the weights, the degree-4 integrand does
+    err = abs(_local_action_sum("mass", m, 8, (pts, w, vals, grads), u, one) - 0.2)
+    assert (err < 1e-13) if mistake == "none" else (err > 1e-6)
+
+
+@pytest.mark.parametrize("mistake", ["none", "swap_slabs", "flip_sign"])
+def test_adjoint_exact_integral_pin_is_sharp(mistake):
+    m = config_mesh("c2", n=2, flatten=0.0)
+    tab = {"none": _identity, "swap_slabs": _swap_slabs, "flip_sign": _flip_sign}[mistake](
+        oracle.tabulation(3, 4, 8))
+    nv = lambda f: nodal_values(m.cell_coords, m.dofmap, m.n_dofs, 4, f)  # noqa: E731
+    u, v, w = nv(lambda x: x[:, 0] ** 2 * x[:, 1]), nv(lambda x: x[:, 0] * x[:, 2]), \
+        nv(lambda x: x[:, 0] * x[:, 1])
+    _, g = oracle.local_vectors("stiffness", m.cell_coords, 4, 8, m.dofmap, u,
+                                coeff=np.ones(m.n_dofs), v=v, tab=tab)
+    err = abs(w @ oracle.assemble_vector(m.dofmap, g, m.n_dofs) - 1.0 / 9.0)
+    assert (err < 1e-13) if mistake == "none" else (err > 1e-3)
