@@ -157,6 +157,9 @@ fe_status fe_tabulate(int32_t cell, int32_t degree, int32_t quad_degree, int32_t
  * lane order of the matrix-core instructions, the weighted table w_q B used
  * to form H = C B^T in single (double for FE_FP64), and, with a
  * coefficient, the value table used to evaluate z at the quadrature points.
+ * FP32 and FP64 forms with n_phi <= 84 also carry the tables of the action
+ * kernels (values and gradients in the lane order of fe_action_vjp, per
+ * tile of 16 quadrature points, with the weights).
  * The buffer also holds a device status word (see fe_get_device_status).
  *   form_buf   : device buffer of *form_bytes bytes, or NULL for a size query
  *   form_bytes : in/out; on a query receives the required size; on a real
@@ -242,6 +245,56 @@ fe_status fe_assemble_csr(const fe_form_desc *forms, const void *const *form_buf
                           int32_t n_forms, const fe_mesh_view *m, int32_t phase,
                           fe_csr *mats, void *plan, size_t *plan_bytes, void *workspace,
                           size_t *ws_bytes, void *stream);
+
+/* Modes of fe_action_vjp. */
+enum { FE_ACTION = 0, FE_VJP = 1 };
+
+/* ------------------------------------------------------------------------
+ * fe_vector_plan -- symbolic phase of vector assembly v^g = L b (Section
+ * 3.3): the dof -> (cell, local index) adjacency of the dof map, every list
+ * in cell-ascending order, so that the numeric sums of fe_action_vjp run in
+ * a fixed order.
+ *   n_phi : dofs per cell (the dof map's row length), 1 <= n_phi <= 256
+ *   plan / plan_bytes : device buffer owned by the caller, sized by a query
+ *       with plan == NULL; its size depends on n_cells, n_phi and n_dofs.
+ * SYNCHRONISES the stream.  Errors: FE_EINVAL (NULL pointers, a dof entry
+ * out of range), FE_EOVERFLOW (n_dofs >= 2^31 - 1), FE_ESIZE, FE_EHIP.
+ * ------------------------------------------------------------------------ */
+fe_status fe_vector_plan(const fe_mesh_view *m, int32_t n_phi, void *plan, size_t *plan_bytes,
+                         void *stream);
+
+/* ------------------------------------------------------------------------
+ * fe_action_vjp -- the action y = A(z) u of the mass or Poisson form and its
+ * vector-Jacobian product, matrix free (Algorithm 2, Section 3.2; the local
+ * vectors v = sum_s B_s r_s with r_s = vstack_q(w_q z(X_q) (G grad u)_s),
+ * assembled as v^g = L b, Section 3.3).
+ *   mode FE_ACTION : y = A(z) u.  Reads u; writes y [n_dofs].
+ *   mode FE_VJP    : for the cotangent v of y, grad_u = A(z)^T v (= A(z) v,
+ *       both forms being symmetric) and, when grad_coeff != NULL (requires
+ *       f->has_coeff), grad_coeff[m] = v^T (dA/dz_m) u
+ *         = sum_K sum_{k: L(K,k) = m} sum_q phi_k(X_q) w_q g_K(q),
+ *       g_K = (grad v_h)^T G (grad u_h) (Poisson) or |det J| v_h u_h (mass).
+ *       Reads v (and u for grad_coeff).
+ *   form_buf : prepared by fe_form_prepare for the same *f; precision
+ *       FE_FP32 or FE_FP64 with n_phi <= 84 (else FE_EUNSUPPORTED)
+ *   vplan    : from fe_vector_plan for the same mesh
+ *   u, v, y, grad_u, grad_coeff : device [n_dofs], double for FE_FP64 else
+ *       float.  Outputs are overwritten (every entry written once); each
+ *       sums its contributions in the fixed order cell ascending.
+ *   workspace / ws_bytes : local vectors, sized by a query with
+ *       workspace == NULL (the size depends on the mode and on whether
+ *       grad_coeff is requested).
+ * Geometry is FP64 per cell, rounded once to the arithmetic type; the
+ * coefficient is evaluated in that type.  Asynchronous, never synchronises.
+ * A degenerate cell gives NaN contributions and sets FE_EDEGENERATE in the
+ * status word of form_buf; a dof out of range or a plan of another mesh
+ * sets FE_EINVAL there (fe_get_device_status).  Errors: FE_EINVAL,
+ * FE_EUNSUPPORTED, FE_ESIZE, FE_EOVERFLOW, FE_EHIP.
+ * ------------------------------------------------------------------------ */
+fe_status fe_action_vjp(const fe_form_desc *f, const void *form_buf, const fe_mesh_view *m,
+                        const void *vplan, int32_t mode, const void *u, const void *v, void *y,
+                        void *grad_u, void *grad_coeff, void *workspace, size_t *ws_bytes,
+                        void *stream);
 
 /* ------------------------------------------------------------------------
  * fe_get_device_status -- read and clear the status word of a form buffer

@@ -36,6 +36,8 @@ FE_NUMERIC = 2
 FE_NUMERIC_GATHER = 3
 FE_NUMERIC_GEOMETRY = 4
 FE_NUMERIC_FUSED = 5
+FE_ACTION = 0
+FE_VJP = 1
 
 # every symbol declared in include/fe.h
 EXPORTS = (
@@ -43,6 +45,8 @@ EXPORTS = (
     "fe_form_prepare",
     "fe_cell_kernels",
     "fe_assemble_csr",
+    "fe_vector_plan",
+    "fe_action_vjp",
     "fe_get_device_status",
     "fe_status_string",
     "fe_version",
@@ -96,6 +100,12 @@ def load() -> ctypes.CDLL:
                                     ctypes.POINTER(ctypes.c_size_t), P,
                                     ctypes.POINTER(ctypes.c_size_t), P]
     lib.fe_assemble_csr.restype = i32
+    lib.fe_vector_plan.argtypes = [ctypes.POINTER(fe_mesh_view), i32, P,
+                                   ctypes.POINTER(ctypes.c_size_t), P]
+    lib.fe_vector_plan.restype = i32
+    lib.fe_action_vjp.argtypes = [ctypes.POINTER(fe_form_desc), P, ctypes.POINTER(fe_mesh_view), P,
+                                  i32, P, P, P, P, P, P, ctypes.POINTER(ctypes.c_size_t), P]
+    lib.fe_action_vjp.restype = i32
     lib.fe_get_device_status.argtypes = [P, P]
     lib.fe_get_device_status.restype = i32
     lib.fe_status_string.argtypes = [i32]

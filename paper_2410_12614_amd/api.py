@@ -178,3 +178,107 @@ class Assembly:
     def status(self) -> list:
         return [fe_get_device_status(b, self.stream) for b in self.form_bufs] + \
                [fe_get_device_status(self.plan, self.stream)]
+
+
+def fe_vector_plan(mesh: MeshView, n_phi: int, stream=None) -> torch.Tensor:
+    """Dof -> (cell, i) adjacency of the dof map (symbolic phase of v^g = L b)."""
+    lib = L.load()
+    mv = mesh.struct()
+    size = ctypes.c_size_t(0)
+    check(lib.fe_vector_plan(ctypes.byref(mv), n_phi, None, ctypes.byref(size), _stream(stream)),
+          "fe_vector_plan(size query)")
+    plan = torch.empty(size.value, dtype=torch.uint8, device=mesh.coords.device)
+    check(lib.fe_vector_plan(ctypes.byref(mv), n_phi, _ptr(plan), ctypes.byref(size),
+                             _stream(stream)), "fe_vector_plan")
+    return plan
+
+
+def fe_action_vjp(desc: L.fe_form_desc, form_buf: torch.Tensor, mesh: MeshView,
+                  vplan: torch.Tensor, mode: int, u: Optional[torch.Tensor],
+                  v: Optional[torch.Tensor], y: Optional[torch.Tensor],
+                  grad_u: Optional[torch.Tensor], grad_coeff: Optional[torch.Tensor],
+                  workspace: Optional[torch.Tensor], stream=None,
+                  ws_bytes: Optional[ctypes.c_size_t] = None) -> int:
+    mv = mesh.struct()
+    wb = ws_bytes if ws_bytes is not None else ctypes.c_size_t(
+        0 if workspace is None else workspace.numel())
+    return L.load().fe_action_vjp(ctypes.byref(desc), _ptr(form_buf), ctypes.byref(mv),
+                                  _ptr(vplan), mode, _ptr(u), _ptr(v), _ptr(y), _ptr(grad_u),
+                                  _ptr(grad_coeff), _ptr(workspace), ctypes.byref(wb),
+                                  _stream(stream))
+
+
+class Action:
+    """y = A(z) u of one form on one mesh, and its vector-Jacobian product:
+    prepares the form buffer and the vector plan once, sizes the workspace."""
+
+    def __init__(self, mesh: MeshView, desc: L.fe_form_desc, stream=None):
+        self.mesh, self.desc, self.stream = mesh, desc, stream
+        dev = mesh.coords.device
+        self.form_buf = fe_form_prepare(desc, dev, stream)
+        self.n_phi = int(mesh.dofmap.shape[1])
+        self.vplan = fe_vector_plan(mesh, self.n_phi, stream)
+        self.dtype = torch.float64 if desc.precision == L.FE_FP64 else torch.float32
+        sizes = []
+        for mode, gz in ((L.FE_ACTION, False), (L.FE_VJP, True)):
+            wb = ctypes.c_size_t(0)
+            dummy = self.form_buf if gz else None
+            check(fe_action_vjp(desc, self.form_buf, mesh, self.vplan, mode, None, None, None,
+                                None, dummy, None, stream, wb), "fe_action_vjp(size query)")
+            sizes.append(wb.value)
+        self.workspace = torch.empty(max(sizes), dtype=torch.uint8, device=dev)
+
+    def _vec(self, x: torch.Tensor) -> torch.Tensor:
+        if x.dtype != self.dtype or not x.is_contiguous() or x.numel() != self.mesh.n_dofs:
+            raise ValueError(f"expected a contiguous {self.dtype} vector of {self.mesh.n_dofs}")
+        return x
+
+    def apply(self, u: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """y = A(z) u (FE_ACTION)."""
+        u = self._vec(u)
+        y = torch.empty_like(u) if out is None else out
+        check(fe_action_vjp(self.desc, self.form_buf, self.mesh, self.vplan, L.FE_ACTION, u, None,
+                            y, None, None, self.workspace, self.stream), "fe_action_vjp(ACTION)")
+        return y
+
+    def vjp(self, u: torch.Tensor, v: torch.Tensor, want_coeff: bool = True):
+        """(grad_u, grad_coeff) for the cotangent v of y = A(z) u (FE_VJP);
+        grad_coeff is None without a coefficient or when not wanted."""
+        v = self._vec(v)
+        gu = torch.empty_like(v)
+        gz = None
+        if want_coeff and self.desc.has_coeff:
+            gz = torch.empty_like(v)
+            u = self._vec(u)
+        check(fe_action_vjp(self.desc, self.form_buf, self.mesh, self.vplan, L.FE_VJP,
+                            u if gz is not None else None, v, None, gu, gz, self.workspace,
+                            self.stream), "fe_action_vjp(VJP)")
+        return gu, gz
+
+
+class ActionFunction(torch.autograd.Function):
+    """y = A(z) u with gradients for u and for the nodal coefficient z.
+
+    The coefficient values live in ``action.mesh.coeff`` (the mesh view the
+    library reads); the ``coeff`` argument must be that tensor, so that
+    autograd can route its gradient.  Forward runs FE_ACTION, backward
+    FE_VJP; both are the library's kernels."""
+
+    @staticmethod
+    def forward(ctx, u: torch.Tensor, coeff: Optional[torch.Tensor], action: "Action"):
+        if coeff is not None and coeff.data_ptr() != action.mesh.coeff.data_ptr():
+            raise ValueError("coeff must be the coefficient tensor of the action's mesh")
+        ctx.action = action
+        ctx.save_for_backward(u)
+        return action.apply(u.detach().contiguous())
+
+    @staticmethod
+    def backward(ctx, gy: torch.Tensor):
+        (u,) = ctx.saved_tensors
+        action = ctx.action
+        want_z = ctx.needs_input_grad[1]
+        gu, gz = action.vjp(u.detach().contiguous(), gy.detach().to(action.dtype).contiguous(),
+                            want_coeff=want_z)
+        if gz is not None:
+            gz = gz.to(torch.float64)
+        return (gu if ctx.needs_input_grad[0] else None), gz, None

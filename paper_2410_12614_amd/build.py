@@ -27,6 +27,8 @@ SOURCES = [
     "fe_cell_fp16.hip",
     "fe_cell_bf16.hip",
     "fe_cell_split.hip",
+    "fe_action_fp32.hip",
+    "fe_action_fp64.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

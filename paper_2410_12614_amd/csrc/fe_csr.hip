@@ -865,3 +865,185 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
   }
   return st;
 }
+
+// ------------------------------------------------- vector assembly, actions
+namespace fe {
+
+VecPlanLayout vec_plan_layout(int64_t n_cells, int n_phi, int64_t n_dofs) {
+  VecPlanLayout P;
+  size_t off = 256;
+  P.off_adj_ptr = off;
+  off = a256(off + sizeof(int64_t) * (size_t)(n_dofs + 1));
+  P.off_cursor = off;
+  off = a256(off + sizeof(int64_t) * (size_t)n_dofs);
+  P.off_adj = off;
+  off = a256(off + sizeof(int64_t) * (size_t)std::max<int64_t>(1, n_cells * n_phi));
+  P.scan_blocks = (size_t)(n_dofs + 1 + SCAN_TILE - 1) / SCAN_TILE;
+  P.off_scan = off;
+  off = a256(off + sizeof(int64_t) * (P.scan_blocks + 1));
+  P.total = off;
+  return P;
+}
+
+namespace {
+
+// v^g = L b (Section 3.3): every dof sums the local-vector entries of its
+// adjacency list, cell ascending, then i -- a fixed order, no atomics.  A
+// plan built for another mesh is detected from its header (read before any
+// offset derived from the mesh sizes is used) and reported through the
+// status word; nothing is written then.
+template <class T, int NF>
+__global__ __launch_bounds__(256) void k_vgather(const VecPlanHeader *hdr, const int64_t *adj_ptr,
+                                                 const int64_t *adj, int64_t n_cells,
+                                                 int64_t n_dofs, int n_phi, int32_t *status,
+                                                 const T *b0, const T *b1, T *out0, T *out1) {
+  if (hdr->magic != VPLAN_MAGIC || hdr->n_cells != n_cells || hdr->n_dofs != n_dofs ||
+      hdr->n_phi != n_phi) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(status, (int32_t)STATUS_BAD_DOF);
+    return;
+  }
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_dofs) return;
+  T s0 = 0, s1 = 0;
+  for (int64_t a = adj_ptr[g]; a < adj_ptr[g + 1]; ++a) {
+    const int64_t e = adj[a];
+    const int64_t idx = (e >> 8) * n_phi + (e & 255);
+    s0 += b0[idx];
+    if (NF == 2) s1 += b1[idx];
+  }
+  out0[g] = s0;
+  if (NF == 2) out1[g] = s1;
+}
+
+template <class T>
+fe_status launch_vgather(const VecPlanHeader *hdr, const int64_t *adj_ptr, const int64_t *adj,
+                         int64_t n_cells, int64_t n_dofs, int n_phi, int32_t *status,
+                         const void *b0, const void *b1, void *out0, void *out1, hipStream_t s) {
+  const unsigned blocks = (unsigned)((n_dofs + 255) / 256);
+  if (b1)
+    hipLaunchKernelGGL((k_vgather<T, 2>), dim3(blocks), dim3(256), 0, s, hdr, adj_ptr, adj,
+                       n_cells, n_dofs, n_phi, status, (const T *)b0, (const T *)b1, (T *)out0,
+                       (T *)out1);
+  else
+    hipLaunchKernelGGL((k_vgather<T, 1>), dim3(blocks), dim3(256), 0, s, hdr, adj_ptr, adj,
+                       n_cells, n_dofs, n_phi, status, (const T *)b0, (const T *)nullptr,
+                       (T *)out0, (T *)nullptr);
+  return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
+}
+
+}  // namespace
+}  // namespace fe
+
+extern "C" fe_status fe_vector_plan(const fe_mesh_view *m, int32_t n_phi, void *plan,
+                                    size_t *plan_bytes, void *stream) {
+  if (!m || n_phi < 1 || n_phi > 256 || m->n_cells < 0 || m->n_dofs < 1) return FE_EINVAL;
+  if (m->n_dofs >= INT32_MAX) return FE_EOVERFLOW;
+  const int64_t n_cells = m->n_cells, n_dofs = m->n_dofs;
+  const VecPlanLayout P = vec_plan_layout(n_cells, n_phi, n_dofs);
+  if (!plan) {
+    if (!plan_bytes) return FE_EINVAL;
+    *plan_bytes = P.total;
+    return FE_OK;
+  }
+  if (plan_bytes && *plan_bytes < P.total) return FE_ESIZE;
+  if (n_cells > 0 && !m->dofmap) return FE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned char *pb = (unsigned char *)plan;
+  VecPlanHeader *hdr_d = (VecPlanHeader *)pb;
+  int64_t *adj_ptr = (int64_t *)(pb + P.off_adj_ptr);
+  int64_t *cursor = (int64_t *)(pb + P.off_cursor);
+  int64_t *adj = (int64_t *)(pb + P.off_adj);
+  int64_t *scan = (int64_t *)(pb + P.off_scan);
+  VecPlanHeader h;
+  std::memset(&h, 0, sizeof(h));
+  h.magic = VPLAN_MAGIC;
+  h.n_cells = n_cells;
+  h.n_dofs = n_dofs;
+  h.n_phi = n_phi;
+  if (hipMemcpyAsync(hdr_d, &h, sizeof(h), hipMemcpyHostToDevice, s) != hipSuccess) return FE_EHIP;
+  hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n_dofs + 1, 256)), dim3(256), 0, s, adj_ptr,
+                     n_dofs + 1, (int64_t)0);
+  hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n_dofs, 256)), dim3(256), 0, s, cursor, n_dofs,
+                     (int64_t)0);
+  if (n_cells > 0) {
+    hipLaunchKernelGGL(k_degree, dim3(grid_for(n_cells * n_phi, 256)), dim3(256), 0, s, m->dofmap,
+                       n_cells * n_phi, n_dofs, adj_ptr, &hdr_d->status);
+    fe_status st = scan_inclusive(adj_ptr + 1, n_dofs, scan, P.scan_blocks, s);
+    if (st != FE_OK) return st;
+    hipLaunchKernelGGL(k_fill_adj, dim3(grid_for(n_cells * n_phi, 256)), dim3(256), 0, s,
+                       m->dofmap, n_cells, n_phi, n_dofs, adj_ptr, cursor, adj);
+    hipLaunchKernelGGL(k_sort_adj, dim3((unsigned)((n_dofs + 255) / 256)), dim3(256), 0, s,
+                       adj_ptr, adj, n_dofs, &hdr_d->max_deg);
+  }
+  if (!sync_ok(s)) return FE_EHIP;
+  if (hipMemcpy(&h, hdr_d, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return FE_EHIP;
+  if (h.status & STATUS_BAD_DOF) return FE_EINVAL;
+  return FE_OK;
+}
+
+extern "C" fe_status fe_action_vjp(const fe_form_desc *f, const void *form_buf,
+                                   const fe_mesh_view *m, const void *vplan, int32_t mode,
+                                   const void *u, const void *v, void *y, void *grad_u,
+                                   void *grad_coeff, void *workspace, size_t *ws_bytes,
+                                   void *stream) {
+  FormLayout L;
+  fe_status st = compute_layout(f, &L);
+  if (st != FE_OK) return st;
+  if (L.act_nt == 0) return FE_EUNSUPPORTED;
+  if (!m || m->n_cells < 0 || m->n_dofs < 1) return FE_EINVAL;
+  if (mode != FE_ACTION && mode != FE_VJP) return FE_EINVAL;
+  if (m->n_dofs >= INT32_MAX) return FE_EOVERFLOW;
+  const int64_t n_cells = m->n_cells, n_dofs = m->n_dofs;
+  const int n_phi = L.n_phi;
+  const size_t elt = (L.prec == FE_FP64) ? 8 : 4;
+  const bool gz = mode == FE_VJP && grad_coeff != nullptr;
+  const size_t loc = a256(elt * (size_t)std::max<int64_t>(1, n_cells * n_phi));
+  const size_t ws_need = loc * (gz ? 2 : 1);
+  if (!workspace) {
+    if (!ws_bytes) return FE_EINVAL;
+    *ws_bytes = ws_need;
+    return FE_OK;
+  }
+  if (ws_bytes && *ws_bytes < ws_need) return FE_ESIZE;
+  if (!form_buf || !vplan) return FE_EINVAL;
+  if (gz && !f->has_coeff) return FE_EINVAL;
+  if (f->has_coeff && !m->coeff) return FE_EINVAL;
+  if (mode == FE_ACTION && (!u || !y)) return FE_EINVAL;
+  if (mode == FE_VJP && (!v || !grad_u || (gz && !u))) return FE_EINVAL;
+  if (n_cells > 0 && (!m->dofmap || !m->cell_coords)) return FE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const VecPlanLayout P = vec_plan_layout(n_cells, n_phi, n_dofs);
+  const unsigned char *pb = (const unsigned char *)vplan;
+  const int64_t *adj_ptr = (const int64_t *)(pb + P.off_adj_ptr);
+  const int64_t *adj = (const int64_t *)(pb + P.off_adj);
+  unsigned char *wb = (unsigned char *)workspace;
+  void *b0 = wb, *b1 = gz ? wb + loc : nullptr;
+  void *out0 = mode == FE_ACTION ? y : grad_u;
+  if (n_cells > 0) {
+    ActionLaunch a;
+    a.L = &L;
+    a.form_buf = (const unsigned char *)form_buf;
+    a.status = (int32_t *)form_buf;
+    a.n_cells = n_cells;
+    a.n_dofs = n_dofs;
+    a.coords = m->cell_coords;
+    a.dofmap = m->dofmap;
+    a.coeff = f->has_coeff ? m->coeff : nullptr;
+    // action on u; the adjoint acts on v (the forms are symmetric, so
+    // A^T v = A v) and pairs it with u for the coefficient
+    a.x0 = mode == FE_ACTION ? u : v;
+    a.x1 = gz ? u : nullptr;
+    a.out0 = b0;
+    a.out1 = b1;
+    a.stream = stream;
+    st = L.prec == FE_FP64 ? launch_action_fp64(a) : launch_action_fp32(a);
+    if (st != FE_OK) return st;
+  }
+  const VecPlanHeader *hdr = (const VecPlanHeader *)vplan;
+  int32_t *status = (int32_t *)form_buf;
+  void *out1 = gz ? grad_coeff : nullptr;
+  return L.prec == FE_FP64 ? launch_vgather<double>(hdr, adj_ptr, adj, n_cells, n_dofs, n_phi,
+                                                    status, b0, b1, out0, out1, s)
+                           : launch_vgather<float>(hdr, adj_ptr, adj, n_cells, n_dofs, n_phi,
+                                                   status, b0, b1, out0, out1, s);
+}

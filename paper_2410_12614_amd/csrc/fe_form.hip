@@ -69,6 +69,21 @@ fe_status compute_layout(const fe_form_desc *f, FormLayout *L) {
   off = align256(off + (size_t)L->ndt * L->n_phi * L->n_q_pad * L->tab_bytes);
   L->off_vtab = off;
   if (L->has_coeff) off = align256(off + (size_t)L->n_q * L->n_phi * L->vtab_bytes);
+  // action tables: FP32 / FP64 forms whose dofs fit the registers of a lane;
+  // the K-steps are padded to the counts of the tetrahedral degrees 1..6
+  // (the kernels are compiled for those), triangles take a zero third slab
+  int act_nks = 0;
+  for (int b : {1, 3, 5, 9, 14, 21})
+    if (act_nks == 0 && 4 * b >= L->n_phi) act_nks = b;
+  if ((f->precision == FE_FP32 || f->precision == FE_FP64) && act_nks > 0) {
+    L->act_nt = L->form == FE_STIFFNESS ? 4 : 1;
+    L->act_nks = act_nks;
+    L->act_mt = (act_nks + 3) / 4;
+    L->act_nqt = (L->n_q + 15) / 16;
+    L->act_chunk = (size_t)64 * (L->act_nt * L->act_nks + L->act_nt * L->act_mt * 4 + 1);
+    L->off_act = off;
+    off = align256(off + L->act_chunk * L->act_nqt * L->elt_bytes);
+  }
   L->total = off;
   return FE_OK;
 }
@@ -192,6 +207,43 @@ extern "C" fe_status fe_form_prepare(const fe_form_desc *f, void *form_buf, size
         if (L.vtab_bytes == 8) put<double>(h.data(), L.off_vtab, idx, v);
         else put<float>(h.data(), L.off_vtab, idx, (float)v);
       }
+  if (L.act_nt > 0) {
+    // action tables, chunk per tile of 16 quadrature points (layout in
+    // fe_internal.h); the FP64 instruction interleaves its output rows
+    auto tabv = [&](int t, int q, int k) -> double {
+      if (q >= nq || k >= nphi || t > d) return 0.0;
+      return tab[(size_t)t * slab + (size_t)q * nphi + k];
+    };
+    auto orow = [&](int kb, int r) { return L.prec == FE_FP64 ? kb + 4 * r : 4 * kb + r; };
+    const size_t e_off = 0, c_off = (size_t)64 * L.act_nt * L.act_nks,
+                 w_off = c_off + (size_t)64 * L.act_nt * L.act_mt * 4;
+    for (int qt = 0; qt < L.act_nqt; ++qt) {
+      const size_t base = (size_t)qt * L.act_chunk;
+      for (int t = 0; t < L.act_nt; ++t)
+        for (int ks = 0; ks < L.act_nks; ++ks)
+          for (int lane = 0; lane < 64; ++lane) {
+            const double v = tabv(t, 16 * qt + lane % 16, 4 * ks + lane / 16);
+            const size_t idx = base + e_off + ((size_t)t * L.act_nks + ks) * 64 + lane;
+            if (L.prec == FE_FP64) put<double>(h.data(), L.off_act, idx, v);
+            else put<float>(h.data(), L.off_act, idx, (float)v);
+          }
+      for (int t = 0; t < L.act_nt; ++t)
+        for (int mt = 0; mt < L.act_mt; ++mt)
+          for (int r = 0; r < 4; ++r)
+            for (int lane = 0; lane < 64; ++lane) {
+              const double v = tabv(t, 16 * qt + orow(lane / 16, r), 16 * mt + lane % 16);
+              const size_t idx = base + c_off + (((size_t)t * L.act_mt + mt) * 4 + r) * 64 + lane;
+              if (L.prec == FE_FP64) put<double>(h.data(), L.off_act, idx, v);
+              else put<float>(h.data(), L.off_act, idx, (float)v);
+            }
+      for (int j = 0; j < 64; ++j) {
+        const int q = 16 * qt + j;
+        const double v = (j < 16 && q < nq) ? w[q] : 0.0;
+        if (L.prec == FE_FP64) put<double>(h.data(), L.off_act, base + w_off + j, v);
+        else put<float>(h.data(), L.off_act, base + w_off + j, (float)v);
+      }
+    }
+  }
   hdr.max_wb = max_wb;
   hdr.lebesgue = leb;
   std::memcpy(h.data(), &hdr, sizeof(hdr));

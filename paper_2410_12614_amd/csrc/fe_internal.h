@@ -32,6 +32,16 @@ enum : int32_t { STATUS_DEGENERATE = 1, STATUS_BAD_DOF = 2 };
 //   afrag_lo: split mode only, fl16((B - fl16(B)) * 2^11) in the same layout
 //   wtab    : weighted table w_q B_t(q, j), [t][j][n_q_pad], t < NDT
 //   vtab    : basis values phi_k(X_q), [n_q][n_phi] (coefficient evaluation)
+//   act     : tables of the action kernels (FP32 and FP64 forms with
+//             n_phi <= 84), one chunk of act_chunk elements per tile of 16
+//             quadrature points qt, see fe_action.h (K-steps padded to
+//             1, 3, 5, 9, 14 or 21; four tables for stiffness):
+//               E[t][ks][lane] = T_t(q, k),  q = 16 qt + lane % 16, k = 4 ks + lane / 16
+//               C[t][mt][r][lane] = T_t(q, i), i = 16 mt + lane % 16,
+//                                  q = 16 qt + row(lane / 16, r)
+//               W[64]          = w_q, q = 16 qt + j (j < 16), zero padding
+//             with T_0 = phi_k (values) and T_{1+s} = d_s phi_k (stiffness),
+//             row(kb, r) the output row of the matrix-core instruction
 struct FormLayout {
   int d, nd, ndt, n_phi, n_q, prec, form, has_coeff;
   int kstep, kpl, n_q_pad, k_pad, nks, mt;
@@ -39,6 +49,8 @@ struct FormLayout {
   int tab_bytes;  // weighted table: 2 (half, FP16 mode), 4 (float) or 8 (double, FP64 mode)
   int vtab_bytes; // value table for the coefficient: 8 unless FP16/BF16 storage
   size_t off_afrag, off_afrag_lo, off_wtab, off_vtab, total;
+  int act_nt, act_nks, act_mt, act_nqt;  // act_nt == 0: no action tables
+  size_t act_chunk, off_act;
 };
 
 struct FormHeader {
@@ -175,6 +187,39 @@ fe_status launch_fused_fp32(const FusedLaunch &a);
 fe_status launch_fused_fp16(const FusedLaunch &a);
 fe_status launch_fused_bf16(const FusedLaunch &a);
 fe_status launch_fused_split(const FusedLaunch &a);
+
+// ---- vector assembly plan (fe_vector_plan) and actions (fe_action.hip) ----
+struct VecPlanHeader {
+  int32_t status;
+  int32_t magic;
+  int64_t n_cells, n_dofs;
+  int32_t n_phi, pad;
+  int64_t max_deg;
+};
+constexpr int32_t VPLAN_MAGIC = 0x46455650;  // "FEVP"
+
+// dof -> (cell, i) adjacency, entries cell * 256 + i ascending per dof
+struct VecPlanLayout {
+  size_t off_adj_ptr, off_cursor, off_adj, off_scan, scan_blocks, total;
+};
+VecPlanLayout vec_plan_layout(int64_t n_cells, int n_phi, int64_t n_dofs);
+
+struct ActionLaunch {
+  const FormLayout *L;
+  const unsigned char *form_buf;
+  int32_t *status;
+  int64_t n_cells, n_dofs;
+  const double *coords;
+  const int32_t *dofmap;
+  const double *coeff;  // NULL without a coefficient
+  const void *x0;       // the FE function acted on
+  const void *x1;       // second function of the coefficient adjoint, or NULL
+  void *out0;           // local vectors [n_cells][n_phi]: action on x0
+  void *out1;           // local coefficient adjoint [n_cells][n_phi] (x1 given)
+  void *stream;
+};
+fe_status launch_action_fp32(const ActionLaunch &a);
+fe_status launch_action_fp64(const ActionLaunch &a);
 
 // Matrix-core tile choice: MT = ceil(n_phi / 16) row tiles of B^T and JC
 // columns j per wave per pass (4 waves per workgroup).
