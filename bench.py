@@ -19,6 +19,13 @@ same mesh, and the relative Frobenius error of the mixed result against the
 FP64 result is reported (the FP64 path itself matches the FP64 CPU oracle
 to 1e-12 in the GPU tests).
 
+The same line carries, under "action_vjp", the matrix-free action of
+Algorithm 2 and its vector-Jacobian product on the P6 weighted-stiffness
+workload (32^3 x 6 tetrahedra, 196,608 cells, 84 dofs/cell, 512-point rule,
+kappa = exp(sin(2 pi x) cos(2 pi y) z) interpolated in P6, u and v ~ N(0,1)
+in FP32): one step = y = A(kappa) u, then grad_u = A(kappa)^T v and
+grad_kappa = v^T (dA/dkappa) u, in FP32 with the FP64 path beside it.
+
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -59,6 +66,10 @@ def parse():
     ap.add_argument("--cpu-sample-cells", type=int, default=0,
                     help="cells of the oracle baseline sample (0 = the whole mesh)")
     ap.add_argument("--cpu-reps", type=int, default=3, help="oracle passes over the sample")
+    ap.add_argument("--no-action", action="store_true",
+                    help="skip the action / vector-Jacobian product measurement")
+    ap.add_argument("--action-cpu-cells", type=int, default=0,
+                    help="cells of the oracle baseline sample of the action step (0 = all)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB elementwise copy (x * 1.0), the reference "
                          "kernel for scaling hardware byte counters")
@@ -102,6 +113,86 @@ def cpu_baseline(mesh, sample_cells, reps):
     return {"value": n / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} of {mesh.n_cells} cells (first n), both forms, local matrices + CSR "
                       f"assembly (FP64, {threads} OpenMP threads), {reps} passes of {dt:.1f} s"}
+
+
+def action_section(args, steps, warmup):
+    """Action + VJP step on the P6 weighted-stiffness workload (FP32, FP64
+    beside it), its matrix-core roofline and an oracle baseline sample."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from fe_inputs import config_mesh, normal_vector
+    from paper_2410_12614_amd import api
+
+    m = config_mesh("c5")
+    n_phi, n_q, q = 84, 512, 14
+    u_h, v_h = normal_vector(m.n_dofs, 3), normal_vector(m.n_dofs, 4)
+    out = {"workload": "P6 weighted stiffness action + VJP, 32^3 x 6 jittered Kuhn tetrahedra "
+                       "(196,608 cells, 84 dofs/cell), 512-point rule, kappa interpolated in P6, "
+                       "u, v ~ N(0,1)",
+           "n_cells": m.n_cells, "n_dofs": m.n_dofs}
+    res = {}
+    for prec in ("fp32", "fp64"):
+        dt = torch.float32 if prec == "fp32" else torch.float64
+        mv = api.MeshView.from_numpy(m.cell_coords, m.dofmap, m.n_dofs, m.coeff)
+        act = api.Action(mv, api.form_desc(3, 6, q, "stiffness", prec, has_coeff=True))
+        u = torch.from_numpy(u_h).to(dt).cuda()
+        v = torch.from_numpy(v_h).to(dt).cuda()
+        y = torch.empty_like(u)
+        ms_fwd = time_steps(lambda: act.apply(u, out=y), steps, warmup)
+        ms_vjp = time_steps(lambda: act.vjp(u, v), steps, warmup)
+        gu, gz = act.vjp(u, v)
+        torch.cuda.synchronize()
+        if api.fe_get_device_status(act.form_buf) != 0:
+            raise RuntimeError("device status after the action")
+        res[prec] = {"ms_action": ms_fwd, "ms_vjp": ms_vjp, "y": y.double(), "gu": gu.double(),
+                     "gz": gz.double()}
+        del act, mv
+    r32, r64 = res["fp32"], res["fp64"]
+    err = {k: float(torch.linalg.vector_norm(r32[k] - r64[k]) / torch.linalg.vector_norm(r64[k]))
+           for k in ("y", "gu", "gz")}
+    ms = r32["ms_action"] + r32["ms_vjp"]
+    # matrix-core work per cell (algorithmic, no padding): evaluation of
+    # grad u (2 d n_q n_phi) and kappa (2 n_q n_phi) and the contraction
+    # sum_s B_s r_s (2 d n_q n_phi) for the action; the VJP evaluates grad v,
+    # grad u and kappa and contracts grad_u (d slabs) and grad_kappa (values)
+    f_act = 2 * n_q * n_phi * (3 + 1 + 3)
+    f_vjp = 2 * n_q * n_phi * (3 + 3 + 1 + 3 + 1)
+    flops = (f_act + f_vjp) * m.n_cells
+    ach = flops / (ms / 1e3) / 1e12
+    out.update({
+        "metric": "cells/s (action + VJP step)", "value": m.n_cells / (ms / 1e3),
+        "unit": "cells/s", "dtype": "f32", "ms_per_step": ms,
+        "ms_action": r32["ms_action"], "ms_vjp": r32["ms_vjp"],
+        "fp64_path": {"value": m.n_cells / ((r64["ms_action"] + r64["ms_vjp"]) / 1e3),
+                      "ms_action": r64["ms_action"], "ms_vjp": r64["ms_vjp"]},
+        "rel_err_vs_fp64": err,
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_MFMA_TFLOPS["fp32"],
+                     "unit": "TFLOP/s", "frac": ach / PEAK_MFMA_TFLOPS["fp32"], "traffic": None,
+                     "kernel": "action_kernel + vector gather (both calls of the step)",
+                     "alg_flops": flops},
+    })
+    del res
+    if not args.no_cpu_baseline:
+        n = m.n_cells if args.action_cpu_cells <= 0 else min(args.action_cpu_cells, m.n_cells)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+        tab = oracle.tabulation(3, 6, q)
+        uu, vv = u_h.astype(np.float64), v_h.astype(np.float64)
+        t0 = time.perf_counter()
+        b, _ = oracle.local_vectors("stiffness", m.cell_coords[:n], 6, q, m.dofmap[:n], uu,
+                                    m.coeff, None, threads, tab)
+        oracle.assemble_vector(m.dofmap[:n], b, m.n_dofs)
+        b, g = oracle.local_vectors("stiffness", m.cell_coords[:n], 6, q, m.dofmap[:n], vv,
+                                    m.coeff, uu, threads, tab)
+        oracle.assemble_vector(m.dofmap[:n], b, m.n_dofs)
+        oracle.assemble_vector(m.dofmap[:n], g, m.n_dofs)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": n / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} of {m.n_cells} cells (first n): action + VJP local vectors and "
+                      f"vector assembly (FP64, {threads} OpenMP threads), one pass of {dt:.1f} s"}
+    return out
 
 
 def sources_digest():
@@ -248,6 +339,10 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(mesh, args.cpu_sample_cells, args.cpu_reps)
+    if not args.no_action:
+        del asm
+        torch.cuda.empty_cache()
+        line["action_vjp"] = action_section(args, max(3, args.steps // 2), 2)
     print(json.dumps(line), flush=True)
 
 
