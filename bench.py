@@ -26,6 +26,14 @@ kappa = exp(sin(2 pi x) cos(2 pi y) z) interpolated in P6, u and v ~ N(0,1)
 in FP32): one step = y = A(kappa) u, then grad_u = A(kappa)^T v and
 grad_kappa = v^T (dA/dkappa) u, in FP32 with the FP64 path beside it.
 
+Under "mixed_degree": the batched mixed-degree workload (first 400,000
+tetrahedra of the 41^3 x 6 mesh, degree p in 1..8 per cell with P(p) ~ 1/p,
+quadrature degree 2p, mass form of a discontinuous space, cells in one
+contiguous block per degree, one block-diagonal CSR of 1.14e9 entries): one
+step = the numeric phase of all eight blocks (per-degree tiles from the
+autotuner) replayed as one HIP graph, FP16 storage / FP32 accumulation, the
+FP64 path beside it.
+
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -70,6 +78,10 @@ def parse():
                     help="skip the action / vector-Jacobian product measurement")
     ap.add_argument("--action-cpu-cells", type=int, default=0,
                     help="cells of the oracle baseline sample of the action step (0 = all)")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-degree batch measurement")
+    ap.add_argument("--mixed-cpu-cells", type=int, default=240000,
+                    help="cells (first n of the mesh) of the oracle sample of the mixed batch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB elementwise copy (x * 1.0), the reference "
                          "kernel for scaling hardware byte counters")
@@ -192,6 +204,81 @@ def action_section(args, steps, warmup):
             "value": n / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} of {m.n_cells} cells (first n): action + VJP local vectors and "
                       f"vector assembly (FP64, {threads} OpenMP threads), one pass of {dt:.1f} s"}
+    return out
+
+
+def mixed_section(args, steps, warmup):
+    """Mixed-degree batch: one graph launch for the eight degree blocks."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from fe_inputs import mixed_degree_blocks
+    from paper_2410_12614_amd import api
+
+    blocks = mixed_degree_blocks()
+    spec = [(b.degree, b.quad_degree, b.cell_coords, b.dofmap) for b in blocks]
+    n_cells = sum(b.n_cells for b in blocks)
+    out = {"workload": "mixed-degree DG mass, first 400,000 tets of 41^3 x 6 jittered Kuhn mesh, "
+                       "p in 1..8 with P(p) ~ 1/p, quadrature degree 2p, one block per degree, "
+                       "one block-diagonal CSR",
+           "n_cells": n_cells, "cells_per_degree": {str(b.degree): b.n_cells for b in blocks}}
+    md = api.MixedDegree(spec, "mass", "fp16")
+    tuned = md.tune(reps=3)
+    md.capture()
+    ms = time_steps(md.numeric, steps, warmup)
+    if any(st != 0 for st in md.status()):
+        raise RuntimeError("device status after the mixed batch")
+    v16 = md.numeric().clone()
+    nnz = md.nnz
+    out["tiles"] = {str(d): t for d, t, _ in tuned}
+    del md
+    torch.cuda.empty_cache()
+    md64 = api.MixedDegree(spec, "mass", "fp64")
+    md64.tune(reps=1)
+    md64.capture()
+    ms64 = time_steps(md64.numeric, max(3, steps // 2), 1)
+    v64 = md64.numeric()
+    torch.cuda.synchronize()
+    err = float(torch.linalg.vector_norm(v16.double() - v64) / torch.linalg.vector_norm(v64))
+    del md64, v64, v16
+    torch.cuda.empty_cache()
+    # algorithmic work: matrix-core flops 2 n_phi^2 n_q per cell, bytes = the
+    # cells' coordinates read once and the values (4 B) written once
+    flops = sum(b.n_cells * 2 * b.n_phi ** 2 * (b.degree + 1) ** 3 for b in blocks)
+    nbytes = 96 * n_cells + 4 * nnz
+    t = ms / 1e3
+    ideal = {"hbm": nbytes / (PEAK_HBM_GBS * 1e9), "mfma": flops / (PEAK_MFMA_TFLOPS["fp16"] * 1e12)}
+    bound = max(ideal, key=ideal.get)
+    if bound == "hbm":
+        roof = {"bound": "hbm", "achieved": nbytes / t / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    else:
+        roof = {"bound": "mfma", "achieved": flops / t / 1e12, "peak": PEAK_MFMA_TFLOPS["fp16"],
+                "unit": "TFLOP/s"}
+    roof.update({"frac": roof["achieved"] / roof["peak"], "traffic": None,
+                 "kernel": "cell_kernel per degree block (one graph launch)",
+                 "ideal_us": {k: v * 1e6 for k, v in ideal.items()}, "alg_flops": flops,
+                 "alg_bytes": nbytes})
+    out.update({"metric": "cells/s (mixed-degree numeric phase, one graph launch)",
+                "value": n_cells / t, "unit": "cells/s", "dtype": "f16 x f16 -> f32",
+                "ms_per_step": ms, "nnz": nnz,
+                "fp64_path": {"value": n_cells / (ms64 / 1e3), "ms_per_step": ms64},
+                "speedup_vs_fp64": ms64 / ms, "rel_err_vs_fp64": err, "roofline": roof})
+    if not args.no_cpu_baseline:
+        n = min(args.mixed_cpu_cells, n_cells)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+        t0 = time.perf_counter()
+        for b in blocks:
+            sel = b.cell_ids < n       # the first n cells of the source mesh
+            if sel.any():
+                oracle.local_matrices("mass", b.cell_coords[sel], b.degree, b.quad_degree,
+                                      nthreads=threads)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": n / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} of {n_cells} cells (all degrees, same mix): local matrices "
+                      f"(FP64, {threads} OpenMP threads; the block-diagonal assembly is the "
+                      f"local matrices themselves), one pass of {dt:.1f} s"}
     return out
 
 
@@ -339,10 +426,13 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(mesh, args.cpu_sample_cells, args.cpu_reps)
+    del asm
+    torch.cuda.empty_cache()
     if not args.no_action:
-        del asm
-        torch.cuda.empty_cache()
         line["action_vjp"] = action_section(args, max(3, args.steps // 2), 2)
+    if not args.no_mixed:
+        torch.cuda.empty_cache()
+        line["mixed_degree"] = mixed_section(args, max(3, args.steps // 2), 2)
     print(json.dumps(line), flush=True)
 
 

@@ -270,3 +270,60 @@ def config_mesh(name: str, n: Optional[int] = None, degree: Optional[int] = None
     return Mesh(d=d, n=n, degree=p, vertices=verts, cells=cells, lattice=lattice,
                 cell_coords=np.ascontiguousarray(cell_coords), dofmap=np.ascontiguousarray(dofmap),
                 n_dofs=n_dofs, flattened=flat, coeff=coeff)
+
+
+@dataclass
+class DegreeBlock:
+    """Cells of one degree of a mixed-degree mesh, with a discontinuous dof
+    map numbered block-locally (dof of local index i in block cell K:
+    K n_phi + i); the block's dofs follow those of the earlier blocks."""
+
+    degree: int
+    quad_degree: int
+    cell_coords: np.ndarray      # [n_K][d+1][d] float64
+    dofmap: np.ndarray           # [n_K][n_phi] int32, block-local numbering
+    n_dofs: int
+    dof_offset: int              # first global dof of the block
+    nnz_offset: int              # first CSR entry of the block
+    cell_ids: np.ndarray         # [n_K] indices of the cells in the source mesh
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.cell_coords.shape[0])
+
+    @property
+    def n_phi(self) -> int:
+        return int(self.dofmap.shape[1])
+
+
+def mixed_degree_blocks(n: int = 41, n_cells: int = 400_000, degrees=range(1, 9),
+                        jitter: float = 0.25, seed: int = 0, degree_seed: int = 2,
+                        cell_limit: Optional[int] = None) -> list:
+    """The mixed-degree workload: the first ``n_cells`` tetrahedra of the
+    jittered n^3 x 6 Kuhn mesh, a degree p drawn per cell with P(p) ~ 1/p
+    (``numpy.random.default_rng(degree_seed)``), quadrature degree 2p, and
+    the cells grouped into one contiguous block per degree (degree order,
+    source order inside a block) with a discontinuous dof map, so the global
+    matrix is block diagonal with sum_K n_phi(p_K)^2 entries.
+    ``cell_limit`` keeps only the first cells (reduced test sizes)."""
+    verts, cells, _ = kuhn_mesh(3, n)
+    verts = jitter_interior(verts, n, jitter, seed, cells)
+    cc = verts[cells[:n_cells]]
+    degs = np.asarray(list(degrees))
+    prob = 1.0 / degs
+    prob /= prob.sum()
+    p_cell = np.random.default_rng(degree_seed).choice(degs, size=cc.shape[0], p=prob)
+    if cell_limit is not None:
+        cc, p_cell = cc[:cell_limit], p_cell[:cell_limit]
+    blocks, dof_off, nnz_off = [], 0, 0
+    for p in degs:
+        ids = np.flatnonzero(p_cell == p)
+        n_phi = math.comb(p + 3, 3)
+        dm, nd = dg_dofmap(ids.size, n_phi)
+        blocks.append(DegreeBlock(degree=int(p), quad_degree=int(2 * p),
+                                  cell_coords=np.ascontiguousarray(cc[ids]), dofmap=dm,
+                                  n_dofs=nd, dof_offset=dof_off, nnz_offset=nnz_off,
+                                  cell_ids=ids))
+        dof_off += nd
+        nnz_off += ids.size * n_phi * n_phi
+    return blocks

@@ -190,6 +190,58 @@ fe_status fe_cell_kernels(const fe_form_desc *f, const void *form_buf, const fe_
                           void *A_local, void *stream);
 
 /* ------------------------------------------------------------------------
+ * fe_cell_kernels_tile -- fe_cell_kernels with an explicit tile variant.
+ *
+ * tile = variant + 3 * occ, 0 <= tile < 6, or -1 for the default choice:
+ *   variant 0: 8-wave workgroups, B^T fragments and the weighted table
+ *              staged in LDS (forms with at most 4 row tiles of 16 whose
+ *              tables fit)
+ *   variant 1: 4-wave workgroups, fragments staged in LDS
+ *   variant 2: 4-wave workgroups, fragments and table read through the caches
+ *   occ 1    : twice the workgroups per compute unit of occ 0.
+ * Every variant sums every entry in the same order: results are bitwise
+ * identical across tiles.  FE_EUNSUPPORTED when the variant does not apply
+ * to the form; FE_EINVAL for a tile out of range; otherwise as
+ * fe_cell_kernels.
+ * ------------------------------------------------------------------------ */
+fe_status fe_cell_kernels_tile(const fe_form_desc *f, const void *form_buf, const fe_mesh_view *m,
+                               void *A_local, int32_t tile, void *stream);
+
+/* ------------------------------------------------------------------------
+ * fe_tune_cell_kernels -- autotuner of the cell-kernel tile for one form and
+ * mesh: runs every tile variant that applies (one warm-up launch, then
+ * `reps` timed launches with HIP events on the stream) and returns the
+ * fastest in *best_tile; times_ms (NULL or [6]) receives the average time
+ * per launch of each tile, -1 where the tile does not apply.  A_local is
+ * overwritten (the result of the last tile run).  SYNCHRONISES the stream.
+ * Errors: FE_EINVAL (reps < 1, NULL best_tile), FE_EUNSUPPORTED (no tile
+ * applies), and those of fe_cell_kernels.
+ * ------------------------------------------------------------------------ */
+fe_status fe_tune_cell_kernels(const fe_form_desc *f, const void *form_buf, const fe_mesh_view *m,
+                               void *A_local, int32_t reps, int32_t *best_tile, float *times_ms,
+                               void *stream);
+
+/* ------------------------------------------------------------------------
+ * fe_dg_pattern -- CSR pattern of a discontinuous Lagrange space over
+ * degree blocks (the mixed-degree mesh of Section 5 with its cells grouped
+ * by degree): block b holds n_cells[b] cells of n_phi[b] dofs numbered
+ * cell-major after the dofs of blocks 0..b-1, so the global matrix
+ * A^g = L D L^T (Section 3.3) is block diagonal and the row-major local
+ * matrices of the cells of block b, in cell order, are exactly its CSR
+ * values from entry sum_{b' < b} n_cells[b'] n_phi[b']^2 on: the numeric
+ * phase is fe_cell_kernels(_tile) per block writing into one values array.
+ *   n_cells, n_phi : host [n_blocks]; 1 <= n_phi[b] <= 1024
+ *   row_ptr  : device [n_dofs + 1] int64 (n_dofs = sum n_cells[b] n_phi[b])
+ *   col_idx  : device [nnz] int32, ascending per row
+ *   nnz      : out (host), sum n_cells[b] n_phi[b]^2; with row_ptr or col_idx
+ *              NULL only nnz is computed (size query)
+ * Asynchronous.  Errors: FE_EINVAL, FE_EOVERFLOW (n_dofs >= 2^31 - 1),
+ * FE_EHIP.
+ * ------------------------------------------------------------------------ */
+fe_status fe_dg_pattern(int32_t n_blocks, const int64_t *n_cells, const int32_t *n_phi,
+                        int64_t *row_ptr, int32_t *col_idx, int64_t *nnz, void *stream);
+
+/* ------------------------------------------------------------------------
  * fe_assemble_csr -- global assembly A^g = L D L^T into CSR (Section 3.3).
  *
  * The CSR pattern is the set of pairs (dof(K,i), dof(K,j)) over all cells,

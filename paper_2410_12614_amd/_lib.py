@@ -44,6 +44,9 @@ EXPORTS = (
     "fe_tabulate",
     "fe_form_prepare",
     "fe_cell_kernels",
+    "fe_cell_kernels_tile",
+    "fe_tune_cell_kernels",
+    "fe_dg_pattern",
     "fe_assemble_csr",
     "fe_vector_plan",
     "fe_action_vjp",
@@ -95,6 +98,15 @@ def load() -> ctypes.CDLL:
     lib.fe_form_prepare.restype = i32
     lib.fe_cell_kernels.argtypes = [ctypes.POINTER(fe_form_desc), P, ctypes.POINTER(fe_mesh_view), P, P]
     lib.fe_cell_kernels.restype = i32
+    lib.fe_cell_kernels_tile.argtypes = [ctypes.POINTER(fe_form_desc), P,
+                                         ctypes.POINTER(fe_mesh_view), P, i32, P]
+    lib.fe_cell_kernels_tile.restype = i32
+    lib.fe_tune_cell_kernels.argtypes = [ctypes.POINTER(fe_form_desc), P,
+                                         ctypes.POINTER(fe_mesh_view), P, i32,
+                                         ctypes.POINTER(i32), P, P]
+    lib.fe_tune_cell_kernels.restype = i32
+    lib.fe_dg_pattern.argtypes = [i32, P, P, P, P, ctypes.POINTER(ctypes.c_int64), P]
+    lib.fe_dg_pattern.restype = i32
     lib.fe_assemble_csr.argtypes = [ctypes.POINTER(fe_form_desc), ctypes.POINTER(P), i32,
                                     ctypes.POINTER(fe_mesh_view), i32, ctypes.POINTER(fe_csr), P,
                                     ctypes.POINTER(ctypes.c_size_t), P,

@@ -282,3 +282,112 @@ class ActionFunction(torch.autograd.Function):
         if gz is not None:
             gz = gz.to(torch.float64)
         return (gu if ctx.needs_input_grad[0] else None), gz, None
+
+
+def fe_cell_kernels_tile(desc: L.fe_form_desc, form_buf: torch.Tensor, mesh: MeshView,
+                         A_local: torch.Tensor, tile: int, stream=None) -> None:
+    mv = mesh.struct()
+    check(L.load().fe_cell_kernels_tile(ctypes.byref(desc), _ptr(form_buf), ctypes.byref(mv),
+                                        _ptr(A_local), int(tile), _stream(stream)),
+          "fe_cell_kernels_tile")
+
+
+def fe_tune_cell_kernels(desc: L.fe_form_desc, form_buf: torch.Tensor, mesh: MeshView,
+                         A_local: torch.Tensor, reps: int = 3, stream=None):
+    """(best tile, per-tile ms with -1 where a tile does not apply)."""
+    mv = mesh.struct()
+    best = ctypes.c_int32(-1)
+    times = (ctypes.c_float * 6)()
+    check(L.load().fe_tune_cell_kernels(ctypes.byref(desc), _ptr(form_buf), ctypes.byref(mv),
+                                        _ptr(A_local), int(reps), ctypes.byref(best),
+                                        ctypes.cast(times, ctypes.c_void_p), _stream(stream)),
+          "fe_tune_cell_kernels")
+    return int(best.value), [float(t) for t in times]
+
+
+def fe_dg_pattern(n_cells: Sequence[int], n_phi: Sequence[int], device="cuda", stream=None):
+    """(row_ptr int64 [n_dofs+1], col_idx int32 [nnz], nnz) of the block-diagonal
+    CSR of a discontinuous space over degree blocks."""
+    lib = L.load()
+    nb = len(n_cells)
+    nc = (ctypes.c_int64 * nb)(*[int(x) for x in n_cells])
+    npi = (ctypes.c_int32 * nb)(*[int(x) for x in n_phi])
+    nnz = ctypes.c_int64(0)
+    check(lib.fe_dg_pattern(nb, ctypes.cast(nc, ctypes.c_void_p), ctypes.cast(npi, ctypes.c_void_p),
+                            None, None, ctypes.byref(nnz), None), "fe_dg_pattern(size query)")
+    n_dofs = sum(int(c) * int(p) for c, p in zip(n_cells, n_phi))
+    row_ptr = torch.empty(n_dofs + 1, dtype=torch.int64, device=device)
+    col_idx = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=device)
+    check(lib.fe_dg_pattern(nb, ctypes.cast(nc, ctypes.c_void_p), ctypes.cast(npi, ctypes.c_void_p),
+                            _ptr(row_ptr), _ptr(col_idx), ctypes.byref(nnz), _stream(stream)),
+          "fe_dg_pattern")
+    return row_ptr, col_idx, int(nnz.value)
+
+
+class MixedDegree:
+    """One form over the degree blocks of a mixed-degree discontinuous mesh,
+    assembled into one block-diagonal CSR matrix.
+
+    ``blocks``: (degree, quad_degree, cell_coords [n][4][3], dofmap [n][n_phi])
+    per block, dofs numbered block-locally (the library places block b after
+    blocks 0..b-1).  The numeric phase is one fe_cell_kernels_tile call per
+    block, each writing its cells' local matrices into its slice of the CSR
+    values; ``tune()`` picks every block's tile with fe_tune_cell_kernels and
+    ``capture()`` records the calls of all blocks in one HIP graph, so that
+    ``numeric()`` is a single graph launch."""
+
+    def __init__(self, blocks, form: str = "mass", precision: str = "fp16", stream=None):
+        self.stream = stream
+        self.blocks = []
+        n_cells, n_phi = [], []
+        for (p, q, coords, dofmap) in blocks:
+            mv = MeshView.from_numpy(coords, dofmap, max(int(np.asarray(dofmap).size), 1))
+            desc = form_desc(3, p, q, form, precision)
+            self.blocks.append({"degree": p, "mesh": mv, "desc": desc,
+                                "form_buf": fe_form_prepare(desc, "cuda", stream), "tile": -1})
+            n_cells.append(mv.n_cells)
+            n_phi.append(int(np.asarray(dofmap).shape[1]))
+        self.row_ptr, self.col_idx, self.nnz = fe_dg_pattern(n_cells, n_phi, "cuda", stream)
+        dt = torch.float64 if precision == "fp64" else torch.float32
+        self.values = torch.empty(max(self.nnz, 1), dtype=dt, device="cuda")
+        off = 0
+        for b, nc, npi in zip(self.blocks, n_cells, n_phi):
+            b["values"] = self.values[off:off + nc * npi * npi]
+            off += nc * npi * npi
+        self.graph = None
+
+    def tune(self, reps: int = 3) -> list:
+        """Autotune every block's tile; returns (degree, tile, per-tile ms)."""
+        out = []
+        for b in self.blocks:
+            if b["mesh"].n_cells == 0:
+                continue
+            b["tile"], times = fe_tune_cell_kernels(b["desc"], b["form_buf"], b["mesh"],
+                                                    b["values"], reps, self.stream)
+            out.append((b["degree"], b["tile"], times))
+        self.graph = None
+        return out
+
+    def numeric_eager(self) -> torch.Tensor:
+        for b in self.blocks:
+            if b["mesh"].n_cells > 0:
+                fe_cell_kernels_tile(b["desc"], b["form_buf"], b["mesh"], b["values"], b["tile"],
+                                     self.stream)
+        return self.values
+
+    def capture(self) -> None:
+        self.numeric_eager()                 # first launches outside the capture
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.numeric_eager()
+        self.graph = g
+
+    def numeric(self) -> torch.Tensor:
+        if self.graph is None:
+            return self.numeric_eager()
+        self.graph.replay()
+        return self.values
+
+    def status(self) -> list:
+        return [fe_get_device_status(b["form_buf"], self.stream) for b in self.blocks]

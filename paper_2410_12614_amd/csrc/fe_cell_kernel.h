@@ -540,7 +540,7 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
 }
 
 template <class P, int MT, int JC, int NDT, bool COEFF, int STAGE, int NW>
-static fe_status launch_one(const KArgs &k, int64_t n_cells, size_t smem, hipStream_t s) {
+static fe_status launch_one(const KArgs &k, int64_t n_cells, size_t smem, int occ, hipStream_t s) {
   auto kern = cell_kernel<P, MT, JC, NDT, COEFF, STAGE, NW>;
   if (smem > 65536) {
     if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -552,21 +552,22 @@ static fe_status launch_one(const KArgs &k, int64_t n_cells, size_t smem, hipStr
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return FE_EHIP;
   const int64_t nbatch = (n_cells + 15) / 16;
-  // eight waves per compute unit: two 4-wave or one 8-wave workgroup
-  const int per_cu = (NW == 4 && smem <= 80 * 1024) ? 2 : 1;
+  // eight waves per compute unit: two 4-wave or one 8-wave workgroup (occ
+  // doubles the workgroups; those the LDS cannot hold wait for a slot)
+  const int per_cu = ((NW == 4 && smem <= 80 * 1024) ? 2 : 1) << occ;
   const int64_t blocks = std::min<int64_t>(nbatch, (int64_t)ncu * per_cu);
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(NW * 64), smem, s, k);
   return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
 }
 
 template <class P, int MT, int JC, int NW, int STAGE>
-static fe_status launch_mt(const KArgs &k, int64_t n_cells, size_t smem, hipStream_t s, int ndt,
-                           bool coeff) {
+static fe_status launch_mt(const KArgs &k, int64_t n_cells, size_t smem, int occ, hipStream_t s,
+                           int ndt, bool coeff) {
   if (ndt == 1)
-    return coeff ? launch_one<P, MT, JC, 1, true, STAGE, NW>(k, n_cells, smem, s)
-                 : launch_one<P, MT, JC, 1, false, STAGE, NW>(k, n_cells, smem, s);
-  return coeff ? launch_one<P, MT, JC, 3, true, STAGE, NW>(k, n_cells, smem, s)
-               : launch_one<P, MT, JC, 3, false, STAGE, NW>(k, n_cells, smem, s);
+    return coeff ? launch_one<P, MT, JC, 1, true, STAGE, NW>(k, n_cells, smem, occ, s)
+                 : launch_one<P, MT, JC, 1, false, STAGE, NW>(k, n_cells, smem, occ, s);
+  return coeff ? launch_one<P, MT, JC, 3, true, STAGE, NW>(k, n_cells, smem, occ, s)
+               : launch_one<P, MT, JC, 3, false, STAGE, NW>(k, n_cells, smem, occ, s);
 }
 
 template <class P>
@@ -600,35 +601,49 @@ fe_status launch_cell_impl(const CellLaunch &a) {
   const size_t wtab_bytes = (size_t)L.ndt * L.n_phi * L.n_q_pad * sizeof(typename P::hreal);
   hipStream_t s = (hipStream_t)a.stream;
   const int ndt = L.ndt;
-  // 8-wave workgroups with fragments and weighted table in LDS when both fit
-  // (small forms: row tiles <= 4); else 4-wave workgroups, fragments staged
-  // when they fit beside the coefficient tables.
-  {
-    const size_t zbytes8 = coeff ? (size_t)16 * L.n_q_pad * sizeof(typename P::zreal) +
-                                       (size_t)16 * L.n_phi * 8 + 512 * 8
-                                 : 0;
-    const size_t smem8 = frag_bytes + wtab_bytes + zbytes8;
-    if (mt <= 4 && smem8 <= 156 * 1024) {
-      int jc8 = 0;
-      if (mt == 1) jc8 = 2;
-      if (mt == 2) jc8 = 4;
-      if (mt == 3) jc8 = 5;
-      if (mt == 4) jc8 = (P::REGMUL == 1) ? 7 : 4;
-#define FE_C8(M, J) \
-  if (mt == M && jc8 == J) return launch_mt<P, M, J, 8, 2>(k, a.n_cells, smem8, s, ndt, coeff);
-      FE_C8(1, 2) FE_C8(2, 4) FE_C8(3, 5) FE_C8(4, 7) FE_C8(4, 4)
-#undef FE_C8
-    }
-  }
+  // Tile variants (CellLaunch::tile = variant + 3 occ):
+  //   0: 8-wave workgroups, fragments and weighted table in LDS (small forms:
+  //      row tiles <= 4, both fit)
+  //   1: 4-wave workgroups, fragments in LDS (they fit beside the
+  //      coefficient tables)
+  //   2: 4-wave workgroups, fragments and table read through the caches
+  // occ = 1 launches twice the workgroups per compute unit.  The default
+  // (tile < 0) is the first variant that applies, occ = 0.  Every variant
+  // sums each entry in the same order, so all give identical results.
+  const size_t zbytes8 = coeff ? (size_t)16 * L.n_q_pad * sizeof(typename P::zreal) +
+                                     (size_t)16 * L.n_phi * 8 + 512 * 8
+                               : 0;
+  const size_t smem8 = frag_bytes + wtab_bytes + zbytes8;
   const size_t zbytes = coeff ? (size_t)16 * L.n_q_pad * sizeof(typename P::zreal) +
                                     (size_t)16 * L.n_phi * 8 + 256 * 8
                               : 0;
-  const bool stage = frag_bytes + zbytes <= 80 * 1024;
+  const bool ok8 = mt <= 4 && smem8 <= 156 * 1024;
+  const bool ok1 = frag_bytes + zbytes <= 80 * 1024;
+  int variant = ok8 ? 0 : (ok1 ? 1 : 2), occ = 0;
+  if (a.tile >= 0) {
+    variant = a.tile % 3;
+    occ = a.tile / 3;
+    if (occ > 1) return FE_EINVAL;
+    if ((variant == 0 && !ok8) || (variant == 1 && !ok1)) return FE_EUNSUPPORTED;
+  }
+  if (variant == 0) {
+    int jc8 = 0;
+    if (mt == 1) jc8 = 2;
+    if (mt == 2) jc8 = 4;
+    if (mt == 3) jc8 = 5;
+    if (mt == 4) jc8 = (P::REGMUL == 1) ? 7 : 4;
+#define FE_C8(M, J) \
+  if (mt == M && jc8 == J) return launch_mt<P, M, J, 8, 2>(k, a.n_cells, smem8, occ, s, ndt, coeff);
+    FE_C8(1, 2) FE_C8(2, 4) FE_C8(3, 5) FE_C8(4, 7) FE_C8(4, 4)
+#undef FE_C8
+    return FE_EUNSUPPORTED;
+  }
+  const bool stage = variant == 1;
   const size_t smem = (stage ? frag_bytes : 0) + zbytes;
-#define FE_CASE(M, J)                                                                   \
-  if (mt == M && jc == J) {                                                             \
-    if (stage) return launch_mt<P, M, J, 4, 1>(k, a.n_cells, smem, s, ndt, coeff);      \
-    return launch_mt<P, M, J, 4, 0>(k, a.n_cells, smem, s, ndt, coeff);                 \
+#define FE_CASE(M, J)                                                                        \
+  if (mt == M && jc == J) {                                                                  \
+    if (stage) return launch_mt<P, M, J, 4, 1>(k, a.n_cells, smem, occ, s, ndt, coeff);      \
+    return launch_mt<P, M, J, 4, 0>(k, a.n_cells, smem, occ, s, ndt, coeff);                 \
   }
   if constexpr (P::REGMUL == 1) {
     FE_CASE(1, 4) FE_CASE(2, 8) FE_CASE(3, 9) FE_CASE(4, 7) FE_CASE(6, 7) FE_CASE(8, 6)

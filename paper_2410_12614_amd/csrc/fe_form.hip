@@ -275,10 +275,10 @@ fe_status launch_cell(const CellLaunch &a) {
   }
   return FE_EUNSUPPORTED;
 }
-}  // namespace fe
 
-extern "C" fe_status fe_cell_kernels(const fe_form_desc *f, const void *form_buf,
-                                     const fe_mesh_view *m, void *A_local, void *stream) {
+namespace {
+fe_status cell_kernels(const fe_form_desc *f, const void *form_buf, const fe_mesh_view *m,
+                       void *A_local, int tile, void *stream) {
   FormLayout L;
   fe_status st = compute_layout(f, &L);
   if (st != FE_OK) return st;
@@ -298,7 +298,112 @@ extern "C" fe_status fe_cell_kernels(const fe_form_desc *f, const void *form_buf
   a.coeff = f->has_coeff ? m->coeff : nullptr;
   a.A_local = A_local;
   a.stream = stream;
+  a.tile = tile;
   return launch_cell(a);
+}
+
+// Block-diagonal CSR pattern of a discontinuous space over degree blocks:
+// row r of block b (cell K = r / n_phi_b) holds the n_phi_b dofs of K.
+__global__ void k_dg_pattern(int64_t n_rows, int n_phi, int64_t dof_off, int64_t nnz_off,
+                             int64_t *row_ptr, int32_t *col_idx) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t start = nnz_off + r * n_phi;
+    row_ptr[dof_off + r] = start;
+    const int64_t first = dof_off + (r / n_phi) * n_phi;
+    for (int j = 0; j < n_phi; ++j) col_idx[start + j] = (int32_t)(first + j);
+  }
+}
+
+__global__ void k_set_i64(int64_t *x, int64_t v) { *x = v; }
+}  // namespace
+}  // namespace fe
+
+extern "C" fe_status fe_cell_kernels(const fe_form_desc *f, const void *form_buf,
+                                     const fe_mesh_view *m, void *A_local, void *stream) {
+  return cell_kernels(f, form_buf, m, A_local, -1, stream);
+}
+
+extern "C" fe_status fe_cell_kernels_tile(const fe_form_desc *f, const void *form_buf,
+                                          const fe_mesh_view *m, void *A_local, int32_t tile,
+                                          void *stream) {
+  if (tile < -1 || tile >= CELL_TILES) return FE_EINVAL;
+  return cell_kernels(f, form_buf, m, A_local, tile, stream);
+}
+
+extern "C" fe_status fe_tune_cell_kernels(const fe_form_desc *f, const void *form_buf,
+                                          const fe_mesh_view *m, void *A_local, int32_t reps,
+                                          int32_t *best_tile, float *times_ms, void *stream) {
+  if (!best_tile || reps < 1) return FE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return FE_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return FE_EHIP;
+  }
+  fe_status result = FE_EUNSUPPORTED;
+  float best = 0.0f;
+  *best_tile = -1;
+  for (int t = 0; t < CELL_TILES; ++t) {
+    if (times_ms) times_ms[t] = -1.0f;
+    fe_status st = cell_kernels(f, form_buf, m, A_local, t, stream);  // warm-up
+    if (st == FE_EUNSUPPORTED) continue;
+    if (st != FE_OK) {
+      result = st;
+      break;
+    }
+    if (hipEventRecord(e0, s) != hipSuccess) {
+      result = FE_EHIP;
+      break;
+    }
+    for (int r = 0; r < reps && st == FE_OK; ++r) st = cell_kernels(f, form_buf, m, A_local, t, stream);
+    float ms = 0.0f;
+    if (st != FE_OK || hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      result = st != FE_OK ? st : FE_EHIP;
+      break;
+    }
+    ms /= (float)reps;
+    if (times_ms) times_ms[t] = ms;
+    if (*best_tile < 0 || ms < best) {
+      best = ms;
+      *best_tile = t;
+    }
+    result = FE_OK;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return result;
+}
+
+extern "C" fe_status fe_dg_pattern(int32_t n_blocks, const int64_t *n_cells, const int32_t *n_phi,
+                                   int64_t *row_ptr, int32_t *col_idx, int64_t *nnz,
+                                   void *stream) {
+  if (n_blocks < 1 || !n_cells || !n_phi || !nnz) return FE_EINVAL;
+  int64_t dofs = 0, entries = 0;
+  for (int b = 0; b < n_blocks; ++b) {
+    if (n_cells[b] < 0 || n_phi[b] < 1 || n_phi[b] > 1024) return FE_EINVAL;
+    dofs += n_cells[b] * n_phi[b];
+    entries += n_cells[b] * n_phi[b] * n_phi[b];
+  }
+  if (dofs >= INT32_MAX) return FE_EOVERFLOW;
+  *nnz = entries;
+  if (!row_ptr || !col_idx) return FE_OK;  // size query
+  hipStream_t s = (hipStream_t)stream;
+  int64_t dof_off = 0, nnz_off = 0;
+  for (int b = 0; b < n_blocks; ++b) {
+    const int64_t rows = n_cells[b] * n_phi[b];
+    if (rows > 0) {
+      const unsigned grid = (unsigned)std::min<int64_t>((rows + 255) / 256, 65536);
+      hipLaunchKernelGGL(k_dg_pattern, dim3(grid), dim3(256), 0, s, rows, n_phi[b], dof_off,
+                         nnz_off, row_ptr, col_idx);
+    }
+    dof_off += rows;
+    nnz_off += rows * n_phi[b];
+  }
+  hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, row_ptr + dof_off, nnz_off);
+  return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
 }
 
 extern "C" fe_status fe_get_device_status(const void *buf, void *stream) {
