@@ -192,12 +192,15 @@ fe_status fe_cell_kernels(const fe_form_desc *f, const void *form_buf, const fe_
 /* ------------------------------------------------------------------------
  * fe_cell_kernels_tile -- fe_cell_kernels with an explicit tile variant.
  *
- * tile = variant + 3 * occ, 0 <= tile < 6, or -1 for the default choice:
+ * tile = variant + 4 * occ, 0 <= tile < 8, or -1 for the default choice:
  *   variant 0: 8-wave workgroups, B^T fragments and the weighted table
  *              staged in LDS (forms with at most 4 row tiles of 16 whose
  *              tables fit)
  *   variant 1: 4-wave workgroups, fragments staged in LDS
  *   variant 2: 4-wave workgroups, fragments and table read through the caches
+ *   variant 3: 8-wave workgroups, fragments and table streamed through a
+ *              double-buffered LDS ring one quadrature chunk at a time
+ *              (not for FE_SPLITFP16_ACC32)
  *   occ 1    : twice the workgroups per compute unit of occ 0.
  * Every variant sums every entry in the same order: results are bitwise
  * identical across tiles.  FE_EUNSUPPORTED when the variant does not apply
@@ -211,7 +214,7 @@ fe_status fe_cell_kernels_tile(const fe_form_desc *f, const void *form_buf, cons
  * fe_tune_cell_kernels -- autotuner of the cell-kernel tile for one form and
  * mesh: runs every tile variant that applies (one warm-up launch, then
  * `reps` timed launches with HIP events on the stream) and returns the
- * fastest in *best_tile; times_ms (NULL or [6]) receives the average time
+ * fastest in *best_tile; times_ms (NULL or [8]) receives the average time
  * per launch of each tile, -1 where the tile does not apply.  A_local is
  * overwritten (the result of the last tile run).  SYNCHRONISES the stream.
  * Errors: FE_EINVAL (reps < 1, NULL best_tile), FE_EUNSUPPORTED (no tile

@@ -322,11 +322,15 @@ __device__ __forceinline__ typename P::frag lds_frag(const unsigned char *base, 
   return *(const typename P::frag *)(base + idx * sizeof(typename P::frag));
 }
 
-// Persistent cell kernel: each workgroup (NW waves) walks batches of 16
-// cells.  STAGE >= 1 copies the B^T fragments of the whole K range into LDS
-// once; STAGE == 2 also copies the weighted table (the 16 lanes of a K-slot
-// read one row j, a broadcast).  Both are then shared by all waves for every
-// batch.
+// Persistent cell kernel: each workgroup (NW waves) walks work items of 16
+// cells (one batch, or one pass over its columns).  STAGE 1 or 2 copies the B^T fragments of the whole K range into
+// LDS once; STAGE == 2 also copies the weighted table (the 16 lanes of a
+// K-slot read one row j, a broadcast).  Both are then shared by all waves for
+// every batch.  STAGE == 3 streams them instead: per quadrature chunk the
+// fragments of the chunk (contiguous in the chunk-major layout) and the
+// chunk's slice of the weighted table pass through a double-buffered LDS
+// ring filled by the whole workgroup, the next chunk's loads in flight
+// during the current chunk's math (forms whose tables do not fit on chip).
 template <class P, int MT, int JC, int NDT, bool COEFF, int STAGE, int NW>
 __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
   typedef typename P::real T;
@@ -340,7 +344,15 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
   const int d = a.d, nphi = a.n_phi, n_q_pad = a.n_q_pad, nks = a.nks;
 
   constexpr int NT = NW * 64;
-  const size_t frag_bytes = STAGE >= 1 ? (size_t)MT * nks * 64 * sizeof(FRAG) : 0;
+  static_assert(STAGE != 3 || !P::SPLIT, "streamed chunks carry one fragment set");
+  // STAGE 3: one ring slot = the chunk's fragments, then its table slice
+  // [t][j][KSTEP]; two slots
+  constexpr size_t CFRAG = (size_t)NDT * MT * 64 * sizeof(FRAG);
+  const size_t ctab = (size_t)NDT * nphi * P::KSTEP * sizeof(HT);
+  const size_t cslot = (CFRAG + ctab + 15) / 16 * 16;
+  const size_t frag_bytes = (STAGE == 1 || STAGE == 2) ? (size_t)MT * nks * 64 * sizeof(FRAG)
+                            : STAGE == 3                ? 2 * cslot
+                                                        : 0;
   const size_t wtab_bytes = STAGE == 2 ? (size_t)NDT * nphi * n_q_pad * sizeof(HT) : 0;
   unsigned char *s_af = smem;
   unsigned char *s_afl = smem + frag_bytes;
@@ -350,7 +362,7 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
   double *zloc = (double *)(zbase + (size_t)16 * n_q_pad * sizeof(Z));  // [16][n_phi]
   double *zred = zloc + 16 * nphi;                                      // [NT]
 
-  if constexpr (STAGE >= 1) {
+  if constexpr (STAGE == 1 || STAGE == 2) {
     const size_t n16 = frag_bytes / 16;
     const uint4 *src = (const uint4 *)a.afrag;
     uint4 *dst = (uint4 *)s_af;
@@ -365,10 +377,33 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
     const size_t n16 = wtab_bytes / 16;
     for (size_t t = tid; t < n16; t += NT) ((uint4 *)s_wt)[t] = ((const uint4 *)a.wtab)[t];
   }
-  if constexpr (STAGE >= 1) __syncthreads();
+  if constexpr (STAGE == 1 || STAGE == 2) __syncthreads();
+  // STAGE 3: copy quadrature chunk qc into ring slot `slot` (all threads),
+  // through registers so that the loads can be issued early
+  // (n_phi <= 16 MT bounds the table slice of a chunk)
+  constexpr int PRE =
+      STAGE == 3 ? (int)((CFRAG + (size_t)NDT * 16 * MT * P::KSTEP * sizeof(HT)) / 16 + NT - 1) / NT
+                 : 1;
+  const int c16 = (int)(CFRAG / 16), t16 = (int)(ctab / 16), n16c = c16 + t16;
+  const int trow16 = P::KSTEP * (int)sizeof(HT) / 16;  // 16-byte pieces per table row slice
+  auto chunk_src = [&](int qc, int e) -> const uint4 * {
+    if (e < c16) return (const uint4 *)(a.afrag + (size_t)qc * CFRAG) + e;
+    const int r = (e - c16) / trow16, piece = (e - c16) - r * trow16;  // row r = t * nphi + j
+    return (const uint4 *)((const HT *)a.wtab + (size_t)r * n_q_pad + (size_t)qc * P::KSTEP) +
+           piece;
+  };
 
+  // Work items: without a coefficient one (batch of 16 cells, pass over
+  // NW * JC columns) per item, so that large forms spread evenly over the
+  // workgroups; with one, a whole batch (its coefficient values at the
+  // quadrature points are shared by the passes).
   const int64_t nbatch = (a.n_cells + 15) / 16;
-  for (int64_t batch = blockIdx.x; batch < nbatch; batch += gridDim.x) {
+  const int npass = (nphi + NW * JC - 1) / (NW * JC);
+  const int64_t nitems = COEFF ? nbatch : nbatch * npass;
+  for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int64_t batch = COEFF ? item : item / npass;
+    const int pass_lo = COEFF ? 0 : (int)(item - batch * npass);
+    const int pass_hi = COEFF ? npass : pass_lo + 1;
     const int64_t cell0 = batch * 16;
     const int64_t cell = cell0 + c;
     const bool valid = cell < a.n_cells;
@@ -419,10 +454,10 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
     cell_factors<P>(a.hdr, a.nd, valid, ok, G, adet, zmax, Gp, inv);
 
     const HT *wt = (const HT *)a.wtab;
-    const int npass = (nphi + NW * JC - 1) / (NW * JC);
-    for (int pass = 0; pass < npass; ++pass) {
+    for (int pass = pass_lo; pass < pass_hi; ++pass) {
       const int jb = pass * NW * JC + wave * JC;
-      if (jb >= nphi) continue;
+      if (STAGE != 3 && jb >= nphi) continue;
+      const bool active = jb < nphi;
       ACC acc[MT][JC];
       ACC acc2[P::SPLIT ? MT : 1][P::SPLIT ? JC : 1];
 #pragma unroll
@@ -437,8 +472,23 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
       // output is (chunk 0: s = 0..NDT-1), (chunk 1: ...), as in the fused
       // kernel.
       const int nqc = n_q_pad / P::KSTEP;
+      if constexpr (STAGE == 3) {
+        for (int e = tid; e < n16c; e += NT) ((uint4 *)s_af)[e] = *chunk_src(0, e);
+        __syncthreads();
+      }
       for (int qc = 0; qc < nqc; ++qc) {
         const int qb = qc * P::KSTEP + kb * P::KPL;
+        uint4 pre[PRE];
+        unsigned char *slot = s_af + (size_t)(qc & 1) * cslot;
+        if constexpr (STAGE == 3) {
+          if (qc + 1 < nqc) {
+#pragma unroll
+            for (int p = 0; p < PRE; ++p) {
+              const int e = tid + p * NT;
+              if (e < n16c) pre[p] = *chunk_src(qc + 1, e);
+            }
+          }
+        }
         FRAG afr[NDT][MT];
         FRAG afl[P::SPLIT ? NDT : 1][P::SPLIT ? MT : 1];
 #pragma unroll
@@ -446,7 +496,9 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
             const size_t fi = frag_slot(mt, s, qc, MT, NDT) * 64 + lane;
-            if constexpr (STAGE >= 1) {
+            if constexpr (STAGE == 3) {
+              afr[s][mt] = lds_frag<P>(slot, ((size_t)s * MT + mt) * 64 + lane);
+            } else if constexpr (STAGE >= 1) {
               afr[s][mt] = lds_frag<P>(s_af, fi);
               if constexpr (P::SPLIT) afl[s][mt] = lds_frag<P>(s_afl, fi);
             } else {
@@ -461,12 +513,17 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
         }
 #pragma unroll
         for (int jj = 0; jj < JC; ++jj) {
+          if (STAGE == 3 && !active) break;
           const int jl = min(jb + jj, nphi - 1);
-          const HT *wj = (STAGE == 2 ? s_wt : wt) + (size_t)jl * n_q_pad + qb;
+          // row stride of the table between derivative slabs t, and the
+          // start of row jl at this lane's K entries
+          const size_t tstride = STAGE == 3 ? (size_t)nphi * P::KSTEP : (size_t)nphi * n_q_pad;
+          const HT *wj = STAGE == 3 ? (const HT *)(slot + CFRAG) + (size_t)jl * P::KSTEP + kb * P::KPL
+                         : (STAGE == 2 ? s_wt : wt) + (size_t)jl * n_q_pad + qb;
           if constexpr (P::H16) {
             half8_t wv[NDT];
 #pragma unroll
-            for (int t = 0; t < NDT; ++t) wv[t] = *(const half8_t *)(wj + (size_t)t * nphi * n_q_pad);
+            for (int t = 0; t < NDT; ++t) wv[t] = *(const half8_t *)(wj + (size_t)t * tstride);
 #pragma unroll
             for (int s = 0; s < NDT; ++s) {
               half2_t g2[NDT];
@@ -485,7 +542,7 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
           } else {
             T wv[NDT][P::KPL];
 #pragma unroll
-            for (int t = 0; t < NDT; ++t) load_w<T, P::KPL>(wj + (size_t)t * nphi * n_q_pad, wv[t]);
+            for (int t = 0; t < NDT; ++t) load_w<T, P::KPL>(wj + (size_t)t * tstride, wv[t]);
 #pragma unroll
             for (int s = 0; s < NDT; ++s) {
               T h[P::KPL];
@@ -511,11 +568,24 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
             }
           }
         }
+        if constexpr (STAGE == 3) {
+          // the other ring slot was last read in chunk qc - 1, which every
+          // wave finished before the barrier closing that chunk
+          if (qc + 1 < nqc) {
+            uint4 *dst = (uint4 *)(s_af + (size_t)((qc + 1) & 1) * cslot);
+#pragma unroll
+            for (int p = 0; p < PRE; ++p) {
+              const int e = tid + p * NT;
+              if (e < n16c) dst[e] = pre[p];
+            }
+          }
+          __syncthreads();
+        }
       }
       // The tile holds column j of A_K (rows i); by the symmetry of the mass
       // and stiffness forms it is stored as row j, so each lane's rows land
       // on consecutive addresses.
-      if (valid) {
+      if (valid && active) {
         T *A = (T *)a.A + (size_t)cell * nphi * nphi;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
@@ -551,11 +621,13 @@ static fe_status launch_one(const KArgs &k, int64_t n_cells, size_t smem, int oc
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return FE_EHIP;
+  // work items as in the kernel: (batch, pass) without a coefficient
   const int64_t nbatch = (n_cells + 15) / 16;
+  const int64_t nitems = COEFF ? nbatch : nbatch * ((k.n_phi + NW * JC - 1) / (NW * JC));
   // eight waves per compute unit: two 4-wave or one 8-wave workgroup (occ
   // doubles the workgroups; those the LDS cannot hold wait for a slot)
   const int per_cu = ((NW == 4 && smem <= 80 * 1024) ? 2 : 1) << occ;
-  const int64_t blocks = std::min<int64_t>(nbatch, (int64_t)ncu * per_cu);
+  const int64_t blocks = std::min<int64_t>(nitems, (int64_t)ncu * per_cu);
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(NW * 64), smem, s, k);
   return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
 }
@@ -601,12 +673,14 @@ fe_status launch_cell_impl(const CellLaunch &a) {
   const size_t wtab_bytes = (size_t)L.ndt * L.n_phi * L.n_q_pad * sizeof(typename P::hreal);
   hipStream_t s = (hipStream_t)a.stream;
   const int ndt = L.ndt;
-  // Tile variants (CellLaunch::tile = variant + 3 occ):
+  // Tile variants (CellLaunch::tile = variant + 4 occ):
   //   0: 8-wave workgroups, fragments and weighted table in LDS (small forms:
   //      row tiles <= 4, both fit)
   //   1: 4-wave workgroups, fragments in LDS (they fit beside the
   //      coefficient tables)
   //   2: 4-wave workgroups, fragments and table read through the caches
+  //   3: 8-wave workgroups, fragments and table streamed through LDS one
+  //      quadrature chunk at a time (not for the split mode)
   // occ = 1 launches twice the workgroups per compute unit.  The default
   // (tile < 0) is the first variant that applies, occ = 0.  Every variant
   // sums each entry in the same order, so all give identical results.
@@ -617,14 +691,20 @@ fe_status launch_cell_impl(const CellLaunch &a) {
   const size_t zbytes = coeff ? (size_t)16 * L.n_q_pad * sizeof(typename P::zreal) +
                                     (size_t)16 * L.n_phi * 8 + 256 * 8
                               : 0;
+  const size_t cslot = ((size_t)ndt * mt * 64 * sizeof(FRAG) +
+                         (size_t)ndt * L.n_phi * P::KSTEP * sizeof(typename P::hreal) + 15) /
+                        16 * 16;
+  const size_t smem3 = 2 * cslot + zbytes8;
   const bool ok8 = mt <= 4 && smem8 <= 156 * 1024;
   const bool ok1 = frag_bytes + zbytes <= 80 * 1024;
+  const bool ok3 = !P::SPLIT && smem3 <= 156 * 1024;
   int variant = ok8 ? 0 : (ok1 ? 1 : 2), occ = 0;
   if (a.tile >= 0) {
-    variant = a.tile % 3;
-    occ = a.tile / 3;
+    variant = a.tile % 4;
+    occ = a.tile / 4;
     if (occ > 1) return FE_EINVAL;
-    if ((variant == 0 && !ok8) || (variant == 1 && !ok1)) return FE_EUNSUPPORTED;
+    if ((variant == 0 && !ok8) || (variant == 1 && !ok1) || (variant == 3 && !ok3))
+      return FE_EUNSUPPORTED;
   }
   if (variant == 0) {
     int jc8 = 0;
@@ -640,6 +720,23 @@ fe_status launch_cell_impl(const CellLaunch &a) {
   }
   const bool stage = variant == 1;
   const size_t smem = (stage ? frag_bytes : 0) + zbytes;
+  if (variant == 3) {
+    // columns per wave: as the 4-wave tiles, fewer where their accumulators
+    // would not fit the registers of two waves per SIMD
+    if constexpr (!P::SPLIT) {
+#define FE_CASE3(M, J) \
+  if (mt == M) return launch_mt<P, M, J, 8, 3>(k, a.n_cells, smem3, occ, s, ndt, coeff);
+      if constexpr (P::REGMUL == 1) {
+        FE_CASE3(1, 4) FE_CASE3(2, 8) FE_CASE3(3, 9) FE_CASE3(4, 7) FE_CASE3(6, 7) FE_CASE3(8, 4)
+        FE_CASE3(11, 3)
+      } else {
+        FE_CASE3(1, 4) FE_CASE3(2, 5) FE_CASE3(3, 5) FE_CASE3(4, 4) FE_CASE3(6, 3) FE_CASE3(8, 2)
+        FE_CASE3(11, 2)
+      }
+#undef FE_CASE3
+    }
+    return FE_EUNSUPPORTED;
+  }
 #define FE_CASE(M, J)                                                                        \
   if (mt == M && jc == J) {                                                                  \
     if (stage) return launch_mt<P, M, J, 4, 1>(k, a.n_cells, smem, occ, s, ndt, coeff);      \

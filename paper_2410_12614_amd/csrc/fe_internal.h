@@ -90,7 +90,7 @@ struct CellLaunch {
   void *stream;
   int tile = -1;  // tile variant (see launch_cell_impl), < 0: default
 };
-constexpr int CELL_TILES = 6;
+constexpr int CELL_TILES = 8;
 fe_status launch_cell_fp64(const CellLaunch &a);
 fe_status launch_cell_fp32(const CellLaunch &a);
 fe_status launch_cell_fp16(const CellLaunch &a);

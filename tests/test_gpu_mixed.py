@@ -87,7 +87,7 @@ def test_tiles_are_bitwise_identical_and_tuner_picks_one():
     md = _md(blocks, "fp16")
     for b in md.blocks:
         ref = None
-        for tile in range(6):
+        for tile in range(8):
             out = torch.full_like(b["values"], float("nan"))
             try:
                 api.fe_cell_kernels_tile(b["desc"], b["form_buf"], b["mesh"], out, tile)
@@ -102,7 +102,7 @@ def test_tiles_are_bitwise_identical_and_tuner_picks_one():
         assert ref is not None
     tuned = md.tune(reps=2)
     for deg, tile, times in tuned:
-        assert 0 <= tile < 6 and times[tile] > 0, (deg, tile, times)
+        assert 0 <= tile < 8 and times[tile] > 0, (deg, tile, times)
         assert times[tile] == min(t for t in times if t >= 0)
         say(f"  p{deg}: tile {tile}, ms {['%.4f' % t for t in times]}")
 
@@ -145,3 +145,33 @@ def test_full_size_mixed_degree_sampled_cells():
             err = np.linalg.norm(got - A.reshape(-1)) / np.linalg.norm(A)
             assert err <= 1e-3, (b.degree, c, err)
         say(f"  p{b.degree}: {len(cells)} sampled cells within 1e-3")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16", "bf16", "split"])
+@pytest.mark.parametrize("form,p,q,coeff", [("stiffness", 4, 8, False), ("mass", 6, 12, False),
+                                            ("stiffness", 3, 6, True), ("mass", 8, 16, False)])
+def test_every_tile_matches_the_default_bitwise(prec, form, p, q, coeff):
+    from fe_inputs import config_mesh, nodal_values
+    m = config_mesh("c2", n=2, degree=p, flatten=0.05)
+    z = nodal_values(m.cell_coords, m.dofmap, m.n_dofs, p, lambda x: 1.0 + x[:, 0] * x[:, 1]) \
+        if coeff else None
+    desc = api.form_desc(3, p, q, form, prec, has_coeff=coeff)
+    mv = api.MeshView.from_numpy(m.cell_coords, m.dofmap, m.n_dofs, z)
+    buf = api.fe_form_prepare(desc)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    ref = torch.empty((m.cell_coords.shape[0], m.n_phi, m.n_phi), dtype=dt, device="cuda")
+    api.fe_cell_kernels(desc, buf, mv, ref)
+    ran = []
+    for tile in range(8):
+        out = torch.full_like(ref, float("nan"))
+        try:
+            api.fe_cell_kernels_tile(desc, buf, mv, out, tile)
+        except api.L.FeError as e:
+            assert e.status == L.FE_EUNSUPPORTED
+            continue
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), (prec, form, p, tile)
+        ran.append(tile)
+    say(f"  {prec} {form} p{p}{' z' if coeff else ''}: tiles {ran}")
+    assert api.fe_get_device_status(buf) == L.FE_OK
+    assert (3 in ran) == (prec != "split")
