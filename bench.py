@@ -66,8 +66,11 @@ WORKLOAD = ("P4 Lagrange mass+stiffness, 24^3 x 6 jittered Kuhn tetrahedra (82,9
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # the default window (100 timed steps after 50 untimed ones, about 0.1 s)
+    # is long enough for the clocks to settle; 20 steps right after set-up
+    # read about 10 % slow
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--precision", default="fp16", choices=["fp16", "bf16", "split", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -237,7 +240,7 @@ def mixed_section(args, steps, warmup):
     md64 = api.MixedDegree(spec, "mass", "fp64")
     md64.tune(reps=1)
     md64.capture()
-    ms64 = time_steps(md64.numeric, max(3, steps // 2), 1)
+    ms64 = time_steps(md64.numeric, max(3, steps // 2), max(1, warmup // 2))
     v64 = md64.numeric()
     torch.cuda.synchronize()
     err = float(torch.linalg.vector_norm(v16.double() - v64) / torch.linalg.vector_norm(v64))
@@ -350,12 +353,13 @@ def main():
     nnz = asm.nnz
     ms_geo = time_steps(lambda: asm.numeric(part="geometry"), args.steps, args.warmup)
     ms_fused = time_steps(lambda: asm.numeric(part="fused"), args.steps, args.warmup)
-    ms_gather_path = time_steps(lambda: asm.numeric(gather=True), max(3, args.steps // 4), 1)
+    ms_gather_path = time_steps(lambda: asm.numeric(gather=True), max(3, args.steps // 4),
+                                max(1, args.warmup // 5))
 
     result = {}
     if not args.no_fp64:
         asm64 = assembly("fp64")
-        ms64 = time_steps(asm64.numeric, max(3, args.steps // 4), 1)
+        ms64 = time_steps(asm64.numeric, max(3, args.steps // 4), max(1, args.warmup // 5))
         v64 = asm64.numeric()
         vm = asm.numeric()
         torch.cuda.synchronize()
@@ -429,10 +433,10 @@ def main():
     del asm
     torch.cuda.empty_cache()
     if not args.no_action:
-        line["action_vjp"] = action_section(args, max(3, args.steps // 2), 2)
+        line["action_vjp"] = action_section(args, max(3, args.steps // 2), max(1, args.warmup // 5))
     if not args.no_mixed:
         torch.cuda.empty_cache()
-        line["mixed_degree"] = mixed_section(args, max(3, args.steps // 2), 2)
+        line["mixed_degree"] = mixed_section(args, max(3, args.steps // 4), max(1, args.warmup // 5))
     print(json.dumps(line), flush=True)
 
 
