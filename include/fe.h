@@ -84,8 +84,17 @@ enum {
   FE_SPLITFP16_ACC32 = 4
 };
 
-/* Geometry precision u_g.  Only FP64 is implemented. */
-enum { FE_GEOM_FP64 = 0 };
+/* Geometry precision u_g (Section 4.2; the per-cell choice remark of
+ * Section 5.2):
+ *   FE_GEOM_FP64  J, det J, J^{-1} and G in double (the default)
+ *   FE_GEOM_FP32  in single, from the coordinates rounded to single
+ *   FE_GEOM_AUTO  in single, recomputed in double for cells whose single
+ *                 result is degenerate or whose condition estimate
+ *                 ||J||_F ||adj J||_F / |det J| exceeds 2^10 (the single
+ *                 error kappa u_32 then stays below an eighth of the FP16
+ *                 unit roundoff).
+ * All forms of one fe_assemble_csr call must use the same mode. */
+enum { FE_GEOM_FP64 = 0, FE_GEOM_FP32 = 1, FE_GEOM_AUTO = 2 };
 
 /* Phases of fe_assemble_csr. */
 enum {
@@ -105,7 +114,7 @@ typedef struct fe_form_desc {
   int32_t form;           /* FE_MASS or FE_STIFFNESS                            */
   int32_t has_coeff;      /* 1: multiply by z(X_q) = sum_k z_k phi_k(X_q)      */
   int32_t precision;      /* FE_FP64 ... FE_SPLITFP16_ACC32                     */
-  int32_t geom_precision; /* FE_GEOM_FP64                                       */
+  int32_t geom_precision; /* FE_GEOM_FP64, FE_GEOM_FP32 or FE_GEOM_AUTO          */
 } fe_form_desc;
 
 typedef struct fe_mesh_view {

@@ -30,6 +30,8 @@ FE_FP16_ACC32 = 2
 FE_BF16_ACC32 = 3
 FE_SPLITFP16_ACC32 = 4
 FE_GEOM_FP64 = 0
+FE_GEOM_FP32 = 1
+FE_GEOM_AUTO = 2
 FE_SYMBOLIC_COUNT = 0
 FE_SYMBOLIC_FILL = 1
 FE_NUMERIC = 2

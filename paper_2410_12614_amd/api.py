@@ -27,11 +27,14 @@ PRECISIONS = {
 FORMS = {"mass": L.FE_MASS, "stiffness": L.FE_STIFFNESS}
 
 
+GEOMETRY = {"fp64": L.FE_GEOM_FP64, "fp32": L.FE_GEOM_FP32, "auto": L.FE_GEOM_AUTO}
+
+
 def form_desc(d: int, degree: int, quad_degree: int, form: str, precision: str = "fp64",
-              has_coeff: bool = False) -> L.fe_form_desc:
+              has_coeff: bool = False, geometry: str = "fp64") -> L.fe_form_desc:
     return L.fe_form_desc(cell=d, degree=degree, quad_degree=quad_degree, form=FORMS[form],
                           has_coeff=int(bool(has_coeff)), precision=PRECISIONS[precision],
-                          geom_precision=L.FE_GEOM_FP64)
+                          geom_precision=GEOMETRY[geometry])
 
 
 def _stream(stream: Optional[torch.cuda.Stream]) -> ctypes.c_void_p:

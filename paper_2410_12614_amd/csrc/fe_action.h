@@ -40,6 +40,7 @@ struct ActArgs {
   int32_t *status;
   int64_t n_cells, n_dofs;
   int d, n_phi, nks, mt, nqt, nt;
+  int geom;      // geometry precision (FE_GEOM_*)
   size_t chunk;  // elements per tile chunk
 };
 
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(NW * 64) void action_kernel(ActArgs a) {
     {
       double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, adet = 0.0;
       bool ok = true;
-      if (valid) ok = cell_geometry(d, a.coords + cell * (d + 1) * d, G, adet);
+      if (valid) ok = cell_geometry_mode(a.geom, d, a.coords + cell * (d + 1) * d, G, adet);
       if (valid && !ok && kb == 0) atomicOr(a.status, (int32_t)STATUS_DEGENERATE);
 #pragma unroll
       for (int s = 0; s < 3; ++s)
@@ -305,6 +306,7 @@ fe_status launch_action_impl(const ActionLaunch &a) {
   k.nqt = L.act_nqt;
   k.nt = L.act_nt;
   k.chunk = L.act_chunk;
+  k.geom = a.geom;
   const bool stiff = L.form == FE_STIFFNESS, coeff = a.coeff != nullptr,
              gz = a.x1 != nullptr && a.out1 != nullptr;
   if (gz && !coeff) return FE_EINVAL;

@@ -226,6 +226,70 @@ __device__ __forceinline__ bool cell_geometry(int d, const double *x, double G[3
   return ok;
 }
 
+// FP32 geometry (the geometry precision u_g = single): coordinates rounded
+// to single, J, its adjugate and det J in single, G = adj adj^T / |det J|;
+// also the Frobenius condition estimate ||J||_F ||adj J||_F / |det J| >=
+// kappa_2(J).  Returns false when det J == 0 or a value is not finite.
+__device__ __forceinline__ bool cell_geometry_f32(int d, const double *x, double G[3][3],
+                                                  double &adet, float &kappa) {
+  float J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) J[i][j] = (float)x[(j + 1) * d + i] - (float)x[i];
+  float adj[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  float det;
+  if (d == 3) {
+    adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
+  } else {
+    adj[0][0] = J[1][1];
+    adj[0][1] = -J[0][1];
+    adj[1][0] = -J[1][0];
+    adj[1][1] = J[0][0];
+    det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  }
+  const float ad = fabsf(det);
+  adet = ad;
+  const float r = 1.0f / ad;
+  bool ok = (det != 0.0f) && isfinite(det);
+  float nj = 0.0f, na = 0.0f;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      nj += J[i][j] * J[i][j];
+      na += adj[i][j] * adj[i][j];
+      float s = 0.0f;
+      for (int k = 0; k < 3; ++k) s += adj[i][k] * adj[j][k];
+      G[i][j] = s * r;
+      ok = ok && isfinite(G[i][j]);
+    }
+  kappa = sqrtf(nj) * sqrtf(na) * r;
+  return ok;
+}
+
+// Above this condition estimate the AUTO geometry mode recomputes a cell in
+// FP64: the single-precision error kappa u_32 then stays below 2^-14, an
+// eighth of the FP16 storage unit roundoff.
+constexpr float GEOM_AUTO_KAPPA = 1024.0f;
+
+// Geometry in the precision of the form (FE_GEOM_FP64, FE_GEOM_FP32, or
+// FE_GEOM_AUTO: single, and double for cells whose single-precision result
+// is degenerate or whose condition estimate exceeds GEOM_AUTO_KAPPA).
+__device__ __forceinline__ bool cell_geometry_mode(int mode, int d, const double *x,
+                                                   double G[3][3], double &adet) {
+  if (mode == FE_GEOM_FP64) return cell_geometry(d, x, G, adet);
+  float kappa;
+  const bool ok = cell_geometry_f32(d, x, G, adet, kappa);
+  if (mode == FE_GEOM_AUTO && !(ok && kappa <= GEOM_AUTO_KAPPA)) return cell_geometry(d, x, G, adet);
+  return ok;
+}
+
 // Factors of H for one cell: the geometry tensor (|det J| for the mass
 // form) times the exact power-of-two scale sigma = 2^e with
 // |H| <= sigma max|w B| max_s sum_t |G_st| max_q |z_q| < 2^15, rounded once to
@@ -412,7 +476,7 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
     double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     double adet = 0.0;
     bool ok = true;
-    if (valid) ok = cell_geometry(d, a.coords + cell * (d + 1) * d, G, adet);
+    if (valid) ok = cell_geometry_mode(a.hdr->geom, d, a.coords + cell * (d + 1) * d, G, adet);
 
     // ---- coefficient at the quadrature points (FE function evaluation) ----
     double zmax = 1.0;

@@ -606,6 +606,7 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
     if (st != FE_OK) return st;
     if (forms[f].cell != forms[0].cell || forms[f].degree != forms[0].degree) return FE_EINVAL;
     if ((forms[f].precision == FE_FP64) != (forms[0].precision == FE_FP64)) return FE_EINVAL;
+    if (forms[f].geom_precision != forms[0].geom_precision) return FE_EINVAL;
   }
   if (m->n_cells < 0 || m->n_dofs < 1) return FE_EINVAL;
   if (m->n_dofs >= INT32_MAX) return FE_EOVERFLOW;
@@ -1033,6 +1034,7 @@ extern "C" fe_status fe_action_vjp(const fe_form_desc *f, const void *form_buf,
     // A^T v = A v) and pairs it with u for the coefficient
     a.x0 = mode == FE_ACTION ? u : v;
     a.x1 = gz ? u : nullptr;
+    a.geom = f->geom_precision;
     a.out0 = b0;
     a.out1 = b1;
     a.stream = stream;

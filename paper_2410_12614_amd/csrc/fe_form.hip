@@ -20,7 +20,7 @@ fe_status check_form(const fe_form_desc *f) {
   if (f->form != FE_MASS && f->form != FE_STIFFNESS) return FE_EINVAL;
   if (f->has_coeff != 0 && f->has_coeff != 1) return FE_EINVAL;
   if (f->precision < FE_FP64 || f->precision > FE_SPLITFP16_ACC32) return FE_EINVAL;
-  if (f->geom_precision != FE_GEOM_FP64) return FE_EUNSUPPORTED;
+  if (f->geom_precision < FE_GEOM_FP64 || f->geom_precision > FE_GEOM_AUTO) return FE_EINVAL;
   if (f->degree > FE_MAX_DEGREE || f->quad_degree > FE_MAX_QUAD_DEGREE) return FE_EUNSUPPORTED;
   return FE_OK;
 }
@@ -149,6 +149,7 @@ extern "C" fe_status fe_form_prepare(const fe_form_desc *f, void *form_buf, size
   hdr.n_q = nq;
   hdr.prec = L.prec;
   hdr.form = L.form;
+  hdr.geom = f->geom_precision;
   // B^T fragments.  In the 16-bit modes B is scaled by an exact power of two
   // so that max |B| lies in [2^14, 2^15): small tabulated values then stay
   // normal numbers instead of being flushed by the matrix cores.

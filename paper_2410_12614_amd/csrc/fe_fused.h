@@ -74,7 +74,8 @@ __global__ __launch_bounds__(256) void k_form_geo(const double *coords, int64_t 
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n_cells) return;
   double G[3][3], adet;
-  const bool ok = cell_geometry(d, coords + c * (d + 1) * d, G, adet);
+  // one geometry per cell for all forms: those share the mode of the first
+  const bool ok = cell_geometry_mode(g.hdr[0]->geom, d, coords + c * (d + 1) * d, G, adet);
   for (int f = 0; f < g.nforms; ++f) {
     typename P::hreal Gp[3][3];
     T inv;

@@ -57,6 +57,7 @@ struct FormHeader {
   int32_t status;
   int32_t magic;
   int32_t d, nd, n_phi, n_q, prec, form;
+  int32_t geom, pad;  // geometry precision (FE_GEOM_*)
   double max_wb;    // max |w_q B_t(q, j)|
   double lebesgue;  // max_q sum_k |phi_k(X_q)|
   double b_scale;   // exact power of two applied to the B^T operand (FP16/BF16 modes)
@@ -218,6 +219,7 @@ struct ActionLaunch {
   const void *x1;       // second function of the coefficient adjoint, or NULL
   void *out0;           // local vectors [n_cells][n_phi]: action on x0
   void *out1;           // local coefficient adjoint [n_cells][n_phi] (x1 given)
+  int geom;             // geometry precision (FE_GEOM_*)
   void *stream;
 };
 fe_status launch_action_fp32(const ActionLaunch &a);

@@ -99,7 +99,7 @@ def test_form_prepare_size_query(lib, prec, d, p, q, form):
 
 @pytest.mark.parametrize("field,value,status", [
     ("cell", 5, L.FE_EINVAL), ("degree", 0, L.FE_EINVAL), ("degree", 9, L.FE_EUNSUPPORTED),
-    ("form", 7, L.FE_EINVAL), ("precision", 9, L.FE_EINVAL), ("geom_precision", 1, L.FE_EUNSUPPORTED),
+    ("form", 7, L.FE_EINVAL), ("precision", 9, L.FE_EINVAL), ("geom_precision", 3, L.FE_EINVAL),
     ("has_coeff", 3, L.FE_EINVAL), ("quad_degree", 18, L.FE_EUNSUPPORTED),
 ])
 def test_form_validation(lib, field, value, status):
