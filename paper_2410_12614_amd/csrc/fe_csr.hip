@@ -906,11 +906,28 @@ __global__ __launch_bounds__(256) void k_vgather(const VecPlanHeader *hdr, const
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n_dofs) return;
   T s0 = 0, s1 = 0;
-  for (int64_t a = adj_ptr[g]; a < adj_ptr[g + 1]; ++a) {
-    const int64_t e = adj[a];
-    const int64_t idx = (e >> 8) * n_phi + (e & 255);
-    s0 += b0[idx];
-    if (NF == 2) s1 += b1[idx];
+  const int64_t a0 = adj_ptr[g], a1 = adj_ptr[g + 1];
+  // four entries at a time: their loads are independent and in flight
+  // together; the sums still run in list order
+  for (int64_t a = a0; a < a1; a += 4) {
+    int64_t idx[4];
+    T v0[4], v1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t e = a + u < a1 ? adj[a + u] : -1;
+      idx[u] = e < 0 ? -1 : (e >> 8) * n_phi + (e & 255);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      v0[u] = idx[u] < 0 ? (T)0 : b0[idx[u]];
+      if (NF == 2) v1[u] = idx[u] < 0 ? (T)0 : b1[idx[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (idx[u] < 0) break;
+      s0 += v0[u];
+      if (NF == 2) s1 += v1[u];
+    }
   }
   out0[g] = s0;
   if (NF == 2) out1[g] = s1;
