@@ -16,6 +16,7 @@ from .meshes import (  # noqa: F401
     nodal_values,
     normal_vector,
     config_mesh,
+    hex_mesh,
     DegreeBlock,
     mixed_degree_blocks,
     CONFIGS,

@@ -327,3 +327,27 @@ def mixed_degree_blocks(n: int = 41, n_cells: int = 400_000, degrees=range(1, 9)
         dof_off += nd
         nnz_off += ids.size * n_phi * n_phi
     return blocks
+
+
+def hex_mesh(n: int, degree: int, jitter: float = 0.25, seed: int = 0) -> Mesh:
+    """n^3 hexahedra of the unit cube (box x fastest), interior vertices
+    jittered by U[-r h, r h] per coordinate (trilinear cells); the cell's
+    vertex v is its box corner (v & 1, (v >> 1) & 1, (v >> 2) & 1).  Dof map
+    of Q_p on the fine lattice (pn+1)^3: local (i, j, k) -> global
+    (p bx + i) + N (p by + j) + N^2 (p bz + k), local index i + (p+1)(j + (p+1)k)."""
+    nv = n + 1
+    lat_v = _lex_points(nv, 3)
+    verts = lat_v.astype(np.float64) / n
+    if jitter > 0.0:
+        verts = jitter_interior(verts, n, jitter, seed)
+    box = _lex_points(n, 3)
+    corners = np.array([[(v >> e) & 1 for e in range(3)] for v in range(8)])
+    lattice = box[:, None, :] + corners[None, :, :]                      # [n^3][8][3]
+    cells = (lattice * (nv ** np.arange(3))).sum(axis=-1)
+    cell_coords = np.ascontiguousarray(verts[cells])
+    p, N = degree, degree * n + 1
+    loc = _lex_points(p + 1, 3)                                          # i fastest
+    pos = p * box[:, None, :] + loc[None, :, :]
+    dofmap = (pos * (N ** np.arange(3))).sum(axis=-1).astype(np.int32)
+    return Mesh(d=3, n=n, degree=p, vertices=verts, cells=cells, lattice=lattice,
+                cell_coords=cell_coords, dofmap=np.ascontiguousarray(dofmap), n_dofs=int(N ** 3))

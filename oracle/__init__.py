@@ -22,6 +22,10 @@ Parts and what pins them (tests under ``tests/test_oracle_*.py``):
 * ``oracle_fe.c`` assembly (Section 3.3) -- pinned by brute-force dense
   assembly on tiny meshes, nnz counts, and exact polynomial integrals
   u^T M v, u^T K v.
+* ``hexahedra.py`` (boxed cells, per-point trilinear geometry): mass matrices
+  -- pinned by exact monomial integrals of the tensor rule, the Kronecker
+  property, the unit cube = tensor product of exact rational 1D mass
+  matrices, the volume of a jittered mesh and an exact polynomial integral.
 * ``oracle_fe.c`` actions (Algorithm 2) and the coefficient adjoint -- pinned
   by the assembled matrix times the vector (Algorithm 1 route), mass and
   stiffness actions on constants (|Omega|, zero), the exact integral of
