@@ -57,8 +57,14 @@ enum {
 };
 
 /* Reference cells (Section 5.1): the triangle / tetrahedron with vertices
- * 0, e_1, ..., e_d.  The value equals the dimension d. */
-enum { FE_TRIANGLE = 2, FE_TETRAHEDRON = 3 };
+ * 0, e_1, ..., e_d (the value equals the dimension d), and the hexahedron
+ * (boxed cell, value 8: its vertex count) on the unit cube [0,1]^3, mapped
+ * trilinearly; its cell_coords are [n_cells][8][3], vertex v at the reference
+ * corner (v & 1, (v >> 1) & 1, (v >> 2) & 1).  Hexahedra: Lagrange Q_p on the
+ * equispaced lattice (n_phi = (p+1)^3, local index i + (p+1)(j + (p+1)k)),
+ * tensor Gauss-Legendre quadrature, mass form only; J and |det J| vary over
+ * the cell and enter per quadrature point. */
+enum { FE_TRIANGLE = 2, FE_TETRAHEDRON = 3, FE_HEXAHEDRON = 8 };
 
 /* Forms of Section 3.1. */
 enum { FE_MASS = 0, FE_STIFFNESS = 1 };

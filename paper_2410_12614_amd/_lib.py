@@ -22,6 +22,7 @@ FE_ESIZE = -6
 
 FE_TRIANGLE = 2
 FE_TETRAHEDRON = 3
+FE_HEXAHEDRON = 8
 FE_MASS = 0
 FE_STIFFNESS = 1
 FE_FP64 = 0

@@ -46,16 +46,18 @@ def _ptr(t: Optional[torch.Tensor]) -> Optional[ctypes.c_void_p]:
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def fe_tabulate(d: int, degree: int, quad_degree: int, nderiv: int = 1):
-    """(points [n_q][d], weights [n_q], table [1 + d*nderiv][n_q][n_phi]) in FP64 (host)."""
+def fe_tabulate(cell: int, degree: int, quad_degree: int, nderiv: int = 1):
+    """(points [n_q][d], weights [n_q], table [1 + d*nderiv][n_q][n_phi]) in FP64 (host);
+    ``cell`` is FE_TRIANGLE (2), FE_TETRAHEDRON (3) or FE_HEXAHEDRON (8, d = 3)."""
     lib = L.load()
+    d = 3 if cell == L.FE_HEXAHEDRON else cell
     n_phi, n_q = ctypes.c_int32(0), ctypes.c_int32(0)
-    check(lib.fe_tabulate(d, degree, quad_degree, nderiv, ctypes.byref(n_phi), ctypes.byref(n_q),
+    check(lib.fe_tabulate(cell, degree, quad_degree, nderiv, ctypes.byref(n_phi), ctypes.byref(n_q),
                           None, None, None), "fe_tabulate")
     pts = np.zeros((n_q.value, d))
     w = np.zeros(n_q.value)
     tab = np.zeros((1 + d * nderiv, n_q.value, n_phi.value))
-    check(lib.fe_tabulate(d, degree, quad_degree, nderiv, ctypes.byref(n_phi), ctypes.byref(n_q),
+    check(lib.fe_tabulate(cell, degree, quad_degree, nderiv, ctypes.byref(n_phi), ctypes.byref(n_q),
                           pts.ctypes.data_as(ctypes.c_void_p), w.ctypes.data_as(ctypes.c_void_p),
                           tab.ctypes.data_as(ctypes.c_void_p)), "fe_tabulate")
     return pts, w, tab

@@ -179,6 +179,8 @@ struct KArgs {
   const double *coords;
   const int32_t *dofmap;
   const double *coeff;
+  const double *ptab;  // hexahedra: quadrature points [n_q][3]
+  int box;             // hexahedra: |det J(X_q)| per point
   void *A;
   int64_t n_cells, n_dofs;
   int d, nd, n_phi, n_q, n_q_pad, nks;
@@ -288,6 +290,27 @@ __device__ __forceinline__ bool cell_geometry_mode(int mode, int d, const double
   const bool ok = cell_geometry_f32(d, x, G, adet, kappa);
   if (mode == FE_GEOM_AUTO && !(ok && kappa <= GEOM_AUTO_KAPPA)) return cell_geometry(d, x, G, adet);
   return ok;
+}
+
+// det J(X) of the trilinear map of a hexahedron with vertices x [8][3]
+// (vertex v at the reference corner (v & 1, (v >> 1) & 1, (v >> 2) & 1)):
+// J_ij = sum_v x_v,i d_j phi_v(X), phi_v the Q1 basis, in FP64.
+__device__ __forceinline__ double box_det(const double *x, const double *X) {
+  double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int v = 0; v < 8; ++v) {
+    double f[3], df[3];
+    for (int e = 0; e < 3; ++e) {
+      const bool b = (v >> e) & 1;
+      f[e] = b ? X[e] : 1.0 - X[e];
+      df[e] = b ? 1.0 : -1.0;
+    }
+    const double g[3] = {df[0] * f[1] * f[2], f[0] * df[1] * f[2], f[0] * f[1] * df[2]};
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) J[i][j] += x[v * 3 + i] * g[j];
+  }
+  return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+         J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
 }
 
 // Factors of H for one cell: the geometry tensor (|det J| for the mass
@@ -423,8 +446,10 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
   HT *s_wt = (HT *)(smem + frag_bytes * (P::SPLIT ? 2 : 1));
   unsigned char *zbase = smem + frag_bytes * (P::SPLIT ? 2 : 1) + wtab_bytes;
   Z *zq = (Z *)zbase;                                                   // [n_q_pad][16]
-  double *zloc = (double *)(zbase + (size_t)16 * n_q_pad * sizeof(Z));  // [16][n_phi]
-  double *zred = zloc + 16 * nphi;                                      // [NT]
+  // [16][24] vertex coordinates of hexahedra, then [16][n_phi] coefficient dofs
+  double *zloc = (double *)(zbase + (size_t)16 * n_q_pad * sizeof(Z));
+  const int zoff = a.box ? 16 * 24 : 0;
+  double *zred = zloc + zoff + (a.coeff ? 16 * nphi : 0);  // [NT]
 
   if constexpr (STAGE == 1 || STAGE == 2) {
     const size_t n16 = frag_bytes / 16;
@@ -476,31 +501,58 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
     double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     double adet = 0.0;
     bool ok = true;
-    if (valid) ok = cell_geometry_mode(a.hdr->geom, d, a.coords + cell * (d + 1) * d, G, adet);
+    if (a.box) {
+      adet = 1.0;  // hexahedra: |det J| varies over the cell; it enters per point below
+    } else if (valid) {
+      ok = cell_geometry_mode(a.hdr->geom, d, a.coords + cell * (d + 1) * d, G, adet);
+    }
 
     // ---- coefficient at the quadrature points (FE function evaluation) ----
     double zmax = 1.0;
+    // Per-point factor z_q of H: the coefficient at the point, times
+    // |det J(X_q)| for hexahedra (the trilinear map's Jacobian varies over
+    // the cell; Section 3.1 with G(X) = |det J(X)| for the mass form).
     if constexpr (COEFF) {
       __syncthreads();  // the previous batch is done with zq
-      for (int idx = tid; idx < 16 * nphi; idx += NT) {
-        const int cc = idx / nphi, k = idx - cc * nphi;
-        const int64_t ce = cell0 + cc;
-        double z = 0.0;
-        if (ce < a.n_cells) {
-          const int32_t g = a.dofmap[ce * nphi + k];
-          if (g >= 0 && g < a.n_dofs) z = a.coeff[g];
-          else atomicOr(a.status, STATUS_BAD_DOF);
+      if (a.box)
+        for (int idx = tid; idx < 16 * 24; idx += NT) {
+          const int64_t ce = cell0 + idx / 24;
+          zloc[idx] = ce < a.n_cells ? a.coords[ce * 24 + idx % 24] : 0.0;
         }
-        zloc[idx] = z;
-      }
+      if (a.coeff)
+        for (int idx = tid; idx < 16 * nphi; idx += NT) {
+          const int cc = idx / nphi, k = idx - cc * nphi;
+          const int64_t ce = cell0 + cc;
+          double z = 0.0;
+          if (ce < a.n_cells) {
+            const int32_t g = a.dofmap[ce * nphi + k];
+            if (g >= 0 && g < a.n_dofs) z = a.coeff[g];
+            else atomicOr(a.status, STATUS_BAD_DOF);
+          }
+          zloc[zoff + idx] = z;
+        }
       __syncthreads();
       const Z *vt = (const Z *)a.vtab;
       double zpart = 0.0;  // this thread's |z_q| maximum for cell tid % 16
       for (int idx = tid; idx < 16 * n_q_pad; idx += NT) {
         const int q = idx >> 4, cc = idx & 15;
         Z z = 0;
-        if (q < a.n_q)
-          for (int k = 0; k < nphi; ++k) z += (Z)zloc[cc * nphi + k] * vt[q * nphi + k];
+        if (q < a.n_q) {
+          if (a.coeff) {
+            for (int k = 0; k < nphi; ++k) z += (Z)zloc[zoff + cc * nphi + k] * vt[q * nphi + k];
+          } else {
+            z = 1;
+          }
+          if (a.box && cell0 + cc < a.n_cells) {
+            const double dj = box_det(zloc + cc * 24, a.ptab + 3 * q);
+            if (!(dj != 0.0 && isfinite(dj))) {
+              atomicOr(a.status, STATUS_DEGENERATE);
+              z = (Z)NAN;
+            } else {
+              z = z * (Z)fabs(dj);
+            }
+          }
+        }
         zq[idx] = z;
         zpart = fmax(zpart, fabs((double)z));
       }
@@ -511,11 +563,24 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
       for (int r = 0; r < NT / 16; ++r) m = fmax(m, zred[c + 16 * r]);
       zmax = m;
     }
+    // the per-point factors of this lane's cell enter H scaled by the exact
+    // power of two zs that brings max_q |z_q| into [1, 2) (per-point |det J|
+    // of a small hexahedron would otherwise be subnormal in half); the
+    // inverse goes into the cell's exact inverse scale below
+    int ez = 0;
+    if constexpr (COEFF) {
+      if (zmax > 0.0 && isfinite(zmax)) {
+        ez = ilogb(zmax);
+        zmax = ldexp(zmax, -ez);
+      }
+    }
+    const T zs = (T)ldexp(1.0, -ez);
 
     if (valid && !ok && wave == 0 && kb == 0) atomicOr(a.status, STATUS_DEGENERATE);
     HT Gp[3][3];
     T inv;
     cell_factors<P>(a.hdr, a.nd, valid, ok, G, adet, zmax, Gp, inv);
+    inv = (T)ldexp((double)inv, ez);
 
     const HT *wt = (const HT *)a.wtab;
     for (int pass = pass_lo; pass < pass_hi; ++pass) {
@@ -573,7 +638,7 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
         T zf[P::KPL];
         if constexpr (COEFF) {
 #pragma unroll
-          for (int e = 0; e < P::KPL; ++e) zf[e] = (T)zq[(qb + e) * 16 + c];
+          for (int e = 0; e < P::KPL; ++e) zf[e] = (T)zq[(qb + e) * 16 + c] * zs;
         }
 #pragma unroll
         for (int jj = 0; jj < JC; ++jj) {
@@ -721,6 +786,8 @@ fe_status launch_cell_impl(const CellLaunch &a) {
   k.coords = a.coords;
   k.dofmap = a.dofmap;
   k.coeff = a.coeff;
+  k.box = L.box;
+  k.ptab = (const double *)(a.form_buf + L.off_ptab);
   k.A = a.A_local;
   k.n_cells = a.n_cells;
   k.n_dofs = a.n_dofs;
@@ -730,7 +797,9 @@ fe_status launch_cell_impl(const CellLaunch &a) {
   k.n_q = L.n_q;
   k.n_q_pad = L.n_q_pad;
   k.nks = L.nks;
-  const bool coeff = L.has_coeff != 0;
+  // per-point factors of H: a coefficient, or |det J(X_q)| of hexahedra
+  const bool coeff = L.has_coeff != 0 || L.box != 0;
+  const size_t zl = (size_t)(L.has_coeff ? L.n_phi : 0) + (L.box ? 24 : 0);
   typedef typename P::frag FRAG;
   typedef typename P::real T;
   const size_t frag_bytes = (size_t)mt * L.nks * 64 * sizeof(FRAG) * (P::SPLIT ? 2 : 1);
@@ -749,11 +818,11 @@ fe_status launch_cell_impl(const CellLaunch &a) {
   // (tile < 0) is the first variant that applies, occ = 0.  Every variant
   // sums each entry in the same order, so all give identical results.
   const size_t zbytes8 = coeff ? (size_t)16 * L.n_q_pad * sizeof(typename P::zreal) +
-                                     (size_t)16 * L.n_phi * 8 + 512 * 8
+                                     (size_t)16 * zl * 8 + 512 * 8
                                : 0;
   const size_t smem8 = frag_bytes + wtab_bytes + zbytes8;
   const size_t zbytes = coeff ? (size_t)16 * L.n_q_pad * sizeof(typename P::zreal) +
-                                    (size_t)16 * L.n_phi * 8 + 256 * 8
+                                    (size_t)16 * zl * 8 + 256 * 8
                               : 0;
   const size_t cslot = ((size_t)ndt * mt * 64 * sizeof(FRAG) +
                          (size_t)ndt * L.n_phi * P::KSTEP * sizeof(typename P::hreal) + 15) /

@@ -15,7 +15,10 @@ static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 fe_status check_form(const fe_form_desc *f) {
   if (!f) return FE_EINVAL;
-  if (f->cell != FE_TRIANGLE && f->cell != FE_TETRAHEDRON) return FE_EINVAL;
+  if (f->cell != FE_TRIANGLE && f->cell != FE_TETRAHEDRON && f->cell != FE_HEXAHEDRON)
+    return FE_EINVAL;
+  // hexahedra: the mass form (the Poisson tensor varies per point as a 3x3 matrix)
+  if (f->cell == FE_HEXAHEDRON && f->form != FE_MASS) return FE_EUNSUPPORTED;
   if (f->degree < 1 || f->quad_degree < 0) return FE_EINVAL;
   if (f->form != FE_MASS && f->form != FE_STIFFNESS) return FE_EINVAL;
   if (f->has_coeff != 0 && f->has_coeff != 1) return FE_EINVAL;
@@ -37,11 +40,13 @@ fe_status compute_layout(const fe_form_desc *f, FormLayout *L) {
   fe_status st = check_form(f);
   if (st != FE_OK) return st;
   std::memset(L, 0, sizeof(*L));
-  L->d = f->cell;
+  L->d = f->cell == FE_HEXAHEDRON ? 3 : f->cell;
+  L->box = f->cell == FE_HEXAHEDRON;
   L->form = f->form;
   L->nd = (f->form == FE_MASS) ? 1 : L->d;
   L->ndt = (f->form == FE_MASS) ? 1 : 3;
-  L->n_phi = simplex_dim(L->d, f->degree);
+  L->n_phi = L->box ? (f->degree + 1) * (f->degree + 1) * (f->degree + 1)
+                    : simplex_dim(L->d, f->degree);
   const int m = f->quad_degree / 2 + 1;
   L->n_q = (L->d == 2) ? m * m : m * m * m;
   L->prec = f->precision;
@@ -69,13 +74,15 @@ fe_status compute_layout(const fe_form_desc *f, FormLayout *L) {
   off = align256(off + (size_t)L->ndt * L->n_phi * L->n_q_pad * L->tab_bytes);
   L->off_vtab = off;
   if (L->has_coeff) off = align256(off + (size_t)L->n_q * L->n_phi * L->vtab_bytes);
+  L->off_ptab = off;
+  if (L->box) off = align256(off + (size_t)L->n_q * 3 * sizeof(double));
   // action tables: FP32 / FP64 forms whose dofs fit the registers of a lane;
   // the K-steps are padded to the counts of the tetrahedral degrees 1..6
   // (the kernels are compiled for those), triangles take a zero third slab
   int act_nks = 0;
   for (int b : {1, 3, 5, 9, 14, 21})
     if (act_nks == 0 && 4 * b >= L->n_phi) act_nks = b;
-  if ((f->precision == FE_FP32 || f->precision == FE_FP64) && act_nks > 0) {
+  if ((f->precision == FE_FP32 || f->precision == FE_FP64) && act_nks > 0 && !L->box) {
     L->act_nt = L->form == FE_STIFFNESS ? 4 : 1;
     L->act_nks = act_nks;
     L->act_mt = (act_nks + 3) / 4;
@@ -245,6 +252,9 @@ extern "C" fe_status fe_form_prepare(const fe_form_desc *f, void *form_buf, size
       }
     }
   }
+  if (L.box)
+    for (int q = 0; q < nq; ++q)
+      for (int e = 0; e < 3; ++e) put<double>(h.data(), L.off_ptab, (size_t)q * 3 + e, pts[(size_t)q * 3 + e]);
   hdr.max_wb = max_wb;
   hdr.lebesgue = leb;
   std::memcpy(h.data(), &hdr, sizeof(hdr));
@@ -263,7 +273,7 @@ bool fused_eligible(const FormLayout &L) {
   // buffers of at least 8 waves; otherwise the cell kernels and the row
   // gather are faster
   const FormLayout *one[1] = {&L};
-  return !L.has_coeff && fused_lds(one, 1, 8, true) <= FUSED_LDS_BUDGET;
+  return !L.has_coeff && !L.box && fused_lds(one, 1, 8, true) <= FUSED_LDS_BUDGET;
 }
 
 fe_status launch_cell(const CellLaunch &a) {

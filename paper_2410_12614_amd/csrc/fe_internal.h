@@ -48,7 +48,8 @@ struct FormLayout {
   int elt_bytes;  // bytes per operand element in afrag
   int tab_bytes;  // weighted table: 2 (half, FP16 mode), 4 (float) or 8 (double, FP64 mode)
   int vtab_bytes; // value table for the coefficient: 8 unless FP16/BF16 storage
-  size_t off_afrag, off_afrag_lo, off_wtab, off_vtab, total;
+  size_t off_afrag, off_afrag_lo, off_wtab, off_vtab, off_ptab, total;
+  int box;  // hexahedron: per-point |det J| (quadrature points at off_ptab)
   int act_nt, act_nks, act_mt, act_nqt;  // act_nt == 0: no action tables
   size_t act_chunk, off_act;
 };

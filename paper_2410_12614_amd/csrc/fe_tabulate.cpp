@@ -170,13 +170,78 @@ void lagrange_eval(int d, int p, const double *X, double *val, double *grad /*[d
 
 using namespace fe;
 
+namespace fe {
+// Equispaced 1D Lagrange basis of degree p on [0, 1] (nodes k / p) and its
+// derivative at t, by the product formula.
+static void lagrange_1d(int p, double t, double *v, double *dv) {
+  for (int k = 0; k <= p; ++k) {
+    double val = 1.0, der = 0.0;
+    for (int a = 0; a <= p; ++a) {
+      if (a == k) continue;
+      const double den = (double)(k - a) / p;
+      const double f = (t - (double)a / p) / den;
+      der = der * f + val / den;
+      val *= f;
+    }
+    v[k] = val;
+    dv[k] = der;
+  }
+}
+
+// The unit cube [0,1]^3: tensor Gauss-Legendre points (m = floor(q/2)+1 per
+// direction, x fastest) and the tensor-product Lagrange basis on the
+// equispaced lattice, local index i + (p+1)(j + (p+1)k) for the node
+// (i, j, k) / p, with its gradient by the product rule.
+static fe_status tabulate_hex(int degree, int quad_degree, int nderiv, int32_t *n_phi,
+                              int32_t *n_q, double *points, double *weights, double *table) {
+  const int m = quad_degree / 2 + 1, p = degree, n1 = p + 1;
+  const int nq = m * m * m, nphi = n1 * n1 * n1;
+  *n_phi = nphi;
+  *n_q = nq;
+  if (!points && !weights && !table) return FE_OK;
+  double t[16], w[16];
+  gauss_jacobi_01(m, 0, t, w);
+  std::vector<double> v1((size_t)m * n1), d1((size_t)m * n1);
+  for (int a = 0; a < m; ++a) lagrange_1d(p, t[a], &v1[(size_t)a * n1], &d1[(size_t)a * n1]);
+  const size_t slab = (size_t)nq * nphi;
+  int q = 0;
+  for (int c = 0; c < m; ++c)
+    for (int b = 0; b < m; ++b)
+      for (int a = 0; a < m; ++a, ++q) {
+        if (points) {
+          points[q * 3 + 0] = t[a];
+          points[q * 3 + 1] = t[b];
+          points[q * 3 + 2] = t[c];
+        }
+        if (weights) weights[q] = w[a] * w[b] * w[c];
+        if (!table) continue;
+        const double *va = &v1[(size_t)a * n1], *vb = &v1[(size_t)b * n1], *vc = &v1[(size_t)c * n1];
+        const double *da = &d1[(size_t)a * n1], *db = &d1[(size_t)b * n1], *dc = &d1[(size_t)c * n1];
+        for (int k = 0; k < n1; ++k)
+          for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n1; ++i) {
+              const size_t idx = (size_t)q * nphi + i + (size_t)n1 * (j + (size_t)n1 * k);
+              table[idx] = va[i] * vb[j] * vc[k];
+              if (nderiv) {
+                table[slab + idx] = da[i] * vb[j] * vc[k];
+                table[2 * slab + idx] = va[i] * db[j] * vc[k];
+                table[3 * slab + idx] = va[i] * vb[j] * dc[k];
+              }
+            }
+      }
+  return FE_OK;
+}
+}  // namespace fe
+
 extern "C" fe_status fe_tabulate(int32_t cell, int32_t degree, int32_t quad_degree,
                                  int32_t nderiv, int32_t *n_phi, int32_t *n_q, double *points,
                                  double *weights, double *table) {
-  if (cell != FE_TRIANGLE && cell != FE_TETRAHEDRON) return FE_EINVAL;
+  if (cell != FE_TRIANGLE && cell != FE_TETRAHEDRON && cell != FE_HEXAHEDRON) return FE_EINVAL;
   if (degree < 1 || quad_degree < 0 || (nderiv != 0 && nderiv != 1)) return FE_EINVAL;
   if (!n_phi || !n_q) return FE_EINVAL;
   if (degree > FE_MAX_DEGREE || quad_degree > FE_MAX_QUAD_DEGREE) return FE_EUNSUPPORTED;
+  if (cell == FE_HEXAHEDRON)
+    return tabulate_hex(degree, quad_degree, nderiv, n_phi, n_q, points, weights, table);
   const int d = cell;
   const int m = quad_degree / 2 + 1;
   const int nq = (d == 2) ? m * m : m * m * m;
