@@ -34,6 +34,12 @@ step = the numeric phase of all eight blocks (per-degree tiles from the
 autotuner) replayed as one HIP graph, FP16 storage / FP32 accumulation, the
 FP64 path beside it.
 
+Under "hex_mass": the mass form on hexahedra (the paper's boxed cells):
+38^3 jittered trilinear hexahedra (54,872 cells), Q4 (125 dofs/cell), the
+125-point tensor Gauss-Legendre rule, |det J| per quadrature point; one
+step = FE_NUMERIC (cell kernels + row-gather assembly into CSR), FP16
+storage / FP32 accumulation, the FP64 path beside it.
+
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -85,6 +91,10 @@ def parse():
                     help="skip the mixed-degree batch measurement")
     ap.add_argument("--mixed-cpu-cells", type=int, default=240000,
                     help="cells (first n of the mesh) of the oracle sample of the mixed batch")
+    ap.add_argument("--no-hex", action="store_true",
+                    help="skip the hexahedral mass measurement")
+    ap.add_argument("--hex-cpu-cells", type=int, default=10000,
+                    help="cells (first n) of the oracle sample of the hexahedral mass step")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB elementwise copy (x * 1.0), the reference "
                          "kernel for scaling hardware byte counters")
@@ -285,6 +295,69 @@ def mixed_section(args, steps, warmup):
     return out
 
 
+def hex_section(args, steps, warmup):
+    """Mass form on trilinear hexahedra (Q4): FE_NUMERIC in FP16 and FP64."""
+    import numpy as np
+    import torch
+
+    from fe_inputs import hex_mesh
+    from paper_2410_12614_amd import _lib as L
+    from paper_2410_12614_amd import api
+
+    m = hex_mesh(38, 4, jitter=0.25, seed=0)
+    n_cells, n_phi, n_q = m.cell_coords.shape[0], 125, 125
+    mv = api.MeshView.from_numpy(m.cell_coords, m.dofmap, m.n_dofs)
+    out = {"workload": "Q4 mass on 38^3 jittered trilinear hexahedra (54,872 cells, 125 dofs/cell), "
+                       "125-point tensor Gauss-Legendre rule, |det J| per point",
+           "n_cells": n_cells, "n_dofs": m.n_dofs}
+    res = {}
+    for prec in ("fp16", "fp64"):
+        asm = api.Assembly(mv, [api.form_desc(L.FE_HEXAHEDRON, 4, 8, "mass", prec)])
+        res[prec] = time_steps(asm.numeric, steps if prec == "fp16" else max(3, steps // 2), warmup)
+        if any(st != 0 for st in asm.status()):
+            raise RuntimeError("device status after the hexahedral step")
+        res[prec + "_vals"] = asm.numeric()[0][:asm.nnz].double().clone()
+        nnz = asm.nnz
+        del asm
+        torch.cuda.empty_cache()
+    err = float(torch.linalg.vector_norm(res["fp16_vals"] - res["fp64_vals"]) /
+                torch.linalg.vector_norm(res["fp64_vals"]))
+    del res["fp16_vals"], res["fp64_vals"]
+    ms = res["fp16"]
+    flops = n_cells * 2 * n_phi ** 2 * n_q
+    nbytes = (192 + 4 * n_phi) * n_cells + 4 * nnz
+    t = ms / 1e3
+    ideal = {"hbm": nbytes / (PEAK_HBM_GBS * 1e9), "mfma": flops / (PEAK_MFMA_TFLOPS["fp16"] * 1e12)}
+    if max(ideal, key=ideal.get) == "hbm":
+        roof = {"bound": "hbm", "achieved": nbytes / t / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    else:
+        roof = {"bound": "mfma", "achieved": flops / t / 1e12, "peak": PEAK_MFMA_TFLOPS["fp16"],
+                "unit": "TFLOP/s"}
+    roof.update({"frac": roof["achieved"] / roof["peak"], "traffic": None,
+                 "kernel": "cell_kernel + k_gather (the whole step)",
+                 "ideal_us": {k: v * 1e6 for k, v in ideal.items()}, "alg_flops": flops,
+                 "alg_bytes": nbytes})
+    out.update({"metric": "cells/s (hexahedral mass, kernels + CSR assembly)",
+                "value": n_cells / t, "unit": "cells/s", "dtype": "f16 x f16 -> f32",
+                "ms_per_step": ms, "nnz": nnz,
+                "fp64_path": {"value": n_cells / (res["fp64"] / 1e3), "ms_per_step": res["fp64"]},
+                "speedup_vs_fp64": res["fp64"] / ms, "rel_err_vs_fp64": err, "roofline": roof})
+    if not args.no_cpu_baseline:
+        import oracle
+        import oracle.hexahedra as H
+        n = min(args.hex_cpu_cells, n_cells)
+        rp, ci = oracle.csr_pattern(m.dofmap[:n], m.n_dofs)      # symbolic: not timed
+        t0 = time.perf_counter()
+        A = H.mass_matrices(m.cell_coords[:n], 4, 8)
+        oracle.assemble(m.dofmap[:n], A, m.n_dofs, rp, ci)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": n / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} of {n_cells} cells: local mass matrices (numpy FP64, per-point "
+                      f"geometry) + CSR assembly (C, one thread), one pass of {dt:.1f} s"}
+    return out
+
+
 def sources_digest():
     """SHA-256 over the sources of the fused pass (traffic is reported only
     for the code it was measured on)."""
@@ -437,6 +510,9 @@ def main():
     if not args.no_mixed:
         torch.cuda.empty_cache()
         line["mixed_degree"] = mixed_section(args, max(3, args.steps // 4), max(1, args.warmup // 5))
+    if not args.no_hex:
+        torch.cuda.empty_cache()
+        line["hex_mass"] = hex_section(args, max(3, args.steps // 4), max(1, args.warmup // 5))
     print(json.dumps(line), flush=True)
 
 
