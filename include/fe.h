@@ -295,8 +295,10 @@ fe_status fe_dg_pattern(int32_t n_blocks, const int64_t *n_cells, const int32_t 
  *       per-cell FP64 geometry pass and one fused kernel: every wave owns a
  *       range of CSR rows in LDS, computes the local rows A_K(j, :) of
  *       exactly the dofs it owns on the matrix cores and writes its rows
- *       once.  Otherwise it runs the cell kernels into the workspace
- *       followed by the row gather.  Either way every entry's
+ *       once.  Otherwise, and always for hexahedral forms (their long rows
+ *       leave the fused tiles mostly empty: the gather is faster), it runs
+ *       the cell kernels into the workspace followed by the row gather.
+ *       Either way every entry's
  *       contributions are summed in the fixed order cell ascending and every
  *       value is written exactly once (no separate zero-fill).
  *       Asynchronous, never synchronises, bitwise repeatable.
@@ -305,8 +307,9 @@ fe_status fe_dg_pattern(int32_t n_blocks, const int64_t *n_cells, const int32_t 
  *   FE_NUMERIC_GEOMETRY, FE_NUMERIC_FUSED : the two halves of the fused
  *       FE_NUMERIC, for callers that keep the coordinates fixed over several
  *       assemblies or time the halves: GEOMETRY writes the per-cell factor
- *       records into the workspace, FUSED runs the fused kernels on the
- *       records the last GEOMETRY (or FE_NUMERIC) call left in that
+ *       records (for hexahedra also |det J| at every quadrature point) into
+ *       the workspace, FUSED runs the fused kernels on the records the last
+ *       GEOMETRY (or, for simplices, FE_NUMERIC) call left in that
  *       workspace.  FE_EUNSUPPORTED when the fused path does not apply.
  * Errors: FE_EINVAL (NULL pointers, dof entries out of range are reported
  * through the status word of the plan), FE_ESIZE, FE_EUNSUPPORTED, FE_EHIP.

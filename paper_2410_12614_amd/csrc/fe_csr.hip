@@ -617,7 +617,12 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
   const size_t geo_offset = a256((size_t)n_forms * n_cells * n_phi * n_phi * elt);
   // per-form factor records of the fused path (FormGeo<double> is the larger)
   const size_t geo_bytes = a256(sizeof(FormGeo<double>) * (size_t)n_cells);
-  const size_t ws_need = std::max<size_t>(256, geo_offset + (size_t)n_forms * geo_bytes);
+  // hexahedra: per-form per-point factors [n_cells][n_q_pad] (at most FP64)
+  const size_t zpt_offset = geo_offset + (size_t)n_forms * geo_bytes;
+  size_t zpt_bytes = 0;
+  for (int f = 0; f < n_forms; ++f)
+    if (L[f].box) zpt_bytes = std::max(zpt_bytes, a256((size_t)n_cells * L[f].n_q_pad * 8));
+  const size_t ws_need = std::max<size_t>(256, zpt_offset + (size_t)n_forms * zpt_bytes);
   const bool numeric = phase == FE_NUMERIC || phase == FE_NUMERIC_GATHER ||
                        phase == FE_NUMERIC_GEOMETRY || phase == FE_NUMERIC_FUSED;
   if (!plan || (numeric && !workspace)) {
@@ -765,11 +770,16 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
   if (n_cells == 0) return FE_OK;  // values of an empty pattern: nothing to write
   // Forms whose tables fit on chip take the fused row-ownership path when the
   // FILL phase built its schedule; the others (coefficient forms, tables too
-  // large) take the cell kernels and the row gather.
+  // large) take the cell kernels and the row gather.  Hexahedral forms take
+  // the gather under FE_NUMERIC: their rows are long (up to (2p+1)^3
+  // entries), so a task of FUSED_SPAN entries holds few rows and its tiles
+  // few columns (about 7 of 16 for Q4), and the gather is the faster path;
+  // the explicit halves FE_NUMERIC_GEOMETRY / FE_NUMERIC_FUSED run them fused.
   bool on_fused[4] = {false, false, false, false};
   int n_fused = 0;
   for (int f = 0; f < n_forms; ++f) {
-    on_fused[f] = phase != FE_NUMERIC_GATHER && mats[0].schedule > 0 && fused_eligible(L[f]);
+    on_fused[f] = phase != FE_NUMERIC_GATHER && mats[0].schedule > 0 && fused_eligible(L[f]) &&
+                  !(phase == FE_NUMERIC && L[f].box);
     n_fused += on_fused[f] ? 1 : 0;
   }
   if ((phase == FE_NUMERIC_GEOMETRY || phase == FE_NUMERIC_FUSED) && n_fused < n_forms)
@@ -780,7 +790,7 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
       if (on_fused[f]) fl[nf++] = f;
     // passes: two forms share one pass when they fit it together
     const FormLayout *pairL[2] = {&L[fl[0]], nf > 1 ? &L[fl[1]] : &L[fl[0]]};
-    const bool pair = nf == 2 && fused_pair_fits(pairL);
+    const bool pair = nf == 2 && fused_pair_fits(pairL) && !pairL[0]->box && !pairL[1]->box;
     for (int i = 0; i < nf; i += pair ? 2 : 1) {
       const int f = fl[i];
       FusedLaunch a;
@@ -796,6 +806,9 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
             a.geo_bufs[a.geo_forms] = (const unsigned char *)form_bufs[fl[e]];
             a.geo_nd[a.geo_forms] = L[fl[e]].nd;
             a.geo_out[a.geo_forms] = (unsigned char *)workspace + geo_offset + fl[e] * geo_bytes;
+            a.geo_zpt[a.geo_forms] =
+                L[fl[e]].box ? (unsigned char *)workspace + zpt_offset + fl[e] * zpt_bytes : nullptr;
+            a.geo_L[a.geo_forms] = &L[fl[e]];
             ++a.geo_forms;
           }
       a.nforms = pair ? 2 : 1;
@@ -807,6 +820,7 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
         a.L[e] = &L[g];
         a.form_buf[e] = (const unsigned char *)form_bufs[g];
         a.geo[e] = (unsigned char *)workspace + geo_offset + g * geo_bytes;
+        a.zpt[e] = L[g].box ? (unsigned char *)workspace + zpt_offset + g * zpt_bytes : nullptr;
         a.values[e] = mats[g].values;
       }
       a.coords = m->cell_coords;

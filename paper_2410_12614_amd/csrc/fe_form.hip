@@ -273,7 +273,7 @@ bool fused_eligible(const FormLayout &L) {
   // buffers of at least 8 waves; otherwise the cell kernels and the row
   // gather are faster
   const FormLayout *one[1] = {&L};
-  return !L.has_coeff && !L.box && fused_lds(one, 1, 8, true) <= FUSED_LDS_BUDGET;
+  return !L.has_coeff && fused_lds(one, 1, 8, true) <= FUSED_LDS_BUDGET;
 }
 
 fe_status launch_cell(const CellLaunch &a) {

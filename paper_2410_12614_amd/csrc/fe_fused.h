@@ -42,6 +42,7 @@ struct FusedForm {
   const unsigned char *afrag, *afrag_lo;
   const void *wtab;
   const void *geo;        // FormGeo<T>[n_cells]
+  const void *zpt;        // hexahedra: per-point factors [n_cells][n_q_pad] (type of H)
   void *values;
   int n_q_pad, nks;
 };
@@ -92,6 +93,50 @@ __global__ __launch_bounds__(256) void k_form_geo(const double *coords, int64_t 
     ((FormGeo<T> *)g.out[f])[c] = r;
     if (!ok) atomicOr(g.status[f], STATUS_DEGENERATE);
   }
+}
+
+// Factors of a hexahedral mass form, one thread per cell: |det J(X_q)| of the
+// trilinear map at every quadrature point (FP64), normalised by the exact
+// power of two 2^-e that brings their maximum into [1, 2), stored in the type
+// of H ([n_cells][n_q_pad], zero padding); the record holds the scaled
+// geometry factor sigma_K and the exact inverse of all scales times 2^e.
+template <class P>
+__global__ __launch_bounds__(256) void k_box_geo(const double *coords, int64_t n_cells, int n_q,
+                                                 int n_q_pad, const double *ptab,
+                                                 const FormHeader *hdr, FormGeo<typename P::real> *out,
+                                                 typename P::hreal *zpt, int32_t *status) {
+  typedef typename P::real T;
+  typedef typename P::hreal HT;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cells) return;
+  double x[24];
+  for (int e = 0; e < 24; ++e) x[e] = coords[c * 24 + e];
+  double zmax = 0.0;
+  bool ok = true;
+  for (int q = 0; q < n_q; ++q) {
+    const double dj = box_det(x, ptab + 3 * q);
+    ok = ok && dj != 0.0 && isfinite(dj);
+    zmax = fmax(zmax, fabs(dj));
+  }
+  int ez = 0;
+  if (ok && zmax > 0.0) ez = ilogb(zmax);
+  HT *zr = zpt + c * n_q_pad;
+  for (int q = 0; q < n_q_pad; ++q) {
+    double v = 0.0;
+    if (q < n_q) v = ok ? ldexp(fabs(box_det(x, ptab + 3 * q)), -ez) : NAN;
+    zr[q] = (HT)v;
+  }
+  double G[3][3] = {{1, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  typename P::hreal Gp[3][3];
+  T inv;
+  cell_factors<P>(hdr, 1, true, ok, G, 1.0, ok ? ldexp(zmax, -ez) : 1.0, Gp, inv);
+  FormGeo<T> r;
+  r.g[0] = Gp[0][0];
+  r.g[1] = r.g[2] = r.g[3] = r.g[4] = r.g[5] = 0;
+  r.inv = (T)ldexp((double)inv, ez);
+  r.pad = 0;
+  out[c] = r;
+  if (!ok) atomicOr(status, STATUS_DEGENERATE);
 }
 
 __device__ __forceinline__ int lane_word1(const FusedLane &l) {
@@ -221,10 +266,10 @@ __device__ __forceinline__ void tile_addr(const uint16_t *const *rk, int rstride
 // from the staged weighted table (rows jv[u]), against the staged B^T
 // fragments (every fragment read serves all TT tiles).  K = (s, q) is
 // walked q-chunk outer, s inner, as in the cell kernel.
-template <class P, int MT, int NDT, bool STAGE_A, int TT>
+template <class P, int MT, int NDT, bool STAGE_A, int TT, bool PZ = false>
 __device__ __forceinline__ void tile_contract(const FormLds<P> &S, const FusedForm &F,
                                               const typename P::hreal (&Gs)[TT][3][3],
-                                              const int *jv, int lane, int kb,
+                                              const int *jv, const int *zc, int lane, int kb,
                                               typename P::acc (&acc)[TT][MT],
                                               typename P::acc (&acc2)[P::SPLIT ? TT : 1][P::SPLIT ? MT : 1]) {
   typedef typename P::real T;
@@ -254,6 +299,12 @@ __device__ __forceinline__ void tile_contract(const FormLds<P> &S, const FusedFo
   const HT *wcol[TT];
 #pragma unroll
   for (int u = 0; u < TT; ++u) wcol[u] = S.wt + (size_t)jv[u] * S.jstride + kb * KPL;
+  // hexahedra: the per-point factors of the tile column's cell, at this
+  // lane's K entries
+  const HT *zrow[TT];
+#pragma unroll
+  for (int u = 0; u < TT; ++u)
+    zrow[u] = PZ ? (const HT *)F.zpt + (size_t)zc[u] * F.n_q_pad + kb * KPL : nullptr;
   for (int qc = 0; qc < nqc; ++qc) {
     if constexpr (P::H16) {
       // the chunk's table reads first, then per s its fragments, H and the
@@ -275,7 +326,8 @@ __device__ __forceinline__ void tile_contract(const FormLds<P> &S, const FusedFo
         }
 #pragma unroll
         for (int u = 0; u < TT; ++u) {
-          const half8_t hf = form_h16<NDT>(g2[u][s], wv[u]);
+          half8_t hf = form_h16<NDT>(g2[u][s], wv[u]);
+          if constexpr (PZ) hf = hf * *(const half8_t *)(zrow[u] + qc * P::KSTEP);
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) acc[u][mt] = P::mma(af[mt], hf, acc[u][mt]);
         }
@@ -304,6 +356,12 @@ __device__ __forceinline__ void tile_contract(const FormLds<P> &S, const FusedFo
         for (int u = 0; u < TT; ++u) {
           T h[KPL];
           form_h<T, NDT, KPL>(Gs[u][s], wv[u], h);
+          if constexpr (PZ) {
+            T zz[KPL];
+            load_w<T, KPL>(zrow[u] + qc * P::KSTEP, zz);
+#pragma unroll
+            for (int e = 0; e < KPL; ++e) h[e] *= zz[e];
+          }
           if constexpr (P::SPLIT) {
             FRAG hh, hl;
             P::pack2(h, hh, hl);
@@ -348,7 +406,7 @@ __device__ __forceinline__ void tile_values(const typename P::acc (&acc)[TT][MT]
 // update the lane's private slot instead: no branch per entry).  `after_k`
 // runs between the contraction and the scatter (used to issue the next
 // task's loads).
-template <class P, int MT, int NDT, bool STAGE_A, int TT, class AfterK>
+template <class P, int MT, int NDT, bool STAGE_A, int TT, bool PZ, class AfterK>
 __device__ __forceinline__ void fused_tiles(const FormLds<P> &S, const FusedForm &F,
                                             const FormGeo<typename P::real> &cg, const int *src,
                                             const Column<typename P::real> *col,
@@ -363,9 +421,12 @@ __device__ __forceinline__ void fused_tiles(const FormLds<P> &S, const FusedForm
   int jv[TT];
 #pragma unroll
   for (int u = 0; u < TT; ++u) jv[u] = col[u].jv;
+  int zc[TT];
+#pragma unroll
+  for (int u = 0; u < TT; ++u) zc[u] = col[u].cell < 0 ? 0 : col[u].cell;
   typename P::acc acc[TT][MT];
   typename P::acc acc2[P::SPLIT ? TT : 1][P::SPLIT ? MT : 1];
-  tile_contract<P, MT, NDT, STAGE_A, TT>(S, F, Gs, jv, lane, kb, acc, acc2);
+  tile_contract<P, MT, NDT, STAGE_A, TT, PZ>(S, F, Gs, jv, zc, lane, kb, acc, acc2);
 
   after_k();
 
@@ -425,7 +486,7 @@ __device__ __forceinline__ void fused_tile_pair(const FormLds<P> &S0, const Form
     tile_factors<P, NDT0, TT>(cg0, src, Gs, inv);
     ACC acc[TT][MT];
     ACC acc2[P::SPLIT ? TT : 1][P::SPLIT ? MT : 1];
-    tile_contract<P, MT, NDT0, STAGE_A, TT>(S0, F0, Gs, jv, lane, kb, acc, acc2);
+    tile_contract<P, MT, NDT0, STAGE_A, TT>(S0, F0, Gs, jv, jv, lane, kb, acc, acc2);
 #pragma unroll
     for (int u = 0; u < TT; ++u) tile_values<P, MT, TT>(acc, acc2, u, inv[u], val0[u]);
   }
@@ -435,7 +496,7 @@ __device__ __forceinline__ void fused_tile_pair(const FormLds<P> &S0, const Form
     tile_factors<P, NDT1, TT>(cg1, src, Gs, inv);
     ACC acc[TT][MT];
     ACC acc2[P::SPLIT ? TT : 1][P::SPLIT ? MT : 1];
-    tile_contract<P, MT, NDT1, STAGE_A, TT>(S1, F1, Gs, jv, lane, kb, acc, acc2);
+    tile_contract<P, MT, NDT1, STAGE_A, TT>(S1, F1, Gs, jv, jv, lane, kb, acc, acc2);
 #pragma unroll
     for (int u = 0; u < TT; ++u) tile_values<P, MT, TT>(acc, acc2, u, inv[u], val1[u]);
   }
@@ -471,7 +532,8 @@ __device__ __forceinline__ void fused_tile_pair(const FormLds<P> &S0, const Form
 // PR: the two forms share one row buffer of value pairs and one pass over
 // each task's tiles (fused_tile_pair); else each form runs its own pass over
 // the tiles with its own row buffer contents.
-template <class P, int MT, int NDT0, int NDT1, int NF, bool STAGE_A, int NW, int TT, bool PR>
+template <class P, int MT, int NDT0, int NDT1, int NF, bool STAGE_A, int NW, int TT, bool PR,
+          bool PZ = false>
 __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
   typedef typename P::real T;
   typedef FormGeo<T> GEO;
@@ -577,18 +639,18 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
         } else if (tt == 2) {
           if constexpr (TT == 2) {
             if (f == 0)
-              fused_tiles<P, MT, NDT0, STAGE_A, 2>(S0, a.f[0], cg[0], src, col, rk, a.rstride,
+              fused_tiles<P, MT, NDT0, STAGE_A, 2, PZ>(S0, a.f[0], cg[0], src, col, rk, a.rstride,
                                                    lane, kb, rowbuf, after_k);
             else if constexpr (NF == 2)
-              fused_tiles<P, MT, NDT1, STAGE_A, 2>(S1, a.f[1], cg[NF - 1], src, col, rk,
+              fused_tiles<P, MT, NDT1, STAGE_A, 2, false>(S1, a.f[1], cg[NF - 1], src, col, rk,
                                                    a.rstride, lane, kb, rowbuf, after_k);
           }
         } else {
           if (f == 0)
-            fused_tiles<P, MT, NDT0, STAGE_A, 1>(S0, a.f[0], cg[0], src, col, rk, a.rstride, lane,
+            fused_tiles<P, MT, NDT0, STAGE_A, 1, PZ>(S0, a.f[0], cg[0], src, col, rk, a.rstride, lane,
                                                  kb, rowbuf, after_k);
           else if constexpr (NF == 2)
-            fused_tiles<P, MT, NDT1, STAGE_A, 1>(S1, a.f[1], cg[NF - 1], src, col, rk, a.rstride,
+            fused_tiles<P, MT, NDT1, STAGE_A, 1, false>(S1, a.f[1], cg[NF - 1], src, col, rk, a.rstride,
                                                  lane, kb, rowbuf, after_k);
         }
         tl += tt;
@@ -611,9 +673,10 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
   }
 }
 
-template <class P, int MT, int NDT0, int NDT1, int NF, bool SA, int NW, int TT, bool PR = false>
+template <class P, int MT, int NDT0, int NDT1, int NF, bool SA, int NW, int TT, bool PR = false,
+          bool PZ = false>
 static fe_status launch_fused_one(const FusedArgs &k, size_t smem, hipStream_t s) {
-  auto kern = fused_kernel<P, MT, NDT0, NDT1, NF, SA, NW, TT, PR>;
+  auto kern = fused_kernel<P, MT, NDT0, NDT1, NF, SA, NW, TT, PR, PZ>;
   if (smem > 65536 && hipFuncSetAttribute((const void *)kern,
                                           hipFuncAttributeMaxDynamicSharedMemorySize,
                                           (int)smem) != hipSuccess)
@@ -631,7 +694,7 @@ static fe_status launch_fused_one(const FusedArgs &k, size_t smem, hipStream_t s
   return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
 }
 
-template <class P, int MT, int NDT0, int NDT1, int NF>
+template <class P, int MT, int NDT0, int NDT1, int NF, bool PZ = false>
 static fe_status launch_fused_nw(const FusedArgs &k, const FormLayout *const *L, hipStream_t s) {
   // A pair shares one row buffer of value pairs (one scatter for both
   // forms) when that fits with 8 waves, two tiles per step where their
@@ -641,6 +704,14 @@ static fe_status launch_fused_nw(const FusedArgs &k, const FormLayout *const *L,
   // per step with the most waves per workgroup that fit with the fragments
   // staged (at least 8: see fused_eligible); there 16 waves with one tile
   // per step beat 12 waves with two tiles sharing each fragment read.
+  if constexpr (PZ) {
+    // hexahedra (single mass form): the 8-wave tile of the cell kernel's size
+    if (fused_lds(L, NF, 16, true) <= FUSED_LDS_BUDGET)
+      return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 16, 1, false, true>(k, fused_lds(L, NF, 16, true), s);
+    if (fused_lds(L, NF, 8, true) <= FUSED_LDS_BUDGET)
+      return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 8, 1, false, true>(k, fused_lds(L, NF, 8, true), s);
+    return FE_EUNSUPPORTED;
+  }
   if constexpr (NF == 2) {
     const size_t pr = fused_lds(L, NF, 8, true) + (size_t)8 * (FUSED_SPAN + 64) * sizeof(typename P::real);
     constexpr int PTT = (P::SPLIT || sizeof(typename P::real) == 8) ? 1 : 2;
@@ -663,8 +734,21 @@ fe_status launch_fused_impl(const FusedLaunch &a) {
   hipStream_t s = (hipStream_t)a.stream;
   for (int f = 0; f < a.nforms; ++f)
     if (!fused_eligible(*L[f])) return FE_EUNSUPPORTED;
-  if (a.nforms == 2 && !fused_pair_fits(L)) return FE_EUNSUPPORTED;
-  if (a.n_cells > 0 && a.geo_forms > 0) {
+  if (a.nforms == 2 && (!fused_pair_fits(L) || L[0]->box || L[1]->box)) return FE_EUNSUPPORTED;
+  if (a.n_cells > 0 && a.geo_forms > 0 && L[0]->box) {
+    // hexahedra: per cell |det J| at every quadrature point
+    for (int f = 0; f < a.geo_forms; ++f) {
+      const FormHeader *h = (const FormHeader *)a.geo_bufs[f];
+      const FormLayout &G = *a.geo_L[f];
+      if (!a.geo_zpt[f]) return FE_EINVAL;
+      hipLaunchKernelGGL(k_box_geo<P>, dim3((unsigned)((a.n_cells + 255) / 256)), dim3(256), 0, s,
+                         a.coords, a.n_cells, G.n_q, G.n_q_pad,
+                         (const double *)(a.geo_bufs[f] + G.off_ptab), h,
+                         (FormGeo<T> *)a.geo_out[f], (typename P::hreal *)a.geo_zpt[f],
+                         (int32_t *)a.geo_bufs[f]);
+    }
+    if (hipGetLastError() != hipSuccess) return FE_EHIP;
+  } else if (a.n_cells > 0 && a.geo_forms > 0) {
     GeoTargets g;
     g.nforms = a.geo_forms;
     for (int f = 0; f < a.geo_forms; ++f) {
@@ -678,6 +762,7 @@ fe_status launch_fused_impl(const FusedLaunch &a) {
     if (hipGetLastError() != hipSuccess) return FE_EHIP;
   }
   if (a.ntasks <= 0 || !a.run_fused) return FE_OK;
+  if (L[0]->box && !a.zpt[0]) return FE_EINVAL;
   FusedArgs k;
   for (int f = 0; f < 2; ++f) {
     const int e = f < a.nforms ? f : 0;
@@ -685,6 +770,7 @@ fe_status launch_fused_impl(const FusedLaunch &a) {
     k.f[f].afrag_lo = a.form_buf[e] + L[e]->off_afrag_lo;
     k.f[f].wtab = a.form_buf[e] + L[e]->off_wtab;
     k.f[f].geo = a.geo[e];
+    k.f[f].zpt = a.zpt[e];
     k.f[f].values = a.values[e];
     k.f[f].n_q_pad = L[e]->n_q_pad;
     k.f[f].nks = L[e]->nks;
@@ -700,6 +786,7 @@ fe_status launch_fused_impl(const FusedLaunch &a) {
 #define FE_FL(M)                                                                         \
   if (mt == M) {                                                                         \
     if (a.nforms == 1) {                                                                 \
+      if (L[0]->box) return launch_fused_nw<P, M, 1, 1, 1, true>(k, L, s);               \
       if (d0 == 1) return launch_fused_nw<P, M, 1, 1, 1>(k, L, s);                       \
       return launch_fused_nw<P, M, 3, 1, 1>(k, L, s);                                    \
     }                                                                                    \

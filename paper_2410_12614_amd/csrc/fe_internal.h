@@ -141,6 +141,7 @@ struct FusedLaunch {
   const FormLayout *L[2];
   const unsigned char *form_buf[2];
   void *geo[2];           // workspace: n_cells FormGeo records per form
+  void *zpt[2];           // hexahedra: per-point factors [n_cells][n_q_pad], else NULL
   void *values[2];
   const double *coords;   // device [n_cells][d+1][d]
   int64_t n_cells;
@@ -151,6 +152,8 @@ struct FusedLaunch {
   const unsigned char *geo_bufs[4];  // their form buffers (header, status word)
   int geo_nd[4];
   void *geo_out[4];
+  void *geo_zpt[4];                  // hexahedra: their per-point factors
+  const FormLayout *geo_L[4];
   const FusedTask *tasks;
   int64_t ntasks;         // tasks of the schedule (from the FILL phase)
   const FusedLane *lanes;
