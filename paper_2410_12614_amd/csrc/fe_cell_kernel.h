@@ -45,6 +45,9 @@ typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
+// four floats at a 4-byte aligned address (one 16-byte access in the
+// target's unaligned access mode)
+typedef float f4u_t __attribute__((ext_vector_type(4), aligned(4)));
 
 // ---- precision policies -------------------------------------------------
 // A/B operand layout of every 16x16 instruction used here: lane l holds
@@ -713,7 +716,9 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
       }
       // The tile holds column j of A_K (rows i); by the symmetry of the mass
       // and stiffness forms it is stored as row j, so each lane's rows land
-      // on consecutive addresses.
+      // on consecutive addresses: with single-precision outputs (rows 4 kb + r)
+      // a lane's four values are one 16-byte store (4-byte aligned: the
+      // target's unaligned access mode), the row tail element by element.
       if (valid && active) {
         T *A = (T *)a.A + (size_t)cell * nphi * nphi;
 #pragma unroll
@@ -722,15 +727,24 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
           for (int jj = 0; jj < JC; ++jj) {
             const int j = jb + jj;
             if (j < nphi) {
+              T v[4];
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
-                const int i = mt * 16 + P::row(kb, r);
-                if (i < nphi) {
-                  T v = acc[mt][jj][r];
-                  if constexpr (P::SPLIT) v += acc2[mt][jj][r] * (T)(1.0 / 2048.0);
-                  A[(size_t)j * nphi + i] = v * inv;
+                v[r] = acc[mt][jj][r];
+                if constexpr (P::SPLIT) v[r] += acc2[mt][jj][r] * (T)(1.0 / 2048.0);
+                v[r] *= inv;
+              }
+              T *dst = A + (size_t)j * nphi + mt * 16;
+              if constexpr (sizeof(T) == 4) {
+                const int i0 = 4 * kb;  // P::row(kb, r) = 4 kb + r
+                if (mt * 16 + i0 + 3 < nphi) {
+                  *(f4u_t *)(dst + i0) = f4u_t{v[0], v[1], v[2], v[3]};
+                  continue;
                 }
               }
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                if (mt * 16 + P::row(kb, r) < nphi) dst[P::row(kb, r)] = v[r];
             }
           }
       }
@@ -776,6 +790,9 @@ fe_status launch_cell_impl(const CellLaunch &a) {
   const FormLayout &L = *a.L;
   int mt, jc;
   tile_choice(L.n_phi, P::REGMUL, &mt, &jc);
+  // with per-point factors (their registers and the factor reads) 6 columns
+  // of 8 row tiles spill; 4 columns cover n_phi <= 128 in 8 passes
+  if ((L.has_coeff || L.box) && mt == 8 && jc == 6) jc = 4;
   KArgs k;
   k.afrag = a.form_buf + L.off_afrag;
   k.afrag_lo = a.form_buf + L.off_afrag_lo;
@@ -877,7 +894,7 @@ fe_status launch_cell_impl(const CellLaunch &a) {
   }
   if constexpr (P::REGMUL == 1) {
     FE_CASE(1, 4) FE_CASE(2, 8) FE_CASE(3, 9) FE_CASE(4, 7) FE_CASE(6, 7) FE_CASE(8, 6)
-    FE_CASE(11, 3)
+    FE_CASE(8, 4) FE_CASE(11, 3)
   } else {
     FE_CASE(1, 4) FE_CASE(2, 5) FE_CASE(3, 5) FE_CASE(4, 4) FE_CASE(6, 3) FE_CASE(8, 2)
     FE_CASE(11, 2)
