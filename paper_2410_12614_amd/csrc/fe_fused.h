@@ -655,18 +655,36 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
         }
         tl += tt;
       }
+      // write-back of the task's rows: single precision in groups of four
+      // consecutive entries per lane (one 16-byte store each), the rest one
+      // by one
+      const int s4 = sizeof(T) == 4 ? (span & ~3) : 0;
       if constexpr (PR) {
         typedef typename std::conditional<sizeof(T) == 4, float2, double2>::type T2;
         T *V0 = (T *)a.f[0].values + base;
         T *V1 = (T *)a.f[NF - 1].values + base;
-        for (int t = lane; t < span; t += 64) {
+        if constexpr (sizeof(T) == 4) {
+          for (int t = 4 * lane; t < s4; t += 256) {
+            const float4 p = *(const float4 *)(rowbuf + 2 * t);
+            const float4 q = *(const float4 *)(rowbuf + 2 * t + 4);
+            *(f4u_t *)(V0 + t) = f4u_t{p.x, p.z, q.x, q.z};
+            *(f4u_t *)(V1 + t) = f4u_t{p.y, p.w, q.y, q.w};
+          }
+        }
+        for (int t = s4 + lane; t < span; t += 64) {
           const T2 v = ((const T2 *)rowbuf)[t];
           V0[t] = v.x;
           V1[t] = v.y;
         }
       } else {
         T *V = (T *)a.f[f].values + base;
-        for (int t = lane; t < span; t += 64) V[t] = rowbuf[t];
+        if constexpr (sizeof(T) == 4) {
+          for (int t = 4 * lane; t < s4; t += 256) {
+            const float4 p = *(const float4 *)(rowbuf + t);
+            *(f4u_t *)(V + t) = f4u_t{p.x, p.y, p.z, p.w};
+          }
+        }
+        for (int t = s4 + lane; t < span; t += 64) V[t] = rowbuf[t];
       }
     }
     task = next;
