@@ -54,6 +54,18 @@ def test_tabulate_matches_oracle(lib, d, p, q):
     np.testing.assert_allclose(tab[1:], og, rtol=0, atol=1e-13 * np.abs(og).max())
 
 
+@pytest.mark.parametrize("p,q", [(1, 2), (2, 4), (3, 6), (4, 8), (2, 0)])
+def test_tabulate_hexahedron_matches_oracle(lib, p, q):
+    import oracle.hexahedra as H
+    pts, w, tab = api.fe_tabulate(L.FE_HEXAHEDRON, p, q)
+    opts, ow = H.tensor_rule(q)
+    ov, og = H.tabulate(p, opts)
+    np.testing.assert_allclose(pts, opts, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(w, ow, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(tab[0], ov, rtol=0, atol=5e-14)
+    np.testing.assert_allclose(tab[1:], og, rtol=0, atol=1e-13 * np.abs(og).max())
+
+
 def test_tabulate_values_only_and_sizes(lib):
     n_phi, n_q = ctypes.c_int32(), ctypes.c_int32()
     assert lib.fe_tabulate(3, 6, 14, 0, ctypes.byref(n_phi), ctypes.byref(n_q), None, None, None) == 0
