@@ -585,13 +585,13 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
 #pragma unroll
     for (int f = 0; f < (PR ? 1 : NF); ++f) {
       for (int tl = 0; tl < nt;) {
-        // tiles processed together: two while at least two remain
-        const int tt = (TT == 2 && tl + 1 < nt) ? 2 : 1;
-        int src[2];
-        Column<T> col[2];
-        const uint16_t *rk[2];
+        // tiles processed together: up to TT while that many remain
+        const int tt = min(TT, nt - tl);
+        int src[TT];
+        Column<T> col[TT];
+        const uint16_t *rk[TT];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < TT; ++u) {
           const int t = tl + (u < tt ? u : 0);
           // this lane's column: slot 16 t + n of the task
           src[u] = 16 * t + n;
@@ -626,8 +626,13 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
           }
         };
         if constexpr (PR) {
-          if (tt == 2) {
-            if constexpr (TT == 2)
+          if (tt == 3) {
+            if constexpr (TT == 3)
+              fused_tile_pair<P, MT, NDT0, NDT1, STAGE_A, 3>(S0, S1, a.f[0], a.f[1], cg[0],
+                                                             cg[NF - 1], src, col, rk, a.rstride,
+                                                             lane, kb, rowbuf, after_k);
+          } else if (tt == 2) {
+            if constexpr (TT >= 2)
               fused_tile_pair<P, MT, NDT0, NDT1, STAGE_A, 2>(S0, S1, a.f[0], a.f[1], cg[0],
                                                              cg[NF - 1], src, col, rk, a.rstride,
                                                              lane, kb, rowbuf, after_k);
@@ -637,7 +642,7 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
                                                            lane, kb, rowbuf, after_k);
           }
         } else if (tt == 2) {
-          if constexpr (TT == 2) {
+          if constexpr (TT >= 2) {
             if (f == 0)
               fused_tiles<P, MT, NDT0, STAGE_A, 2, PZ>(S0, a.f[0], cg[0], src, col, rk, a.rstride,
                                                    lane, kb, rowbuf, after_k);
@@ -715,10 +720,12 @@ static fe_status launch_fused_one(const FusedArgs &k, size_t smem, hipStream_t s
 template <class P, int MT, int NDT0, int NDT1, int NF, bool PZ = false>
 static fe_status launch_fused_nw(const FusedArgs &k, const FormLayout *const *L, hipStream_t s) {
   // A pair shares one row buffer of value pairs (one scatter for both
-  // forms) when that fits with 8 waves, two tiles per step where their
-  // accumulators fit the register file (measured on the benchmark workload,
-  // P4 mass + stiffness in FP16: 457 us against 472 us with one tile; the
-  // split and FP64 pairs spill with two and take one).  Otherwise one tile
+  // forms) when that fits with 8 waves, several tiles per step where their
+  // accumulators fit the register file: three in half precision (a task of
+  // the P4 benchmark workload mostly holds 33 to 48 columns, so one step
+  // covers it and each fragment read serves three tiles: 4 % faster than two
+  // per step, which was 3 % faster than one), two in FP32; the split and FP64
+  // pairs spill with two and take one.  Otherwise one tile
   // per step with the most waves per workgroup that fit with the fragments
   // staged (at least 8: see fused_eligible); there 16 waves with one tile
   // per step beat 12 waves with two tiles sharing each fragment read.
@@ -732,7 +739,7 @@ static fe_status launch_fused_nw(const FusedArgs &k, const FormLayout *const *L,
   }
   if constexpr (NF == 2) {
     const size_t pr = fused_lds(L, NF, 8, true) + (size_t)8 * (FUSED_SPAN + 64) * sizeof(typename P::real);
-    constexpr int PTT = (P::SPLIT || sizeof(typename P::real) == 8) ? 1 : 2;
+    constexpr int PTT = (P::SPLIT || sizeof(typename P::real) == 8) ? 1 : (P::H16 ? 3 : 2);
     if (pr <= FUSED_LDS_BUDGET)
       return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 8, PTT, true>(k, pr, s);
   }
