@@ -721,10 +721,11 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
       // target's unaligned access mode), the row tail element by element.
       if (valid && active) {
         T *A = (T *)a.A + (size_t)cell * nphi * nphi;
+        // row by row: consecutive stores of a lane fill consecutive addresses
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+        for (int jj = 0; jj < JC; ++jj)
 #pragma unroll
-          for (int jj = 0; jj < JC; ++jj) {
+          for (int mt = 0; mt < MT; ++mt) {
             const int j = jb + jj;
             if (j < nphi) {
               T v[4];
