@@ -62,8 +62,9 @@ enum {
  * trilinearly; its cell_coords are [n_cells][8][3], vertex v at the reference
  * corner (v & 1, (v >> 1) & 1, (v >> 2) & 1).  Hexahedra: Lagrange Q_p on the
  * equispaced lattice (n_phi = (p+1)^3, local index i + (p+1)(j + (p+1)k)),
- * tensor Gauss-Legendre quadrature, mass form only; J and |det J| vary over
- * the cell and enter per quadrature point. */
+ * tensor Gauss-Legendre quadrature; forms: the mass form with p <= 4 (other
+ * forms and degrees FE_EUNSUPPORTED); J and |det J| vary over the cell and
+ * enter per quadrature point. */
 enum { FE_TRIANGLE = 2, FE_TETRAHEDRON = 3, FE_HEXAHEDRON = 8 };
 
 /* Forms of Section 3.1. */
