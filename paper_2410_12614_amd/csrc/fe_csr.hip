@@ -503,13 +503,15 @@ __global__ __launch_bounds__(64) void k_slot_ranks(const FusedTask *tasks, const
 
 // Numeric gather: one wave per CSR row, NF forms, LDS window of W entries per
 // form.  The incident local rows are visited in adjacency order (cell
-// ascending, then local index); their loads are issued GROUP at a time and
-// the LDS additions then applied in that same order, so the sum of every
-// entry is formed in a fixed order.
+// ascending, then local index), each whole (its n_phi <= 64 CH entries in
+// chunks of 64 lanes); their loads are issued GROUP rows at a time
+// and the LDS additions then applied row after row, so every entry is summed
+// in cell-ascending order.
 constexpr int GATHER_W = 512;
 constexpr int GATHER_GROUP = 4;
+constexpr int GATHER_CH = 3;  // chunks of the longest local row (n_phi <= 192)
 
-template <class T, int NF>
+template <class T, int NF, int CH>
 __global__ __launch_bounds__(256) void k_gather(const int64_t *adj_ptr, const int64_t *adj,
                                                 const uint16_t *rank, const int64_t *row_ptr,
                                                 int64_t n_rows, int n_phi,
@@ -531,30 +533,38 @@ __global__ __launch_bounds__(256) void k_gather(const int64_t *adj_ptr, const in
     for (int r = lane; r < wl; r += 64)
 #pragma unroll
       for (int f = 0; f < NF; ++f) buf[f][r] = 0;
-    for (int j0 = 0; j0 < n_phi; j0 += 64) {
-      const int j = j0 + lane;
-      for (int64_t a = a0; a < a1; a += GATHER_GROUP) {
-        int rk[GATHER_GROUP];
-        T v[GATHER_GROUP][NF];
+    for (int64_t a = a0; a < a1; a += GATHER_GROUP) {
+      int rk[GATHER_GROUP][CH];
+      T v[GATHER_GROUP][CH][NF];
 #pragma unroll
-        for (int u = 0; u < GATHER_GROUP; ++u) {
-          rk[u] = -1;
-          if (a + u < a1 && j < n_phi) {
-            const int64_t ent = adj[a + u];
-            const size_t row = (size_t)(ent >> 8) * n_phi + (ent & 255);
-            const size_t base = row * n_phi + j;
-            rk[u] = (int)rank[base] - w0;
-#pragma unroll
-            for (int f = 0; f < NF; ++f) v[u][f] = A[f][base];
-          }
+      for (int u = 0; u < GATHER_GROUP; ++u) {
+        size_t row = 0;
+        if (a + u < a1) {
+          const int64_t ent = adj[a + u];
+          row = (size_t)(ent >> 8) * n_phi + (ent & 255);
         }
 #pragma unroll
-        for (int u = 0; u < GATHER_GROUP; ++u)
-          if (rk[u] >= 0 && rk[u] < wl) {
+        for (int ch = 0; ch < CH; ++ch) {
+          const int j = 64 * ch + lane;
+          rk[u][ch] = -1;
+          if (a + u < a1 && j < n_phi) {
+            const size_t base = row * n_phi + j;
+            rk[u][ch] = (int)rank[base] - w0;
 #pragma unroll
-            for (int f = 0; f < NF; ++f) buf[f][rk[u]] += v[u][f];
+            for (int f = 0; f < NF; ++f) v[u][ch][f] = A[f][base];
           }
+        }
       }
+      // the local row of entry a + u holds each column once: its chunks
+      // touch distinct entries, and rows are added in adjacency order
+#pragma unroll
+      for (int u = 0; u < GATHER_GROUP; ++u)
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch)
+          if (rk[u][ch] >= 0 && rk[u][ch] < wl) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) buf[f][rk[u][ch]] += v[u][ch][f];
+          }
     }
     for (int r = lane; r < wl; r += 64)
 #pragma unroll
@@ -566,8 +576,10 @@ template <class T, int NF>
 fe_status launch_gather(const int64_t *adj_ptr, const int64_t *adj, const uint16_t *rank,
                         const int64_t *row_ptr, int64_t n_rows, int n_phi, void *const *A,
                         void *const *V, hipStream_t s) {
+  if (n_phi > 64 * GATHER_CH) return FE_EUNSUPPORTED;
   const int64_t blocks = (n_rows + 3) / 4;
-  hipLaunchKernelGGL((k_gather<T, NF>), dim3((unsigned)blocks), dim3(256), 0, s, adj_ptr, adj, rank,
+  auto kern = n_phi <= 64 ? k_gather<T, NF, 1> : n_phi <= 128 ? k_gather<T, NF, 2> : k_gather<T, NF, 3>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, adj_ptr, adj, rank,
                      row_ptr, n_rows, n_phi, (const T *)A[0], (const T *)A[1], (const T *)A[2],
                      (const T *)A[3], (T *)V[0], (T *)V[1], (T *)V[2], (T *)V[3]);
   return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;

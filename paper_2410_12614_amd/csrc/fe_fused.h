@@ -96,10 +96,13 @@ __global__ __launch_bounds__(256) void k_form_geo(const double *coords, int64_t 
 }
 
 // Factors of a hexahedral mass form, one thread per cell: |det J(X_q)| of the
-// trilinear map at every quadrature point (FP64), normalised by the exact
-// power of two 2^-e that brings their maximum into [1, 2), stored in the type
-// of H ([n_cells][n_q_pad], zero padding); the record holds the scaled
-// geometry factor sigma_K and the exact inverse of all scales times 2^e.
+// trilinear map at every quadrature point (FP64, then in the type the cell
+// kernel evaluates per-point factors in), normalised by the exact power of
+// two 2^-e that brings their maximum into [1, 2), stored in the type of H
+// ([n_cells][n_q_pad], zero padding); the record holds the scaled geometry
+// factor sigma_K and the exact inverse of all scales times 2^e.  Every value
+// is rounded as in the cell kernel, so that both assembly paths give the
+// same bits.
 template <class P>
 __global__ __launch_bounds__(256) void k_box_geo(const double *coords, int64_t n_cells, int n_q,
                                                  int n_q_pad, const double *ptab,
@@ -107,6 +110,7 @@ __global__ __launch_bounds__(256) void k_box_geo(const double *coords, int64_t n
                                                  typename P::hreal *zpt, int32_t *status) {
   typedef typename P::real T;
   typedef typename P::hreal HT;
+  typedef typename P::zreal Z;
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n_cells) return;
   double x[24];
@@ -116,20 +120,24 @@ __global__ __launch_bounds__(256) void k_box_geo(const double *coords, int64_t n
   for (int q = 0; q < n_q; ++q) {
     const double dj = box_det(x, ptab + 3 * q);
     ok = ok && dj != 0.0 && isfinite(dj);
-    zmax = fmax(zmax, fabs(dj));
+    zmax = fmax(zmax, fabs((double)(Z)fabs(dj)));
   }
   int ez = 0;
-  if (ok && zmax > 0.0) ez = ilogb(zmax);
+  if (ok && zmax > 0.0 && isfinite(zmax)) {
+    ez = ilogb(zmax);
+    zmax = ldexp(zmax, -ez);
+  }
+  const T zs = (T)ldexp(1.0, -ez);
   HT *zr = zpt + c * n_q_pad;
   for (int q = 0; q < n_q_pad; ++q) {
-    double v = 0.0;
-    if (q < n_q) v = ok ? ldexp(fabs(box_det(x, ptab + 3 * q)), -ez) : NAN;
+    T v = 0;
+    if (q < n_q) v = ok ? (T)(Z)fabs(box_det(x, ptab + 3 * q)) * zs : (T)NAN;
     zr[q] = (HT)v;
   }
   double G[3][3] = {{1, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  typename P::hreal Gp[3][3];
+  HT Gp[3][3];
   T inv;
-  cell_factors<P>(hdr, 1, true, ok, G, 1.0, ok ? ldexp(zmax, -ez) : 1.0, Gp, inv);
+  cell_factors<P>(hdr, 1, true, ok, G, 1.0, ok ? zmax : 1.0, Gp, inv);
   FormGeo<T> r;
   r.g[0] = Gp[0][0];
   r.g[1] = r.g[2] = r.g[3] = r.g[4] = r.g[5] = 0;

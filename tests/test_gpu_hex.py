@@ -59,7 +59,7 @@ def test_hex_mass_local_and_assembled(p, prec):
     rp, ci, ref = oracle.assemble(m.dofmap, A_ref, m.n_dofs)
     np.testing.assert_array_equal(asm.row_ptr.cpu().numpy(), rp)
     np.testing.assert_array_equal(asm.col_idx[:asm.nnz].cpu().numpy(), ci)
-    e_glob = {}
+    e_glob, got = {}, {}
     for path in ("fused", "gather"):
         asm.values[0].fill_(float("nan"))
         if path == "fused":             # the two halves exist only on the fused path
@@ -76,9 +76,13 @@ def test_hex_mass_local_and_assembled(p, prec):
             vals = asm.numeric(gather=True)[0]
         torch.cuda.synchronize()
         assert all(s == 0 for s in asm.status())
-        e_glob[path] = _err(vals[:asm.nnz].double().cpu().numpy(), ref, prec)
+        got[path] = vals[:asm.nnz].clone()
+        e_glob[path] = _err(got[path].double().cpu().numpy(), ref, prec)
     say(f"  local {e_loc:.2e}  assembled " + "  ".join(f"{k} {v:.2e}" for k, v in e_glob.items()))
     assert e_loc <= TOL[prec] and max(e_glob.values()) <= TOL[prec]
+    if "fused" in got:
+        # both paths round every factor alike and sum in cell order: same bits
+        assert torch.equal(got["fused"], got["gather"]), (p, prec)
 
 
 def test_hex_unsupported_cases():

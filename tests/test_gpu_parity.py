@@ -139,7 +139,8 @@ def test_all_degrees_local_matrices(p, q, prec):
 def test_fused_equals_gather_bitwise(prec, p, q):
     """The fused row-ownership path and the cell-kernel + row-gather path sum
     every entry in the same order (cell ascending) from the same matrix-core
-    columns, so their values agree bit for bit."""
+    columns, so their values agree bit for bit (local rows longer than 64
+    entries: the Q4 hexahedral case of the hexahedral tests)."""
     mesh = config_mesh("c2", n=3 if p < 5 else 2, degree=p)
     descs = [api.form_desc(3, p, q, f, prec) for f in ("mass", "stiffness")]
     mv = api.MeshView.from_numpy(mesh.cell_coords, mesh.dofmap, mesh.n_dofs)
