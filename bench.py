@@ -395,8 +395,8 @@ def measured_traffic():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is a design note, not an implemented path", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
+              "sharding over several GPUs is designed, not implemented", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
