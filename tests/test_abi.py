@@ -145,6 +145,19 @@ def test_assemble_size_query(lib):
     assert wb == ((local + 255) // 256) * 256 + 2 * 64 * 82944
 
 
+def test_assemble_size_query_hexahedra(lib):
+    d = api.form_desc(L.FE_HEXAHEDRON, 4, 8, "mass", "fp16")
+    n_cells, n_dofs = 54872, 3581577
+    st, pb, wb = _assemble_query(lib, [d], n_cells, n_dofs)
+    assert st == 0
+    assert pb >= n_cells * 125 * 125 * 2
+    # FP32 local matrices + factor records + the per-point factors (125
+    # points padded to 128, at most 8 bytes each) of the fused halves
+    a256 = lambda x: ((x + 255) // 256) * 256          # noqa: E731
+    local = n_cells * 125 * 125 * 4
+    assert wb == a256(local) + a256(64 * n_cells) + a256(n_cells * 128 * 8)
+
+
 def test_assemble_argument_errors(lib):
     d1 = api.form_desc(3, 4, 8, "mass", "fp16")
     d2 = api.form_desc(3, 3, 8, "stiffness", "fp16")
