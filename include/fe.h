@@ -296,10 +296,9 @@ fe_status fe_dg_pattern(int32_t n_blocks, const int64_t *n_cells, const int32_t 
  *       per-cell FP64 geometry pass and one fused kernel: every wave owns a
  *       range of CSR rows in LDS, computes the local rows A_K(j, :) of
  *       exactly the dofs it owns on the matrix cores and writes its rows
- *       once.  Otherwise, and always for hexahedral forms (their long rows
- *       leave the fused tiles mostly empty: the gather is faster), it runs
- *       the cell kernels into the workspace followed by the row gather.
- *       Either way every entry's
+ *       once (hexahedral forms: the geometry pass also evaluates |det J| at
+ *       every quadrature point).  Otherwise it runs the cell kernels into
+ *       the workspace followed by the row gather.  Either way every entry's
  *       contributions are summed in the fixed order cell ascending and every
  *       value is written exactly once (no separate zero-fill).
  *       Asynchronous, never synchronises, bitwise repeatable.
@@ -310,8 +309,7 @@ fe_status fe_dg_pattern(int32_t n_blocks, const int64_t *n_cells, const int32_t 
  *       assemblies or time the halves: GEOMETRY writes the per-cell factor
  *       records (for hexahedra also |det J| at every quadrature point) into
  *       the workspace, FUSED runs the fused kernels on the records the last
- *       GEOMETRY (or, for simplices, FE_NUMERIC) call left in that
- *       workspace.  FE_EUNSUPPORTED when the fused path does not apply.
+ *       GEOMETRY (or FE_NUMERIC) call left in that workspace.  FE_EUNSUPPORTED when the fused path does not apply.
  * Errors: FE_EINVAL (NULL pointers, dof entries out of range are reported
  * through the status word of the plan), FE_ESIZE, FE_EUNSUPPORTED, FE_EHIP.
  * ------------------------------------------------------------------------ */

@@ -782,16 +782,11 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
   if (n_cells == 0) return FE_OK;  // values of an empty pattern: nothing to write
   // Forms whose tables fit on chip take the fused row-ownership path when the
   // FILL phase built its schedule; the others (coefficient forms, tables too
-  // large) take the cell kernels and the row gather.  Hexahedral forms take
-  // the gather under FE_NUMERIC: their rows are long (up to (2p+1)^3
-  // entries), so a task of FUSED_SPAN entries holds few rows and its tiles
-  // few columns (about 7 of 16 for Q4), and the gather is the faster path;
-  // the explicit halves FE_NUMERIC_GEOMETRY / FE_NUMERIC_FUSED run them fused.
+  // large) take the cell kernels and the row gather.
   bool on_fused[4] = {false, false, false, false};
   int n_fused = 0;
   for (int f = 0; f < n_forms; ++f) {
-    on_fused[f] = phase != FE_NUMERIC_GATHER && mats[0].schedule > 0 && fused_eligible(L[f]) &&
-                  !(phase == FE_NUMERIC && L[f].box);
+    on_fused[f] = phase != FE_NUMERIC_GATHER && mats[0].schedule > 0 && fused_eligible(L[f]);
     n_fused += on_fused[f] ? 1 : 0;
   }
   if ((phase == FE_NUMERIC_GEOMETRY || phase == FE_NUMERIC_FUSED) && n_fused < n_forms)

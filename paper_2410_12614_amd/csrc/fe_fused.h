@@ -738,8 +738,9 @@ static fe_status launch_fused_nw(const FusedArgs &k, const FormLayout *const *L,
   // staged (at least 8: see fused_eligible); there 16 waves with one tile
   // per step beat 12 waves with two tiles sharing each fragment read.
   if constexpr (PZ) {
-    // hexahedra (single mass form): the 8-wave tile of the cell kernel's size
-    if (fused_lds(L, NF, 16, true) <= FUSED_LDS_BUDGET)
+    // hexahedra (single mass form): 16 waves where their 128 registers hold
+    // the tile (up to 4 row tiles; 6 and more spill), else 8
+    if (MT <= 4 && fused_lds(L, NF, 16, true) <= FUSED_LDS_BUDGET)
       return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 16, 1, false, true>(k, fused_lds(L, NF, 16, true), s);
     if (fused_lds(L, NF, 8, true) <= FUSED_LDS_BUDGET)
       return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 8, 1, false, true>(k, fused_lds(L, NF, 8, true), s);

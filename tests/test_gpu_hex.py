@@ -116,10 +116,10 @@ def test_hex_degenerate_cell_reports_status():
         assert st == L.FE_EDEGENERATE
 
 
-@pytest.mark.parametrize("path", ["numeric", "fused"])
+@pytest.mark.parametrize("path", ["numeric", "fused", "gather"])
 def test_hex_full_size_sampled_rows(path):
     # the Q4 mass workload: 38^3 = 54,872 jittered hexahedra, FP16; FE_NUMERIC
-    # (cell kernels + row gather for hexahedra) and the explicit fused halves
+    # (the fused pass), its explicit halves, and the cell kernels + row gather
     m = hex_mesh(38, 4, jitter=0.25, seed=0)
     say(f"[hex] full size ({path}): {m.cell_coords.shape[0]} cells, {m.n_dofs} dofs")
     mv = api.MeshView.from_numpy(m.cell_coords, m.dofmap, m.n_dofs)
@@ -128,7 +128,7 @@ def test_hex_full_size_sampled_rows(path):
         asm.numeric(part="geometry")
         vals = asm.numeric(part="fused")[0]
     else:
-        vals = asm.numeric()[0]
+        vals = asm.numeric(gather=path == "gather")[0]
     torch.cuda.synchronize()
     assert all(s == 0 for s in asm.status())
     rp = asm.row_ptr.cpu().numpy()
