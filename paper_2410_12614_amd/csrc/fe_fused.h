@@ -725,6 +725,20 @@ static fe_status launch_fused_one(const FusedArgs &k, size_t smem, hipStream_t s
   return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
 }
 
+// Whether an instantiation of the fused kernel keeps per-lane values in
+// scratch memory (register spills), as the compiled code object reports it;
+// asked once per instantiation.
+template <class P, int MT, int NDT0, int NDT1, int NF, bool SA, int NW, int TT, bool PR, bool PZ>
+static bool fused_spills() {
+  static const bool spills = [] {
+    hipFuncAttributes at;
+    return hipFuncGetAttributes(&at, (const void *)fused_kernel<P, MT, NDT0, NDT1, NF, SA, NW, TT, PR, PZ>) ==
+               hipSuccess &&
+           at.localSizeBytes > 0;
+  }();
+  return spills;
+}
+
 template <class P, int MT, int NDT0, int NDT1, int NF, bool PZ = false>
 static fe_status launch_fused_nw(const FusedArgs &k, const FormLayout *const *L, hipStream_t s) {
   // A pair shares one row buffer of value pairs (one scatter for both
@@ -735,12 +749,15 @@ static fe_status launch_fused_nw(const FusedArgs &k, const FormLayout *const *L,
   // per step, which was 3 % faster than one), two in FP32; the split and FP64
   // pairs spill with two and take one.  Otherwise one tile
   // per step with the most waves per workgroup that fit with the fragments
-  // staged (at least 8: see fused_eligible); there 16 waves with one tile
-  // per step beat 12 waves with two tiles sharing each fragment read.
+  // staged (at least 8: see fused_eligible) and hold the tile in registers
+  // (16 waves get 128 registers each, 12 get 168: larger tiles spill there,
+  // which cost the Q4 hexahedral pass more than half its time); there 16
+  // waves with one tile per step beat 12 waves with two tiles sharing each
+  // fragment read.
   if constexpr (PZ) {
-    // hexahedra (single mass form): 16 waves where their 128 registers hold
-    // the tile (up to 4 row tiles; 6 and more spill), else 8
-    if (MT <= 4 && fused_lds(L, NF, 16, true) <= FUSED_LDS_BUDGET)
+    // hexahedra (single mass form): 16 waves, else 8
+    if (fused_lds(L, NF, 16, true) <= FUSED_LDS_BUDGET &&
+        !fused_spills<P, MT, NDT0, NDT1, NF, true, 16, 1, false, true>())
       return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 16, 1, false, true>(k, fused_lds(L, NF, 16, true), s);
     if (fused_lds(L, NF, 8, true) <= FUSED_LDS_BUDGET)
       return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 8, 1, false, true>(k, fused_lds(L, NF, 8, true), s);
@@ -752,9 +769,11 @@ static fe_status launch_fused_nw(const FusedArgs &k, const FormLayout *const *L,
     if (pr <= FUSED_LDS_BUDGET)
       return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 8, PTT, true>(k, pr, s);
   }
-  if (fused_lds(L, NF, 16, true) <= FUSED_LDS_BUDGET)
+  if (fused_lds(L, NF, 16, true) <= FUSED_LDS_BUDGET &&
+      !fused_spills<P, MT, NDT0, NDT1, NF, true, 16, 1, false, false>())
     return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 16, 1>(k, fused_lds(L, NF, 16, true), s);
-  if (fused_lds(L, NF, 12, true) <= FUSED_LDS_BUDGET)
+  if (fused_lds(L, NF, 12, true) <= FUSED_LDS_BUDGET &&
+      !fused_spills<P, MT, NDT0, NDT1, NF, true, 12, 1, false, false>())
     return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 12, 1>(k, fused_lds(L, NF, 12, true), s);
   if (fused_lds(L, NF, 8, true) <= FUSED_LDS_BUDGET)
     return launch_fused_one<P, MT, NDT0, NDT1, NF, true, 8, 1>(k, fused_lds(L, NF, 8, true), s);
