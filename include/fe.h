@@ -286,8 +286,9 @@ fe_status fe_dg_pattern(int32_t n_blocks, const int64_t *n_cells, const int32_t 
  *       FE_EOVERFLOW when a row holds 65536 or more entries.
  *   FE_SYMBOLIC_FILL  : fills mats[0].col_idx (sorted) and the plan: the
  *       position of every local entry inside its CSR row and, when every
- *       row fits one owner task (at most 1024 entries and 64 incident
- *       (cell, local index) pairs), the row-ownership schedule of the fused
+ *       row fits one owner task (at most 1024 entries, 2048 when every form
+ *       is an FP16 hexahedral form, and 64 incident (cell, local index)
+ *       pairs), the row-ownership schedule of the fused
  *       numeric path; writes its task count into every mats[f].schedule.
  *       SYNCHRONISES the stream.
  *   FE_NUMERIC : writes the values of every form.  With a schedule

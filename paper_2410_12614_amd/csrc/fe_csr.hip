@@ -97,9 +97,10 @@ PlanLayout plan_layout(int64_t n_cells, int n_phi, int64_t n_dofs, bool f64rows)
 }
 
 // Row-ownership schedule of the fused numeric path (host, once per dof map).
-// Rows are packed in order into tasks of at most FUSED_SPAN CSR entries and
+// Rows are packed in order into tasks of at most SPAN CSR entries (FUSED_SPAN,
+// or FUSED_SPAN_BOX for hexahedral forms) and
 // FUSED_TILE_MAX tiles of 16 (cell, local index) pairs.  Among the feasible
-// ends of a task holding at least FUSED_SPAN / 2 entries, the one whose pairs
+// ends of a task holding at least SPAN / 2 entries, the one whose pairs
 // fill their tiles best is taken (then the longest), since idle lanes of a
 // partial tile cost as much as busy ones.  The task's pairs are then dealt
 // into tiles (below); lanes of one tile holding the same row carry
@@ -107,7 +108,7 @@ PlanLayout plan_layout(int64_t n_cells, int n_phi, int64_t n_dofs, bool f64rows)
 // too long or has too many pairs, or the bounds of the layout would be
 // exceeded.
 bool build_fused_schedule(const std::vector<int64_t> &rp, const std::vector<int64_t> &ap,
-                          const std::vector<int64_t> &adj, int64_t n_rows,
+                          const std::vector<int64_t> &adj, int64_t n_rows, int SPAN,
                           const PlanLayout &P, std::vector<FusedTask> &tasks,
                           std::vector<FusedLane> &lanes) {
   tasks.clear();
@@ -120,12 +121,12 @@ bool build_fused_schedule(const std::vector<int64_t> &rp, const std::vector<int6
     int64_t best_end = -1, best_pairs = 0, best_span = 0;
     while (r < n_rows) {
       const int64_t len = rp[r + 1] - rp[r], deg = ap[r + 1] - ap[r];
-      if (len > FUSED_SPAN || deg > PAIRS_MAX) return false;
-      if (r > r0 && (span + len > FUSED_SPAN || npairs + deg > PAIRS_MAX)) break;
+      if (len > SPAN || deg > PAIRS_MAX) return false;
+      if (r > r0 && (span + len > SPAN || npairs + deg > PAIRS_MAX)) break;
       span += len;
       npairs += deg;
       ++r;
-      if (2 * span >= FUSED_SPAN) {
+      if (2 * span >= SPAN) {
         // fill fraction npairs / (16 ceil(npairs / 16)), compared exactly
         const int64_t tiles = (npairs + 15) / 16, btiles = (best_pairs + 15) / 16;
         bool better = best_end < 0;
@@ -452,7 +453,7 @@ __global__ __launch_bounds__(256) void k_ranks(const int32_t *dofmap, int64_t n_
 // i.e. local row i = 16 mt + row(kb, r)), the LDS byte offset of the entry
 // inside the owning wave's row buffer: rowoff + rank of dof(K, i) in row
 // dof(K, j), or, for padding rows i >= n_phi, the private slot
-// FUSED_SPAN + 16 kb + n of that lane.  Bit 15 marks the first contribution
+// span + 16 kb + n of that lane.  Bit 15 marks the first contribution
 // to its entry in the order the fused kernel applies them (tile, then
 // round): that one is stored rather than added, so the row buffer needs no
 // clearing.  One workgroup per task.
@@ -460,11 +461,11 @@ constexpr uint16_t SRANK_FIRST = 0x8000;
 
 __global__ __launch_bounds__(64) void k_slot_ranks(const FusedTask *tasks, const FusedLane *lanes,
                                                    const uint16_t *rank, int n_phi, int sstride,
-                                                   bool f64rows, int elt, uint16_t *srank) {
-  __shared__ int owner[FUSED_SPAN];
+                                                   bool f64rows, int elt, int span, uint16_t *srank) {
+  __shared__ int owner[FUSED_SPAN_BOX];
   const FusedTask tk = tasks[blockIdx.x];
   const int nent = tk.nt * 16 * sstride;
-  for (int u = threadIdx.x; u < FUSED_SPAN; u += 64) owner[u] = 0x7fffffff;
+  for (int u = threadIdx.x; u < span; u += 64) owner[u] = 0x7fffffff;
   __syncthreads();
   // pass 1: the earliest (tile, round) contributing to every entry
   for (int u = threadIdx.x; u < nent; u += 64) {
@@ -494,7 +495,7 @@ __global__ __launch_bounds__(64) void k_slot_ranks(const FusedTask *tasks, const
       off = pos;
       first = owner[pos] == (slot >> 4) * 16 + (L.round & 15);
     } else {
-      off = FUSED_SPAN + 16 * kb + n;
+      off = span + 16 * kb + n;
       first = true;
     }
     srank[(size_t)pair * sstride + e] = (uint16_t)(off * elt) | (first ? SRANK_FIRST : 0);
@@ -745,7 +746,9 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
     // fused schedule (host): needs row_ptr and the sorted adjacency
     h.ntasks = 0;
     h.ntiles = 0;
-    if (h.max_len <= FUSED_SPAN && n_cells > 0) {
+    // task span: longer for hexahedral forms (all forms share the cell type)
+    const int span = assembly_span(L, n_forms);
+    if (h.max_len <= span && n_cells > 0) {
       std::vector<int64_t> rp(n_dofs + 1), apv(n_dofs + 1), adjv((size_t)n_cells * n_phi);
       if (hipMemcpy(rp.data(), row_ptr, sizeof(int64_t) * rp.size(), hipMemcpyDeviceToHost) != hipSuccess ||
           hipMemcpy(apv.data(), adj_ptr, sizeof(int64_t) * apv.size(), hipMemcpyDeviceToHost) != hipSuccess ||
@@ -753,7 +756,7 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
         return FE_EHIP;
       std::vector<FusedTask> tasks;
       std::vector<FusedLane> lanes;
-      if (build_fused_schedule(rp, apv, adjv, n_dofs, P, tasks, lanes)) {
+      if (build_fused_schedule(rp, apv, adjv, n_dofs, span, P, tasks, lanes)) {
         if (hipMemcpy(pb + P.off_tasks, tasks.data(), sizeof(FusedTask) * tasks.size(),
                       hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(pb + P.off_lanes, lanes.data(), sizeof(FusedLane) * lanes.size(),
@@ -764,7 +767,7 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
         hipLaunchKernelGGL(k_slot_ranks, dim3((unsigned)tasks.size()), dim3(64), 0, s,
                            (const FusedTask *)(pb + P.off_tasks),
                            (const FusedLane *)(pb + P.off_lanes), (const uint16_t *)rank, n_phi,
-                           P.sstride, forms[0].precision == FE_FP64, (int)elt,
+                           P.sstride, forms[0].precision == FE_FP64, (int)elt, span,
                            (uint16_t *)(pb + P.off_srank));
         if (hipGetLastError() != hipSuccess || !sync_ok(s)) return FE_EHIP;
       }
@@ -837,6 +840,7 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
       a.lanes = (const FusedLane *)(pb + P.off_lanes);
       a.srank = (const uint16_t *)(pb + P.off_srank);
       a.rstride = P.sstride;
+      a.span = assembly_span(L, n_forms);
       a.stream = stream;
       fe_status st = launch_fused(a);
       if (st != FE_OK) return st;

@@ -55,6 +55,7 @@ struct FusedArgs {
   const uint16_t *srank;  // [pairs][rstride], schedule order: LDS byte offsets of a lane's outputs
                           // (lane order, four per row tile; entries past rstride are padding)
   int n_phi, rstride;
+  int span;               // CSR entries of a task's row buffer (FUSED_SPAN or FUSED_SPAN_BOX)
 };
 
 // Geometry pass: FP64 geometry of every cell (Section 4.2), once, and the
@@ -253,9 +254,9 @@ __device__ __forceinline__ void tile_factors(const FormGeo<typename P::real> &cg
 // 8-byte load).  Padding rows point at the lane's private slot; bit 15 marks
 // the first contribution to an entry.
 template <class T, int MT, int TT>
-__device__ __forceinline__ void tile_addr(const uint16_t *const *rk, int rstride, int lane,
+__device__ __forceinline__ void tile_addr(const uint16_t *const *rk, int rstride, int span, int lane,
                                           int kb, int (&addr)[TT][MT][4]) {
-  const int dummy = (FUSED_SPAN * (int)sizeof(T) + lane * (int)sizeof(T)) | 0x8000;
+  const int dummy = (span * (int)sizeof(T) + lane * (int)sizeof(T)) | 0x8000;
 #pragma unroll
   for (int u = 0; u < TT; ++u)
 #pragma unroll
@@ -418,14 +419,15 @@ template <class P, int MT, int NDT, bool STAGE_A, int TT, bool PZ, class AfterK>
 __device__ __forceinline__ void fused_tiles(const FormLds<P> &S, const FusedForm &F,
                                             const FormGeo<typename P::real> &cg, const int *src,
                                             const Column<typename P::real> *col,
-                                            const uint16_t *const *rk, int rstride, int lane,
-                                            int kb, typename P::real *rowbuf, AfterK after_k) {
+                                            const uint16_t *const *rk, int rstride, int span,
+                                            int lane, int kb, typename P::real *rowbuf,
+                                            AfterK after_k) {
   typedef typename P::real T;
   typename P::hreal Gs[TT][3][3];
   T inv[TT];
   tile_factors<P, NDT, TT>(cg, src, Gs, inv);
   int addr[TT][MT][4];
-  tile_addr<T, MT, TT>(rk, rstride, lane, kb, addr);
+  tile_addr<T, MT, TT>(rk, rstride, span, lane, kb, addr);
   int jv[TT];
 #pragma unroll
   for (int u = 0; u < TT; ++u) jv[u] = col[u].jv;
@@ -478,12 +480,13 @@ __device__ __forceinline__ void fused_tile_pair(const FormLds<P> &S0, const Form
                                                 const FormGeo<typename P::real> &cg0,
                                                 const FormGeo<typename P::real> &cg1,
                                                 const int *src, const Column<typename P::real> *col,
-                                                const uint16_t *const *rk, int rstride, int lane,
-                                                int kb, typename P::real *rowbuf, AfterK after_k) {
+                                                const uint16_t *const *rk, int rstride, int span,
+                                                int lane, int kb, typename P::real *rowbuf,
+                                                AfterK after_k) {
   typedef typename P::real T;
   typedef typename P::acc ACC;
   int addr[TT][MT][4];
-  tile_addr<T, MT, TT>(rk, rstride, lane, kb, addr);
+  tile_addr<T, MT, TT>(rk, rstride, span, lane, kb, addr);
   int jv[TT];
 #pragma unroll
   for (int u = 0; u < TT; ++u) jv[u] = col[u].jv;
@@ -554,7 +557,7 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
   FormLds<P> S0, S1;
   unsigned char *end = stage_form<P, MT, NDT0, STAGE_A, NW>(smem, a.f[0], nphi, tid, S0);
   if constexpr (NF == 2) end = stage_form<P, MT, NDT1, STAGE_A, NW>(end, a.f[1], nphi, tid, S1);
-  T *rowbuf = (T *)end + (size_t)wave * (FUSED_SPAN + 64) * (PR ? 2 : 1);
+  T *rowbuf = (T *)end + (size_t)wave * (a.span + 64) * (PR ? 2 : 1);
   __syncthreads();
 
   const int ntasks = a.ntasks;
@@ -637,33 +640,33 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
           if (tt == 3) {
             if constexpr (TT == 3)
               fused_tile_pair<P, MT, NDT0, NDT1, STAGE_A, 3>(S0, S1, a.f[0], a.f[1], cg[0],
-                                                             cg[NF - 1], src, col, rk, a.rstride,
+                                                             cg[NF - 1], src, col, rk, a.rstride, a.span,
                                                              lane, kb, rowbuf, after_k);
           } else if (tt == 2) {
             if constexpr (TT >= 2)
               fused_tile_pair<P, MT, NDT0, NDT1, STAGE_A, 2>(S0, S1, a.f[0], a.f[1], cg[0],
-                                                             cg[NF - 1], src, col, rk, a.rstride,
+                                                             cg[NF - 1], src, col, rk, a.rstride, a.span,
                                                              lane, kb, rowbuf, after_k);
           } else {
             fused_tile_pair<P, MT, NDT0, NDT1, STAGE_A, 1>(S0, S1, a.f[0], a.f[1], cg[0],
-                                                           cg[NF - 1], src, col, rk, a.rstride,
+                                                           cg[NF - 1], src, col, rk, a.rstride, a.span,
                                                            lane, kb, rowbuf, after_k);
           }
         } else if (tt == 2) {
           if constexpr (TT >= 2) {
             if (f == 0)
-              fused_tiles<P, MT, NDT0, STAGE_A, 2, PZ>(S0, a.f[0], cg[0], src, col, rk, a.rstride,
+              fused_tiles<P, MT, NDT0, STAGE_A, 2, PZ>(S0, a.f[0], cg[0], src, col, rk, a.rstride, a.span,
                                                    lane, kb, rowbuf, after_k);
             else if constexpr (NF == 2)
               fused_tiles<P, MT, NDT1, STAGE_A, 2, false>(S1, a.f[1], cg[NF - 1], src, col, rk,
-                                                   a.rstride, lane, kb, rowbuf, after_k);
+                                                   a.rstride, a.span, lane, kb, rowbuf, after_k);
           }
         } else {
           if (f == 0)
-            fused_tiles<P, MT, NDT0, STAGE_A, 1, PZ>(S0, a.f[0], cg[0], src, col, rk, a.rstride, lane,
+            fused_tiles<P, MT, NDT0, STAGE_A, 1, PZ>(S0, a.f[0], cg[0], src, col, rk, a.rstride, a.span, lane,
                                                  kb, rowbuf, after_k);
           else if constexpr (NF == 2)
-            fused_tiles<P, MT, NDT1, STAGE_A, 1, false>(S1, a.f[1], cg[NF - 1], src, col, rk, a.rstride,
+            fused_tiles<P, MT, NDT1, STAGE_A, 1, false>(S1, a.f[1], cg[NF - 1], src, col, rk, a.rstride, a.span,
                                                  lane, kb, rowbuf, after_k);
         }
         tl += tt;
@@ -834,6 +837,8 @@ fe_status launch_fused_impl(const FusedLaunch &a) {
   k.srank = a.srank;
   k.n_phi = L[0]->n_phi;
   k.rstride = a.rstride;
+  k.span = a.span;
+  if (k.span < FUSED_SPAN || k.span > fused_span(*L[0])) return FE_EINVAL;
   const int mt = L[0]->mt;
   const int d0 = L[0]->ndt, d1 = a.nforms == 2 ? L[1]->ndt : 1;
 #define FE_FL(M)                                                                         \

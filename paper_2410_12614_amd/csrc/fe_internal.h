@@ -102,6 +102,10 @@ fe_status launch_cell(const CellLaunch &a);
 
 // ---- fused (row-ownership) numeric path, see fe_fused.h ----
 constexpr int FUSED_SPAN = 1024;    // CSR entries per task (LDS row buffer of one wave)
+// Hexahedral forms: rows of up to (2p+1)^3 entries (729 at Q4), so tasks of
+// 1024 entries would hold one or two rows and fill half a tile; with half
+// tables (FP16) their tasks hold up to 2048 and 8 waves still fit.
+constexpr int FUSED_SPAN_BOX = 2048;
 constexpr int FUSED_TILE_MAX = 4;   // tiles per task: one lane record per lane of a wave
 
 struct FusedTask {
@@ -159,6 +163,7 @@ struct FusedLaunch {
   const FusedLane *lanes;
   const uint16_t *srank;  // [pairs][rstride]: LDS byte offsets, see fe_fused.h
   int rstride;
+  int span;               // the schedule's task span (assembly_span)
   void *stream;
 };
 
@@ -166,9 +171,21 @@ struct FusedLaunch {
 // form the weighted table (always staged: it is read per lane with 16
 // different rows per K-slot) and the B^T fragments if staged, and one row
 // buffer (plus a private slot per lane) per wave.
+inline int fused_span(const FormLayout &L) {
+  return (L.box && L.prec == FE_FP16_ACC32) ? FUSED_SPAN_BOX : FUSED_SPAN;
+}
+// the span of an assembly's schedule: the longer one only when every form
+// takes it (a form's LDS estimate with its own span is then exact, else an
+// upper bound)
+inline int assembly_span(const FormLayout *L, int n) {
+  for (int f = 0; f < n; ++f)
+    if (fused_span(L[f]) != FUSED_SPAN_BOX) return FUSED_SPAN;
+  return FUSED_SPAN_BOX;
+}
+
 inline size_t fused_lds(const FormLayout *const *L, int nforms, int nw, bool with_frags) {
   const size_t real = (L[0]->prec == FE_FP64) ? 8 : 4;
-  size_t bytes = (size_t)nw * (FUSED_SPAN + 64) * real;
+  size_t bytes = (size_t)nw * (fused_span(*L[0]) + 64) * real;
   for (int f = 0; f < nforms; ++f) {
     const FormLayout &F = *L[f];
     const size_t frag = (F.elt_bytes == 2) ? 16 : F.elt_bytes;
