@@ -40,6 +40,15 @@ Under "hex_mass": the mass form on hexahedra (the paper's boxed cells):
 step = FE_NUMERIC (cell kernels + row-gather assembly into CSR), FP16
 storage / FP32 accumulation, the FP64 path beside it.
 
+Under "weighted_p6": the weighted P6 stiffness form div(kappa grad u) on the
+32^3 x 6 mesh (196,608 cells, 84 dofs/cell, 512-point rule, kappa as above,
+FP64 geometry) in BF16, FP16, FP32 and FP64 (the precision sweep): one step
+= FE_NUMERIC (cell kernels with the coefficient at the points, then the row
+gather into CSR); every mode's cell kernel is also timed alone for its
+matrix-core roofline, and every mode's error is taken against the FP64
+result.  The P4 line also carries the BF16 and split-FP16 modes under
+"other_modes".
+
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -56,8 +65,10 @@ sys.path.insert(0, ROOT)
 # Peaks used for roofline fractions (MI355X published figures).
 PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "split": 2500.0, "fp32": 157.3, "fp64": 78.6}
-# vector ALU: 256 CUs x 4 SIMDs x 32 packed flops x 2.4 GHz (the published
-# fp32 vector figure; packed half runs at the same lane-pair rate)
+# vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2 operations per lane (packed
+# pair) x 2 flops per fused multiply-add x 2.4 GHz = 157.3 TFLOP/s, the
+# published packed FP32 vector figure; packed half FMAs run at the same
+# pair rate (unpacked FP32 is half of it, 78.6)
 PEAK_VALU_TFLOPS = 157.3
 
 # Measured HBM traffic of the fused pass (rocprofv3 FETCH_SIZE / WRITE_SIZE,
@@ -93,6 +104,10 @@ def parse():
                     help="cells (first n of the mesh) of the oracle sample of the mixed batch")
     ap.add_argument("--no-hex", action="store_true",
                     help="skip the hexahedral mass measurement")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the weighted P6 stiffness precision sweep")
+    ap.add_argument("--c3-cpu-cells", type=int, default=8192,
+                    help="cells (first n) of the oracle sample of the weighted stiffness step")
     ap.add_argument("--hex-cpu-cells", type=int, default=10000,
                     help="cells (first n) of the oracle sample of the hexahedral mass step")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -373,6 +388,104 @@ def hex_section(args, steps, warmup):
     return out
 
 
+def c3_section(args, steps, warmup):
+    """Weighted P6 stiffness (the coefficient workload) in BF16, FP16, FP32
+    and FP64: FE_NUMERIC (cell kernels + CSR assembly), each mode's cell
+    kernel timed alone for its matrix-core roofline, relative Frobenius error
+    of every mode against the FP64 result, and an oracle baseline sample."""
+    import numpy as np
+    import torch
+
+    from fe_inputs import config_mesh
+    from paper_2410_12614_amd import api
+
+    m = config_mesh("c3")
+    n_phi, n_q, q = 84, 512, 14
+    mv = api.MeshView.from_numpy(m.cell_coords, m.dofmap, m.n_dofs, m.coeff)
+    # algorithmic matrix-core work per cell: the contraction 2 n_phi^2 (d n_q)
+    # and the coefficient at the points 2 n_phi n_q (no padding counted)
+    f_con = 2 * n_phi ** 2 * 3 * n_q
+    f_coef = 2 * n_phi * n_q
+    flops = (f_con + f_coef) * m.n_cells
+    out = {"workload": "P6 weighted stiffness div(kappa grad u), 32^3 x 6 jittered Kuhn tetrahedra "
+                       "(196,608 cells, 84 dofs/cell), 512-point collapsed Gauss-Jacobi rule, "
+                       "kappa = exp(sin(2 pi x) cos(2 pi y) z) interpolated in P6, FP64 geometry",
+           "n_cells": m.n_cells, "n_dofs": m.n_dofs, "alg_flops": flops,
+           "alg_flops_per_cell": {"contraction": f_con, "coefficient": f_coef}}
+    modes, vals = {}, {}
+    # FP64 first: its values are the reference of the other modes' errors
+    for prec in ("fp64", "fp32", "bf16", "fp16"):
+        desc = api.form_desc(3, 6, q, "stiffness", prec, has_coeff=True)
+        asm = api.Assembly(mv, [desc])
+        k = steps if prec in ("fp16", "bf16") else max(3, steps // 4)
+        w = warmup if prec in ("fp16", "bf16") else max(1, warmup // 2)
+        ms = time_steps(asm.numeric, k, w)
+        ms_cell = time_steps(lambda: api.fe_cell_kernels(desc, asm.form_bufs[0], mv, asm.workspace),
+                             k, w)
+        (v,) = asm.numeric()
+        torch.cuda.synchronize()
+        if any(st != 0 for st in asm.status()):
+            raise RuntimeError(f"device status after the weighted-stiffness step ({prec})")
+        nnz = asm.nnz
+        vals[prec] = v[:nnz].clone()
+        peak = PEAK_MFMA_TFLOPS[prec]
+        t_cell = ms_cell / 1e3
+        modes[prec] = {
+            "ms_per_step": ms, "value": m.n_cells / (ms / 1e3), "unit": "cells/s",
+            "dtype": {"fp16": "f16 x f16 -> f32", "bf16": "bf16 x bf16 -> f32", "fp32": "f32",
+                      "fp64": "f64"}[prec],
+            "kernels": {"cell_kernel": {"ms": ms_cell}, "row_gather": {"ms": ms - ms_cell}},
+            "roofline": {"bound": "mfma", "achieved": flops / t_cell / 1e12, "peak": peak,
+                         "unit": "TFLOP/s", "frac": flops / t_cell / 1e12 / peak, "traffic": None,
+                         "kernel": "cell_kernel (a2-a5 of every cell)",
+                         "step_frac": flops / (ms / 1e3) / 1e12 / peak},
+        }
+        del asm
+        torch.cuda.empty_cache()
+    ref = vals["fp64"]
+    nref = float(torch.linalg.vector_norm(ref))
+    for prec in ("fp32", "bf16", "fp16"):
+        err = float(torch.linalg.vector_norm(vals[prec].double() - ref)) / nref
+        modes[prec]["rel_err_vs_fp64"] = err
+        modes[prec]["speedup_vs_fp64"] = modes["fp64"]["ms_per_step"] / modes[prec]["ms_per_step"]
+    del vals, ref
+    torch.cuda.empty_cache()
+    out["nnz"] = nnz
+    out["modes"] = modes
+    f16 = modes["fp16"]
+    out.update({"metric": "cells/s (weighted P6 stiffness, kernels + CSR assembly)",
+                "value": f16["value"], "unit": "cells/s", "dtype": f16["dtype"],
+                "ms_per_step": f16["ms_per_step"], "roofline": f16["roofline"],
+                "rel_err_vs_fp64": f16["rel_err_vs_fp64"],
+                "speedup_vs_fp64": f16["speedup_vs_fp64"]})
+    if not args.no_cpu_baseline:
+        import oracle
+        n = min(args.c3_cpu_cells, m.n_cells)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+        tab = oracle.tabulation(3, 6, q)
+        rp, ci = oracle.csr_pattern(m.dofmap[:n], m.n_dofs)      # symbolic: not timed
+        t0 = time.perf_counter()
+        A = oracle.local_matrices("stiffness", m.cell_coords[:n], 6, q, m.dofmap[:n], m.coeff,
+                                  nthreads=threads, tab=tab)
+        oracle.assemble(m.dofmap[:n], A, m.n_dofs, rp, ci)
+        dt = time.perf_counter() - t0
+        del A
+        n1 = min(256, n)
+        rp1, ci1 = oracle.csr_pattern(m.dofmap[:n1], m.n_dofs)
+        t0 = time.perf_counter()
+        A = oracle.local_matrices("stiffness", m.cell_coords[:n1], 6, q, m.dofmap[:n1], m.coeff,
+                                  nthreads=1, tab=tab)
+        oracle.assemble(m.dofmap[:n1], A, m.n_dofs, rp1, ci1)
+        dt1 = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": n / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} of {m.n_cells} cells: local matrices (coefficient at the points, "
+                      f"FP64) + CSR assembly, {threads} OpenMP threads, one pass of {dt:.1f} s",
+            "single_thread": {"value": n1 / dt1, "unit": "cells/s", "cores": 1,
+                              "sample": f"first {n1} cells, one pass of {dt1:.1f} s"}}
+    return out
+
+
 def sources_digest():
     """SHA-256 over the sources of the fused pass (traffic is reported only
     for the code it was measured on)."""
@@ -430,35 +543,10 @@ def main():
         del src, dst
 
     prec = args.precision
-    asm = assembly(prec)
-    ms = time_steps(asm.numeric, args.steps, args.warmup)
-    st = asm.status()
-    if any(s != 0 for s in st):
-        raise RuntimeError(f"device status {st}")
-
-    # the two halves of the step, and the unfused path for comparison
     n_phi = mesh.n_phi
-    nnz = asm.nnz
-    ms_geo = time_steps(lambda: asm.numeric(part="geometry"), args.steps, args.warmup)
-    ms_fused = time_steps(lambda: asm.numeric(part="fused"), args.steps, args.warmup)
-    ms_gather_path = time_steps(lambda: asm.numeric(gather=True), max(3, args.steps // 4),
-                                max(1, args.warmup // 5))
-
-    result = {}
-    if not args.no_fp64:
-        asm64 = assembly("fp64")
-        ms64 = time_steps(asm64.numeric, max(3, args.steps // 4), max(1, args.warmup // 5))
-        v64 = asm64.numeric()
-        vm = asm.numeric()
-        torch.cuda.synchronize()
-        errs = {}
-        for f, a, b in zip(forms, vm, v64):
-            a, b = a[:asm.nnz].double(), b[:asm.nnz]
-            errs[f] = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
-        result["fp64_path"] = {"value": mesh.n_cells / (ms64 / 1e3), "ms_per_step": ms64}
-        result["speedup_vs_fp64"] = ms64 / ms
-        result["rel_err_vs_fp64"] = errs
-        del asm64, v64
+    n_q = 125
+    kq = {"mass": n_q, "stiffness": 3 * n_q}
+    flops = sum(2 * n_phi ** 2 * kq[f] * mesh.n_cells for f in forms)
 
     # Roofline of the dominant kernel: the fused pass (both forms).  Its
     # algorithmic work per launch: matrix-core flops 2 n_phi^2 K per cell and
@@ -466,34 +554,93 @@ def main():
     # cell for stiffness, n_q n_phi for mass; bytes: each cell's coordinates
     # (96) and dof map (4 n_phi) read once, each form's CSR values (4 nnz)
     # written once.
-    n_q = 125
-    kq = {"mass": n_q, "stiffness": 3 * n_q}
-    flops = sum(2 * n_phi ** 2 * kq[f] * mesh.n_cells for f in forms)
     valu = sum(2 * (9 if f == "stiffness" else 1) * n_q * n_phi * mesh.n_cells for f in forms)
-    nbytes = (96 + 4 * n_phi) * mesh.n_cells + len(forms) * 4 * nnz
+
+    def c2_roofline(pr, t, nnz):
+        nbytes = (96 + 4 * n_phi) * mesh.n_cells + len(forms) * 4 * nnz
+        ideal = {"hbm": nbytes / (PEAK_HBM_GBS * 1e9),
+                 "mfma": flops / (PEAK_MFMA_TFLOPS[pr] * 1e12),
+                 "alu": valu / (PEAK_VALU_TFLOPS * 1e12)}
+        bound = max(ideal, key=ideal.get)
+        if bound == "hbm":
+            roof = {"bound": "hbm", "achieved": nbytes / t / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+        elif bound == "mfma":
+            roof = {"bound": "mfma", "achieved": flops / t / 1e12, "peak": PEAK_MFMA_TFLOPS[pr],
+                    "unit": "TFLOP/s"}
+        else:
+            roof = {"bound": "alu", "achieved": valu / t / 1e12, "peak": PEAK_VALU_TFLOPS,
+                    "unit": "TFLOP/s"}
+        roof["frac"] = roof["achieved"] / roof["peak"]
+        roof["kernel"] = "fused_pass"
+        roof["ideal_us"] = {k: v * 1e6 for k, v in ideal.items()}
+        roof["alg_bytes"] = nbytes
+        return roof
+
+    # The FP64 path and the other mixed modes first (their values are kept
+    # for the error of each mode against FP64), then the reported mode.
+    result, v64, other = {}, None, {}
+    if not args.no_fp64:
+        asm64 = assembly("fp64")
+        ms64 = time_steps(asm64.numeric, max(3, args.steps // 4), max(1, args.warmup // 5))
+        v64 = [v[:asm64.nnz].clone() for v in asm64.numeric()]
+        torch.cuda.synchronize()
+        result["fp64_path"] = {"value": mesh.n_cells / (ms64 / 1e3), "ms_per_step": ms64}
+        del asm64
+        torch.cuda.empty_cache()
+
+    def rel_errs(vals, nnz):
+        return {f: float(torch.linalg.vector_norm(a[:nnz].double() - b) / torch.linalg.vector_norm(b))
+                for f, a, b in zip(forms, vals, v64)}
+
+    for other_prec in ("split", "bf16"):
+        if other_prec == prec:
+            continue
+        a2 = assembly(other_prec)
+        ms2 = time_steps(a2.numeric, args.steps, args.warmup)
+        ms2_fused = time_steps(lambda: a2.numeric(part="fused"), args.steps, args.warmup)
+        if any(st != 0 for st in a2.status()):
+            raise RuntimeError(f"device status ({other_prec})")
+        roof2 = c2_roofline(other_prec, ms2_fused / 1e3, a2.nnz)
+        roof2["traffic"] = None
+        other[other_prec] = {
+            "ms_per_step": ms2, "value": mesh.n_cells / (ms2 / 1e3), "unit": "cells/s",
+            "dtype": {"bf16": "bf16 x bf16 -> f32", "split": "2xf16 x 2xf16 -> f32"}[other_prec],
+            "fused_pass_ms": ms2_fused, "roofline": roof2,
+        }
+        if v64 is not None:
+            other[other_prec]["rel_err_vs_fp64"] = rel_errs(a2.numeric(), a2.nnz)
+            other[other_prec]["speedup_vs_fp64"] = result["fp64_path"]["ms_per_step"] / ms2
+        del a2
+        torch.cuda.empty_cache()
+
+    asm = assembly(prec)
+    ms = time_steps(asm.numeric, args.steps, args.warmup)
+    st = asm.status()
+    if any(s != 0 for s in st):
+        raise RuntimeError(f"device status {st}")
+
+    # the two halves of the step, and the unfused path for comparison
+    nnz = asm.nnz
+    ms_geo = time_steps(lambda: asm.numeric(part="geometry"), args.steps, args.warmup)
+    ms_fused = time_steps(lambda: asm.numeric(part="fused"), args.steps, args.warmup)
+    ms_gather_path = time_steps(lambda: asm.numeric(gather=True), max(3, args.steps // 4),
+                                max(1, args.warmup // 5))
+    if v64 is not None:
+        result["speedup_vs_fp64"] = result["fp64_path"]["ms_per_step"] / ms
+        result["rel_err_vs_fp64"] = rel_errs(asm.numeric(), nnz)
+    if other:
+        result["other_modes"] = other
+    del v64
+
     t = ms_fused / 1e3
+    roof = c2_roofline(prec, t, nnz)
+    nbytes = roof["alg_bytes"]
     kern = {"fused_pass": {"ms": ms_fused, "alg_flops": flops, "alg_valu_flops": valu,
                            "alg_bytes": nbytes, "tflops": flops / t / 1e12,
                            "gbs": nbytes / t / 1e9},
             "geometry_pass": {"ms": ms_geo},
             "unfused_step": {"ms": ms_gather_path}}
-    ideal = {"hbm": nbytes / (PEAK_HBM_GBS * 1e9),
-             "mfma": flops / (PEAK_MFMA_TFLOPS[prec] * 1e12),
-             "alu": valu / (PEAK_VALU_TFLOPS * 1e12)}
-    bound = max(ideal, key=ideal.get)
-    traffic = measured_traffic() if prec == "fp16" else None
-    if bound == "hbm":
-        roof = {"bound": "hbm", "achieved": nbytes / t / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
-    elif bound == "mfma":
-        roof = {"bound": "mfma", "achieved": flops / t / 1e12, "peak": PEAK_MFMA_TFLOPS[prec],
-                "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "alu", "achieved": valu / t / 1e12, "peak": PEAK_VALU_TFLOPS,
-                "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = traffic
-    roof["kernel"] = "fused_pass"
-    roof["ideal_us"] = {k: v * 1e6 for k, v in ideal.items()}
+    roof["traffic"] = measured_traffic() if prec == "fp16" else None
 
     line = {
         "metric": "cells/sec (kernel+CSR assembly) mixed FP16/FP32 vs FP64 at stated rel. error",
@@ -528,6 +675,9 @@ def main():
     if not args.no_hex:
         torch.cuda.empty_cache()
         line["hex_mass"] = hex_section(args, max(3, args.steps // 4), max(1, args.warmup // 5))
+    if not args.no_c3:
+        torch.cuda.empty_cache()
+        line["weighted_p6"] = c3_section(args, max(3, args.steps // 4), max(1, args.warmup // 5))
     print(json.dumps(line), flush=True)
 
 

@@ -2,9 +2,10 @@
  * fe.h -- C ABI of the MI355X (gfx950) finite element cell-kernel and
  * assembly library.
  *
- * The library computes, for every simplex cell K of an affine mesh, the
- * local element matrix of the mass or Poisson (stiffness) form with an
- * optional coefficient z in the same Lagrange space,
+ * The library computes, for every cell K of a mesh of affine simplices
+ * (triangles, tetrahedra) or trilinear hexahedra, the local element matrix
+ * of the mass or Poisson (stiffness) form with an optional coefficient z in
+ * the same Lagrange space,
  *
  *     A_K = sum_{s,t} B_s C_st B_t^T,   C_st = diag_q(w_q z(X_q) G_st)
  *
@@ -31,8 +32,10 @@
  *     deterministic for a given GPU, input and build: the numeric assembly
  *     sums every CSR entry in a fixed order.
  *
- * Cell geometry is affine: J, det J and G are constant on a cell, computed
- * once per cell in FP64 (the geometry precision u_g of List 1 is double).
+ * Simplex geometry is affine: J, det J and G are constant on a cell,
+ * computed once per cell (in FP64 by default: the geometry precision u_g of
+ * List 1 is double).  Hexahedra are mapped trilinearly, so J, det J and G
+ * vary over the cell and are evaluated in FP64 at every quadrature point.
  */
 #ifndef FE_MI355X_FE_H
 #define FE_MI355X_FE_H
@@ -114,7 +117,7 @@ enum {
 };
 
 typedef struct fe_form_desc {
-  int32_t cell;           /* FE_TRIANGLE or FE_TETRAHEDRON                     */
+  int32_t cell;           /* FE_TRIANGLE, FE_TETRAHEDRON or FE_HEXAHEDRON      */
   int32_t degree;         /* Lagrange degree p, 1 <= p <= 8                     */
   int32_t quad_degree;    /* q >= 0: floor(q/2)+1 collapsed Gauss-Jacobi points
                              per direction, at most 9 (q <= 17)                 */
@@ -138,6 +141,12 @@ typedef struct fe_csr {
   int64_t max_row_len; /* written by FE_SYMBOLIC_COUNT: longest row           */
   int64_t schedule; /* written by FE_SYMBOLIC_FILL: owner tasks of the fused
                        numeric schedule, 0 when none was built              */
+  int32_t schedule_span; /* written by FE_SYMBOLIC_FILL: CSR entries per task
+                            of that schedule (1024, or 2048 when every form
+                            of the FILL call was an FP16 hexahedral form)    */
+  int32_t schedule_elt;  /* written by FE_SYMBOLIC_FILL: bytes per value of
+                            the forms of the FILL call (8 FP64, else 4); the
+                            schedule's record layout depends on it           */
   int64_t *row_ptr; /* device [n_rows+1]                                       */
   int32_t *col_idx; /* device [nnz], ascending and unique per row              */
   void *values;     /* device [nnz], double for FE_FP64 else float             */
@@ -273,9 +282,13 @@ fe_status fe_dg_pattern(int32_t n_blocks, const int64_t *n_cells, const int32_t 
  *       (all FE_FP64 or none)
  *   mats[n_forms] : output matrices; row_ptr/col_idx may be shared
  *   plan / plan_bytes : device scratch owned by the caller, sized by a query
- *       with plan == NULL; holds the dof-to-cell adjacency and the
- *       position of every local entry inside its CSR row.  Its size depends
- *       only on the mesh (n_cells, n_phi, n_dofs).
+ *       with plan == NULL; holds the dof-to-cell adjacency, the position of
+ *       every local entry inside its CSR row and the fused schedule.  Its
+ *       size depends on the mesh (n_cells, n_phi, n_dofs) and on the value
+ *       type of the forms (FP64 or not: the schedule's record layout).  The
+ *       schedule built by FE_SYMBOLIC_FILL serves only forms of the value
+ *       type and task span of that call (mats[0].schedule_elt and
+ *       schedule_span); FE_NUMERIC takes the gather for other forms.
  *   workspace / ws_bytes : device scratch for the numeric phase (local
  *       matrices of all forms for the gather, per-cell factors of H for the
  *       fused path), sized by a query with workspace == NULL.
@@ -310,7 +323,10 @@ fe_status fe_dg_pattern(int32_t n_blocks, const int64_t *n_cells, const int32_t 
  *       assemblies or time the halves: GEOMETRY writes the per-cell factor
  *       records (for hexahedra also |det J| at every quadrature point) into
  *       the workspace, FUSED runs the fused kernels on the records the last
- *       GEOMETRY (or FE_NUMERIC) call left in that workspace.  FE_EUNSUPPORTED when the fused path does not apply.
+ *       GEOMETRY (or FE_NUMERIC) call left in that workspace.
+ *       FE_EUNSUPPORTED when the fused path does not apply to every form;
+ *       FE_EINVAL when the schedule was built for forms of another value
+ *       type or task span (checked on the host before any launch).
  * Errors: FE_EINVAL (NULL pointers, dof entries out of range are reported
  * through the status word of the plan), FE_ESIZE, FE_EUNSUPPORTED, FE_EHIP.
  * ------------------------------------------------------------------------ */

@@ -76,7 +76,8 @@ class fe_mesh_view(ctypes.Structure):
 
 class fe_csr(ctypes.Structure):
     _fields_ = [("n_rows", ctypes.c_int64), ("nnz", ctypes.c_int64), ("max_row_len", ctypes.c_int64),
-                ("schedule", ctypes.c_int64),
+                ("schedule", ctypes.c_int64), ("schedule_span", ctypes.c_int32),
+                ("schedule_elt", ctypes.c_int32),
                 ("row_ptr", ctypes.c_void_p),
                 ("col_idx", ctypes.c_void_p), ("values", ctypes.c_void_p)]
 

@@ -253,16 +253,9 @@ static fe_status launch_action_one(const ActArgs &k, hipStream_t s) {
   auto kern = action_kernel<P, KS, STIFF, COEFF, GZ, STAGE, NW>;
   const size_t smem = STAGE ? 2 * k.chunk * sizeof(T) : 0;
   if (smem > 160 * 1024) return FE_EUNSUPPORTED;
-  if (smem > 65536 && hipFuncSetAttribute((const void *)kern,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize,
-                                          (int)smem) != hipSuccess)
-    return FE_EHIP;
-  int dev = 0, ncu = 256, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, NW * 64, smem) !=
-          hipSuccess)
-    return FE_EHIP;
+  LaunchInfo li;
+  if (launch_info((const void *)kern, NW * 64, smem, &li) != FE_OK) return FE_EHIP;
+  const int ncu = li.ncu, per_cu = li.per_cu;
   if (per_cu < 1) return FE_EUNSUPPORTED;
   const int64_t groups = ((k.n_cells + 15) / 16 + NW - 1) / NW;
   const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(groups, (int64_t)ncu * per_cu));

@@ -756,15 +756,9 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
 template <class P, int MT, int JC, int NDT, bool COEFF, int STAGE, int NW>
 static fe_status launch_one(const KArgs &k, int64_t n_cells, size_t smem, int occ, hipStream_t s) {
   auto kern = cell_kernel<P, MT, JC, NDT, COEFF, STAGE, NW>;
-  if (smem > 65536) {
-    if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)smem) != hipSuccess)
-      return FE_EHIP;
-  }
-  int dev = 0, ncu = 256;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return FE_EHIP;
+  LaunchInfo li;
+  if (launch_info((const void *)kern, NW * 64, smem, &li) != FE_OK) return FE_EHIP;
+  const int ncu = li.ncu;
   // work items as in the kernel: (batch, pass) without a coefficient
   const int64_t nbatch = (n_cells + 15) / 16;
   const int64_t nitems = COEFF ? nbatch : nbatch * ((k.n_phi + NW * JC - 1) / (NW * JC));

@@ -37,6 +37,8 @@ struct PlanHeader {
   int64_t nnz, max_deg, max_len;
   int32_t ntasks;  // fused schedule: number of owner tasks (0 = not built)
   int32_t ntiles;
+  int32_t span;    // CSR entries per task of the schedule
+  int32_t elt;     // bytes per value of the forms it was built for (record layout)
 };
 constexpr int32_t PLAN_MAGIC = 0x46455043;  // "FEPC"
 
@@ -304,15 +306,29 @@ __global__ void k_scan_tiles(int64_t *x, int64_t n, int64_t *tile_sum) {
   if (threadIdx.x == 255) tile_sum[blockIdx.x] = part[255];
 }
 
-__global__ void k_scan_totals(int64_t *tile_sum, int64_t nt) {
-  // single block: exclusive scan of tile totals, serial per chunk
-  if (threadIdx.x == 0) {
-    int64_t run = 0;
-    for (int64_t t = 0; t < nt; ++t) {
-      int64_t v = tile_sum[t];
-      tile_sum[t] = run;
-      run += v;
-    }
+// Exclusive scan of the tile totals in one workgroup of SCAN_TOT threads:
+// each thread sums a contiguous chunk, the chunk sums are scanned in LDS,
+// then every thread writes its chunk's exclusive prefixes.
+constexpr int SCAN_TOT = 1024;
+__global__ __launch_bounds__(SCAN_TOT) void k_scan_totals(int64_t *tile_sum, int64_t nt) {
+  __shared__ int64_t part[SCAN_TOT];
+  const int64_t chunk = (nt + SCAN_TOT - 1) / SCAN_TOT;
+  const int64_t t0 = (int64_t)threadIdx.x * chunk, t1 = min(nt, t0 + chunk);
+  int64_t run = 0;
+  for (int64_t t = t0; t < t1; ++t) run += tile_sum[t];
+  part[threadIdx.x] = run;
+  __syncthreads();
+  for (int off = 1; off < SCAN_TOT; off <<= 1) {
+    const int64_t add = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t v = tile_sum[t];
+    tile_sum[t] = run;
+    run += v;
   }
 }
 
@@ -596,7 +612,7 @@ fe_status scan_inclusive(int64_t *x, int64_t n, int64_t *scratch, size_t tiles, 
   const int64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
   if ((size_t)nt > tiles) return FE_EINVAL;
   hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(256), 0, s, x, n, scratch);
-  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(64), 0, s, scratch, nt);
+  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(SCAN_TOT), 0, s, scratch, nt);
   hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nt), dim3(256), 0, s, x, n, scratch);
   return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
 }
@@ -743,12 +759,17 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
     }
     if (hipGetLastError() != hipSuccess) return FE_EHIP;
     if (!sync_ok(s)) return FE_EHIP;
-    // fused schedule (host): needs row_ptr and the sorted adjacency
+    // fused schedule (host): needs row_ptr and the sorted adjacency; built
+    // only when one of the forms can take the fused path
     h.ntasks = 0;
     h.ntiles = 0;
     // task span: longer for hexahedral forms (all forms share the cell type)
     const int span = assembly_span(L, n_forms);
-    if (h.max_len <= span && n_cells > 0) {
+    h.span = span;
+    h.elt = (int32_t)elt;
+    bool any_fused = false;
+    for (int f = 0; f < n_forms; ++f) any_fused = any_fused || fused_eligible(L[f]);
+    if (any_fused && h.max_len <= span && n_cells > 0) {
       std::vector<int64_t> rp(n_dofs + 1), apv(n_dofs + 1), adjv((size_t)n_cells * n_phi);
       if (hipMemcpy(rp.data(), row_ptr, sizeof(int64_t) * rp.size(), hipMemcpyDeviceToHost) != hipSuccess ||
           hipMemcpy(apv.data(), adj_ptr, sizeof(int64_t) * apv.size(), hipMemcpyDeviceToHost) != hipSuccess ||
@@ -773,7 +794,11 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
       }
     }
     if (hipMemcpy(hdr_d, &h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess) return FE_EHIP;
-    for (int f = 0; f < n_forms; ++f) mats[f].schedule = h.ntasks;
+    for (int f = 0; f < n_forms; ++f) {
+      mats[f].schedule = h.ntasks;
+      mats[f].schedule_span = h.ntasks > 0 ? span : 0;
+      mats[f].schedule_elt = h.ntasks > 0 ? (int32_t)elt : 0;
+    }
     return FE_OK;
   }
 
@@ -783,13 +808,20 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
   for (int f = 0; f < n_forms; ++f)
     if (!form_bufs || !form_bufs[f] || !mats[f].values) return FE_EINVAL;
   if (n_cells == 0) return FE_OK;  // values of an empty pattern: nothing to write
+  // The schedule's task span and record layout were fixed by the forms of the
+  // FILL call: a schedule built for other forms (another value type, or a
+  // span these forms' row buffers cannot hold) is not used.
+  const bool sched_ok = mats[0].schedule > 0 && mats[0].schedule_span == assembly_span(L, n_forms) &&
+                        mats[0].schedule_elt == (int32_t)elt;
+  if ((phase == FE_NUMERIC_GEOMETRY || phase == FE_NUMERIC_FUSED) && mats[0].schedule > 0 && !sched_ok)
+    return FE_EINVAL;
   // Forms whose tables fit on chip take the fused row-ownership path when the
   // FILL phase built its schedule; the others (coefficient forms, tables too
   // large) take the cell kernels and the row gather.
   bool on_fused[4] = {false, false, false, false};
   int n_fused = 0;
   for (int f = 0; f < n_forms; ++f) {
-    on_fused[f] = phase != FE_NUMERIC_GATHER && mats[0].schedule > 0 && fused_eligible(L[f]);
+    on_fused[f] = phase != FE_NUMERIC_GATHER && sched_ok && fused_eligible(L[f]);
     n_fused += on_fused[f] ? 1 : 0;
   }
   if ((phase == FE_NUMERIC_GEOMETRY || phase == FE_NUMERIC_FUSED) && n_fused < n_forms)

@@ -5,6 +5,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "fe_internal.h"
@@ -274,6 +277,35 @@ bool fused_eligible(const FormLayout &L) {
   // gather are faster
   const FormLayout *one[1] = {&L};
   return !L.has_coeff && fused_lds(one, 1, 8, true) <= FUSED_LDS_BUDGET;
+}
+
+fe_status launch_info(const void *kern, int threads, size_t smem, LaunchInfo *out) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void *, int, int, size_t>, LaunchInfo> info;
+  static std::map<std::pair<const void *, int>, size_t> lds_limit;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return FE_EHIP;
+  std::lock_guard<std::mutex> lock(mu);
+  if (smem > 65536) {
+    size_t &lim = lds_limit[{kern, dev}];
+    if (smem > lim) {
+      if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) !=
+          hipSuccess)
+        return FE_EHIP;
+      lim = smem;
+    }
+  }
+  const auto key = std::make_tuple(kern, dev, threads, smem);
+  auto it = info.find(key);
+  if (it == info.end()) {
+    LaunchInfo li;
+    if (hipDeviceGetAttribute(&li.ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&li.per_cu, kern, threads, smem) != hipSuccess)
+      return FE_EHIP;
+    it = info.emplace(key, li).first;
+  }
+  *out = it->second;
+  return FE_OK;
 }
 
 fe_status launch_cell(const CellLaunch &a) {

@@ -711,16 +711,9 @@ template <class P, int MT, int NDT0, int NDT1, int NF, bool SA, int NW, int TT, 
           bool PZ = false>
 static fe_status launch_fused_one(const FusedArgs &k, size_t smem, hipStream_t s) {
   auto kern = fused_kernel<P, MT, NDT0, NDT1, NF, SA, NW, TT, PR, PZ>;
-  if (smem > 65536 && hipFuncSetAttribute((const void *)kern,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize,
-                                          (int)smem) != hipSuccess)
-    return FE_EHIP;
-  int dev = 0, ncu = 256, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, NW * 64, smem) !=
-          hipSuccess)
-    return FE_EHIP;
+  LaunchInfo li;
+  if (launch_info((const void *)kern, NW * 64, smem, &li) != FE_OK) return FE_EHIP;
+  const int ncu = li.ncu, per_cu = li.per_cu;
   if (per_cu < 1) return FE_EUNSUPPORTED;
   const int64_t need = ((int64_t)k.ntasks + NW - 1) / NW;
   const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)ncu * per_cu));

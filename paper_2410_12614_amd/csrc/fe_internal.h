@@ -246,6 +246,16 @@ struct ActionLaunch {
 fe_status launch_action_fp32(const ActionLaunch &a);
 fe_status launch_action_fp64(const ActionLaunch &a);
 
+// Launch facts of one kernel on the current device, queried from the runtime
+// once per (kernel, device, block size, LDS bytes) and cached: the compute
+// unit count and the workgroups per compute unit.  The kernel's dynamic LDS
+// limit is raised (once per kernel and device) to the largest size asked.
+struct LaunchInfo {
+  int ncu;     // compute units
+  int per_cu;  // resident workgroups per compute unit (0: does not fit)
+};
+fe_status launch_info(const void *kern, int threads, size_t smem, LaunchInfo *out);
+
 // Matrix-core tile choice: MT = ceil(n_phi / 16) row tiles of B^T and JC
 // columns j per wave per pass (4 waves per workgroup).
 void tile_choice(int n_phi, int regmul, int *mt, int *jc);

@@ -187,3 +187,26 @@ def test_product_path_has_no_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(L.FeLibraryError):
         api.fe_tabulate(3, 1, 0)
+
+
+@pytest.mark.parametrize("span,elt", [(1024, 8), (2048, 4), (512, 4)])
+def test_schedule_of_other_forms_is_rejected(lib, span, elt):
+    """A fused schedule records the task span and value type of the forms it
+    was built for; the fused half of the numeric phase refuses forms of
+    another kind on the host, before anything is launched (the pointers
+    below are never dereferenced)."""
+    descs = [api.form_desc(3, 4, 8, f, "fp16") for f in ("mass", "stiffness")]
+    darr = (L.fe_form_desc * 2)(*descs)
+    fake = ctypes.c_void_p(4096)
+    bufs = (ctypes.c_void_p * 2)(fake, fake)
+    mv = L.fe_mesh_view(n_cells=82944, cell_coords=fake, dofmap=fake, n_dofs=912673, coeff=None)
+    mats = (L.fe_csr * 2)()
+    for m in mats:
+        m.n_rows, m.nnz, m.schedule = 912673, 67338433, 1000
+        m.schedule_span, m.schedule_elt = span, elt
+        m.row_ptr = m.col_idx = m.values = 4096
+    big = ctypes.c_size_t(1 << 62)
+    for phase in (L.FE_NUMERIC_FUSED, L.FE_NUMERIC_GEOMETRY):
+        st = lib.fe_assemble_csr(darr, bufs, 2, ctypes.byref(mv), phase, mats, fake,
+                                 ctypes.byref(big), fake, ctypes.byref(big), None)
+        assert st == L.FE_EINVAL, (phase, st)
