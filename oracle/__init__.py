@@ -22,10 +22,14 @@ Parts and what pins them (tests under ``tests/test_oracle_*.py``):
 * ``oracle_fe.c`` assembly (Section 3.3) -- pinned by brute-force dense
   assembly on tiny meshes, nnz counts, and exact polynomial integrals
   u^T M v, u^T K v.
-* ``hexahedra.py`` (boxed cells, per-point trilinear geometry): mass matrices
-  -- pinned by exact monomial integrals of the tensor rule, the Kronecker
-  property, the unit cube = tensor product of exact rational 1D mass
-  matrices, the volume of a jittered mesh and an exact polynomial integral.
+* ``hexahedra.py`` (rule and Q_p basis) with ``oracle_fe.c``'s
+  ``oracle_hex_local_matrices`` (boxed cells, geometry tensor per
+  quadrature point of the trilinear map): mass and stiffness matrices --
+  pinned by exact monomial integrals of the tensor rule, the Kronecker
+  property, the unit cube = Kronecker sums and products of exact rational 1D
+  mass and stiffness matrices, the volume of a jittered mesh, zero row sums
+  of the stiffness matrix, x^T K x = |Omega| for the coordinate function
+  (which lies in Q_1 on a trilinear cell), and exact polynomial integrals.
 * ``oracle_fe.c`` actions (Algorithm 2) and the coefficient adjoint -- pinned
   by the assembled matrix times the vector (Algorithm 1 route), mass and
   stiffness actions on constants (|Omega|, zero), the exact integral of
@@ -90,6 +94,9 @@ def _load():
         lib.oracle_assemble_vector.argtypes = [ctypes.c_int64, ctypes.c_int, P, P,
                                                ctypes.c_int64, P]
         lib.oracle_assemble_vector.restype = ctypes.c_int
+        lib.oracle_hex_local_matrices.argtypes = [ctypes.c_int, ctypes.c_int64, P, ctypes.c_int,
+                                                  ctypes.c_int, P, P, P, P, P, ctypes.c_int]
+        lib.oracle_hex_local_matrices.restype = ctypes.c_int
         _lib = lib
     return _lib
 

@@ -1,4 +1,4 @@
-"""Oracle for hexahedral (boxed) cells: mass matrices with per-point geometry (FP64).
+"""Oracle for hexahedral (boxed) cells: mass and Poisson matrices with per-point geometry (FP64).
 
 TEST INFRASTRUCTURE ONLY (see the package header).
 
@@ -8,10 +8,12 @@ index i + (p+1)(j + (p+1)k) (x fastest).  Quadrature: the tensor product of
 the m-point Gauss-Legendre rule on [0, 1], m = floor(q/2) + 1, x fastest.
 Geometry: the trilinear map x(X) = sum_v x_v phi_v(X) over the 8 vertices
 (vertex v at the reference corner (v & 1, (v >> 1) & 1, (v >> 2) & 1)); on a
-boxed cell J and det J vary in space (Section 4.2, the geometry tensor
-G(X) = |det J(X)| of the mass form).  The mass matrix is
-A = B^T diag_q(w_q |det J(X_q)|) B, B[q][k] = phi_k(X_q) (Algorithm 1 with
-n_d = 1 and a per-point C).
+boxed cell J and det J vary in space (Section 4.2), so the geometry tensor
+G(X) = |det J(X)| (mass) or |det J| J^{-1} J^{-T} (Poisson) is taken at every
+quadrature point.  The matrices are Algorithm 1 with a per-point C,
+A = sum_s sum_t B_s^T diag_q(w_q G_st(X_q)) B_t; that arithmetic (LU
+geometry per point, the triple product) is in the oracle's C part, this
+module supplies the rule and the basis tables.
 """
 from __future__ import annotations
 
@@ -60,25 +62,32 @@ def tabulate(p: int, X: np.ndarray):
     return vals, np.stack([gx, gy, gz])
 
 
-def jacobian(x8: np.ndarray, X: np.ndarray) -> np.ndarray:
-    """J(X) [n][3][3] of the trilinear map of vertices x8 [8][3]."""
-    J = np.zeros((len(X), 3, 3))
-    for v in range(8):
-        bits = [(v >> e) & 1 for e in range(3)]
-        f = np.stack([X[:, e] if bits[e] else 1.0 - X[:, e] for e in range(3)], axis=1)
-        s = np.array([1.0 if b else -1.0 for b in bits])
-        grad = np.stack([s[0] * f[:, 1] * f[:, 2], f[:, 0] * s[1] * f[:, 2],
-                         f[:, 0] * f[:, 1] * s[2]], axis=1)              # d phi_v / d X_j
-        J += x8[v][None, :, None] * grad[:, None, :]
-    return J
-
-
-def mass_matrices(cell_coords: np.ndarray, p: int, quad_degree: int) -> np.ndarray:
-    """A_K [n_cells][n_phi][n_phi] of the mass form on trilinear hexahedra."""
+def local_matrices(form: str, cell_coords: np.ndarray, p: int, quad_degree: int,
+                   nthreads: int = 0) -> np.ndarray:
+    """A_K [n_cells][n_phi][n_phi] of the mass or Poisson form on trilinear
+    hexahedra: the rule and basis tabulated here, geometry and Algorithm 1
+    (with G evaluated at every quadrature point) in the oracle's C part."""
+    from . import FORMS, OracleError, _load, _ptr
     pts, w = tensor_rule(quad_degree)
-    B, _ = tabulate(p, pts)
-    out = np.empty((len(cell_coords), B.shape[1], B.shape[1]))
-    for K, x8 in enumerate(np.asarray(cell_coords, dtype=np.float64)):
-        c = w * np.abs(np.linalg.det(jacobian(x8, pts)))
-        out[K] = B.T @ (c[:, None] * B)
-    return out
+    B, dB = tabulate(p, pts)
+    cc = np.ascontiguousarray(cell_coords, dtype=np.float64).reshape(-1, 8, 3)
+    pts = np.ascontiguousarray(pts); w = np.ascontiguousarray(w)
+    B = np.ascontiguousarray(B); dB = np.ascontiguousarray(dB)
+    n_q, n_phi = B.shape
+    A = np.empty((len(cc), n_phi, n_phi))
+    st = _load().oracle_hex_local_matrices(FORMS[form], len(cc), _ptr(cc), n_phi, n_q, _ptr(pts),
+                                           _ptr(w), _ptr(B), _ptr(dB), _ptr(A), int(nthreads))
+    if st != 0:
+        raise OracleError(f"oracle_hex_local_matrices failed (status {st})")
+    return A
+
+
+def mass_matrices(cell_coords: np.ndarray, p: int, quad_degree: int, nthreads: int = 0) -> np.ndarray:
+    """A_K of the mass form on trilinear hexahedra."""
+    return local_matrices("mass", cell_coords, p, quad_degree, nthreads)
+
+
+def stiffness_matrices(cell_coords: np.ndarray, p: int, quad_degree: int,
+                       nthreads: int = 0) -> np.ndarray:
+    """A_K of the Poisson form on trilinear hexahedra."""
+    return local_matrices("stiffness", cell_coords, p, quad_degree, nthreads)

@@ -37,6 +37,10 @@
  *   - Vector assembly v^g = L b (Section 3.3): local vectors summed into the
  *     global vector in the order cell K ascending, then i.
  *
+ *   - Hexahedra (boxed cells): the same Algorithm 1 with the geometry tensor
+ *     evaluated at every quadrature point of the trilinear map
+ *     (oracle_hex_local_matrices).
+ *
  * Tabulations (weights, basis values and gradients at the quadrature points)
  * are inputs; the oracle's own Python side computes them.
  */
@@ -242,6 +246,143 @@ int oracle_local_matrices(int d, int form, int64_t n_cells, const double *coords
       }
     }
     free(BT); free(HT); free(z);
+  }
+  return status;
+}
+
+/* Hexahedra (boxed cells, Section 5.1 reference cube [0,1]^3): the
+ * trilinear map x(X) = sum_v x_v phi_v(X) over the 8 vertices, vertex v at
+ * the reference corner (v & 1, (v >> 1) & 1, (v >> 2) & 1), so
+ *     J_ij(X) = sum_v x_v,i d_j phi_v(X),
+ * which varies over the cell (Section 4.2: the geometry tensor is evaluated
+ * at every quadrature point).  X is [3], x8 is [8][3]. */
+static void hex_jacobian(const double *x8, const double *X, double *J) {
+  for (int e = 0; e < 9; ++e) J[e] = 0.0;
+  for (int v = 0; v < 8; ++v) {
+    double f[3], df[3];
+    for (int e = 0; e < 3; ++e) {
+      int b = (v >> e) & 1;
+      f[e] = b ? X[e] : 1.0 - X[e];
+      df[e] = b ? 1.0 : -1.0;
+    }
+    double g[3] = {df[0] * f[1] * f[2], f[0] * df[1] * f[2], f[0] * f[1] * df[2]};
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) J[i * 3 + j] += x8[v * 3 + i] * g[j];
+  }
+}
+
+/* Geometry tensor of a hexahedron at one point: |det J| (mass) or
+ * |det J| J^{-1} J^{-T} (Poisson), det J by LU with partial pivoting and
+ * J^{-1} by LU solves, as for simplices. */
+static int hex_point_geometry(const double *x8, const double *X, int form, double *G) {
+  double J[9], LU[9], Jinv[9];
+  int piv[3];
+  hex_jacobian(x8, X, J);
+  memcpy(LU, J, sizeof J);
+  int sign = lu_factor(3, LU, piv);
+  if (sign == 0) return ORACLE_EDEGENERATE;
+  double det = (double)sign * LU[0] * LU[4] * LU[8];
+  if (det == 0.0 || !isfinite(det)) return ORACLE_EDEGENERATE;
+  if (form == FORM_MASS) {
+    G[0] = fabs(det);
+    return ORACLE_OK;
+  }
+  for (int c = 0; c < 3; ++c) {
+    double e[3] = {0, 0, 0}, col[3];
+    e[c] = 1.0;
+    lu_solve(3, LU, piv, e, col);
+    for (int r = 0; r < 3; ++r) Jinv[r * 3 + c] = col[r];
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += Jinv[i * 3 + k] * Jinv[j * 3 + k];
+      G[i * 3 + j] = fabs(det) * s;
+      if (!isfinite(G[i * 3 + j])) return ORACLE_EDEGENERATE;
+    }
+  return ORACLE_OK;
+}
+
+/* Local element matrices of trilinear hexahedra by Algorithm 1 with a
+ * geometry tensor per quadrature point:
+ *   C_st = diag_q(w_q G_st(X_q)), H_st = C_st B_t^T, A = sum_s sum_t B_s H_st.
+ *   coords  [n_cells][8][3]
+ *   points  [n_q][3], weights [n_q]
+ *   bval    [n_q][n_phi], bgrad [3][n_q][n_phi] (stiffness only)
+ *   A_out   [n_cells][n_phi][n_phi]
+ * Returns ORACLE_OK or the first error met (ORACLE_EDEGENERATE: det J = 0 or
+ * not finite at some point; that cell's matrix is NaN). */
+int oracle_hex_local_matrices(int form, int64_t n_cells, const double *coords, int n_phi,
+                              int n_q, const double *points, const double *weights,
+                              const double *bval, const double *bgrad, double *A_out,
+                              int nthreads) {
+  if (n_phi < 1 || n_q < 1 || !coords || !points || !weights || !bval || !A_out)
+    return ORACLE_EINVAL;
+  if (form != FORM_MASS && form != FORM_STIFFNESS) return ORACLE_EINVAL;
+  if (form == FORM_STIFFNESS && !bgrad) return ORACLE_EINVAL;
+  const int nd = (form == FORM_MASS) ? 1 : 3;
+  int status = ORACLE_OK;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+  {
+    double *BT = (double *)malloc(sizeof(double) * nd * n_phi * n_q);
+    double *HT = (double *)malloc(sizeof(double) * nd * nd * n_phi * n_q);
+    double *C = (double *)malloc(sizeof(double) * nd * nd * n_q);
+    if (!BT || !HT || !C) {
+#pragma omp atomic write
+      status = ORACLE_ENOMEM;
+    } else {
+      for (int s = 0; s < nd; ++s)
+        for (int i = 0; i < n_phi; ++i)
+          for (int q = 0; q < n_q; ++q)
+            BT[((size_t)s * n_phi + i) * n_q + q] =
+                (form == FORM_MASS) ? bval[(size_t)q * n_phi + i]
+                                    : bgrad[((size_t)s * n_q + q) * n_phi + i];
+#pragma omp for schedule(static)
+      for (int64_t K = 0; K < n_cells; ++K) {
+        double *A = A_out + (size_t)K * n_phi * n_phi;
+        int st = ORACLE_OK;
+        /* Step 2: C_st(q) = w_q G_st(X_q) */
+        for (int q = 0; q < n_q && st == ORACLE_OK; ++q) {
+          double G[9];
+          st = hex_point_geometry(coords + K * 24, points + 3 * q, form, G);
+          for (int s = 0; s < nd; ++s)
+            for (int t = 0; t < nd; ++t) C[((size_t)s * nd + t) * n_q + q] = weights[q] * G[s * nd + t];
+        }
+        if (st != ORACLE_OK) {
+#pragma omp atomic write
+          status = st;
+          for (int e = 0; e < n_phi * n_phi; ++e) A[e] = NAN;
+          continue;
+        }
+        /* Step 3: H_st = C_st B_t^T, stored as H_st^T [s][t][j][q] */
+        for (int s = 0; s < nd; ++s)
+          for (int t = 0; t < nd; ++t) {
+            const double *c = C + ((size_t)s * nd + t) * n_q;
+            for (int j = 0; j < n_phi; ++j) {
+              const double *bt = BT + ((size_t)t * n_phi + j) * n_q;
+              double *h = HT + (((size_t)s * nd + t) * n_phi + j) * n_q;
+              for (int q = 0; q < n_q; ++q) h[q] = c[q] * bt[q];
+            }
+          }
+        /* Step 4: A = sum_s sum_t B_s H_st */
+        for (int i = 0; i < n_phi; ++i)
+          for (int j = 0; j < n_phi; ++j) {
+            double acc = 0.0;
+            for (int s = 0; s < nd; ++s) {
+              const double *bs = BT + ((size_t)s * n_phi + i) * n_q;
+              for (int t = 0; t < nd; ++t) {
+                const double *h = HT + (((size_t)s * nd + t) * n_phi + j) * n_q;
+                for (int q = 0; q < n_q; ++q) acc += bs[q] * h[q];
+              }
+            }
+            A[(size_t)i * n_phi + j] = acc;
+          }
+      }
+    }
+    free(BT); free(HT); free(C);
   }
   return status;
 }

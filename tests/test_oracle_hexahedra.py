@@ -1,5 +1,6 @@
-"""Pins for the oracle's hexahedral mass matrices (boxed cells, trilinear
-geometry evaluated per quadrature point), independent of the GPU library."""
+"""Pins for the oracle's hexahedral mass and Poisson matrices (boxed cells,
+trilinear geometry evaluated per quadrature point), independent of the GPU
+library."""
 from fractions import Fraction
 
 import numpy as np
@@ -37,8 +38,9 @@ def test_basis_kronecker_unity_linear(p):
         assert np.abs(grads[e] @ nodes[:, e] - 1).max() < 1e-10
 
 
-def _exact_1d_mass(p):
-    """int_0^1 L_i L_j with exact rational polynomial arithmetic."""
+def _exact_1d_mass(p, deriv=False):
+    """int_0^1 L_i L_j (or L_i' L_j' with deriv) with exact rational
+    polynomial arithmetic."""
     nodes = [Fraction(k, p) for k in range(p + 1)]
 
     def poly(k):                       # coefficients, lowest first
@@ -51,6 +53,8 @@ def _exact_1d_mass(p):
             c = [ci / den for ci in c]
         return c
     P = [poly(k) for k in range(p + 1)]
+    if deriv:
+        P = [[n * c for n, c in enumerate(pk)][1:] or [Fraction(0)] for pk in P]
     M = np.zeros((p + 1, p + 1))
     for i in range(p + 1):
         for j in range(p + 1):
@@ -137,3 +141,92 @@ def test_pins_are_sharp(mistake, monkeypatch):
         assert err > 1e-4
     else:
         assert kron > 0.5
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_unit_cube_stiffness_is_kronecker_sum_of_exact_1d_matrices(p):
+    corners = np.array([[(v >> e) & 1 for e in range(3)] for v in range(8)], dtype=float)
+    A = H.stiffness_matrices(corners[None], p, 2 * p)[0]
+    M1, K1 = _exact_1d_mass(p), _exact_1d_mass(p, deriv=True)
+    # index i + (p+1)(j + (p+1)k): the last Kronecker factor is x
+    ref = (np.kron(M1, np.kron(M1, K1)) + np.kron(M1, np.kron(K1, M1)) +
+           np.kron(K1, np.kron(M1, M1)))
+    assert np.abs(A - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def _hex_node_positions(m, p):
+    """Physical position of every global dof: the trilinear map of its cell
+    at the reference lattice point (shared nodes get one position: the map
+    on a face depends only on the face's vertices)."""
+    n1 = p + 1
+    idx = np.arange(n1 ** 3)
+    X = np.stack([idx % n1, (idx // n1) % n1, idx // n1 ** 2], axis=1) / p
+    phi = np.ones((len(X), 8))
+    for v in range(8):
+        for e in range(3):
+            phi[:, v] *= X[:, e] if (v >> e) & 1 else 1.0 - X[:, e]
+    pos = np.zeros((m.n_dofs, 3))
+    for K in range(m.cell_coords.shape[0]):
+        pos[m.dofmap[K]] = phi @ m.cell_coords[K]
+    return pos
+
+
+def _stiffness_pins(m, p, q):
+    """(max |K 1| / max|K|, max_e |x_e^T K x_e - 1|, symmetry defect)."""
+    A = H.stiffness_matrices(m.cell_coords, p, q)
+    rp, ci, vals = oracle.assemble(m.dofmap, A, m.n_dofs)
+    K = sp.csr_matrix((vals, ci, rp), shape=(m.n_dofs, m.n_dofs))
+    pos = _hex_node_positions(m, p)
+    rows = np.abs(K @ np.ones(m.n_dofs)).max() / np.abs(vals).max()
+    energy = max(abs(pos[:, e] @ (K @ pos[:, e]) - 1.0) for e in range(3))
+    sym = np.abs(A - A.transpose(0, 2, 1)).max() / np.abs(A).max()
+    return rows, energy, sym
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_jittered_mesh_stiffness_rows_and_coordinate_energy(p):
+    # the coordinate functions lie in Q_1 on every trilinear cell, so
+    # x^T K x = int |grad x|^2 = |Omega| = 1; |det J| has degree <= 2 per
+    # variable, integrated exactly by m >= 2 points per direction
+    m = hex_mesh(3, p, jitter=0.25, seed=4)
+    rows, energy, sym = _stiffness_pins(m, p, 2 * p)
+    assert rows < 1e-13 and energy < 1e-13 and sym < 1e-15, (rows, energy, sym)
+
+
+def test_uniform_mesh_stiffness_polynomial_integral():
+    # u = x^2 y, v = y z in Q_2: int grad u . grad v = int x^2 z = 1/6
+    m = hex_mesh(2, 2, jitter=0.0)
+    A = H.stiffness_matrices(m.cell_coords, 2, 4)
+    rp, ci, vals = oracle.assemble(m.dofmap, A, m.n_dofs)
+    K = sp.csr_matrix((vals, ci, rp), shape=(m.n_dofs, m.n_dofs))
+    u = _hex_nodal(m, 2, lambda x: x[:, 0] ** 2 * x[:, 1])
+    v = _hex_nodal(m, 2, lambda x: x[:, 1] * x[:, 2])
+    assert abs(u @ (K @ v) - 1.0 / 6.0) < 1e-14
+
+
+@pytest.mark.parametrize("mistake", ["swap_slabs", "flip_sign", "points_reordered"])
+def test_stiffness_pins_are_sharp(mistake, monkeypatch):
+    """Plausible mistakes planted in the oracle's inputs break a pin: two
+    derivative slabs exchanged, one slab's sign flipped (both invisible on
+    the unit cube, where G is diagonal and the sum symmetric in the axes),
+    and quadrature points out of step with their weights."""
+    tab, rule = H.tabulate, H.tensor_rule
+    if mistake == "swap_slabs":
+        monkeypatch.setattr(H, "tabulate", lambda p, X: (tab(p, X)[0], tab(p, X)[1][[1, 0, 2]]))
+    elif mistake == "flip_sign":
+        monkeypatch.setattr(H, "tabulate",
+                            lambda p, X: (tab(p, X)[0], tab(p, X)[1] * np.array([1, 1, -1])[:, None, None]))
+    else:
+        def bad_rule(q):
+            pts, w = rule(q)
+            return np.roll(pts, 1, axis=0), w
+        monkeypatch.setattr(H, "tensor_rule", bad_rule)
+    m = hex_mesh(3, 2, jitter=0.25, seed=4)
+    rows, energy, sym = _stiffness_pins(m, 2, 4)
+    mu = hex_mesh(2, 2, jitter=0.0)
+    A = H.stiffness_matrices(mu.cell_coords, 2, 4)
+    rp, ci, vals = oracle.assemble(mu.dofmap, A, mu.n_dofs)
+    K = sp.csr_matrix((vals, ci, rp), shape=(mu.n_dofs, mu.n_dofs))
+    u = _hex_nodal(mu, 2, lambda x: x[:, 0] ** 2 * x[:, 1])
+    v = _hex_nodal(mu, 2, lambda x: x[:, 1] * x[:, 2])
+    poly = abs(u @ (K @ v) - 1.0 / 6.0)
+    assert energy > 1e-6 or poly > 1e-6, (mistake, energy, poly)
