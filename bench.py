@@ -34,11 +34,13 @@ step = the numeric phase of all eight blocks (per-degree tiles from the
 autotuner) replayed as one HIP graph, FP16 storage / FP32 accumulation, the
 FP64 path beside it.
 
-Under "hex_mass": the mass form on hexahedra (the paper's boxed cells):
-38^3 jittered trilinear hexahedra (54,872 cells), Q4 (125 dofs/cell), the
-125-point tensor Gauss-Legendre rule, |det J| per quadrature point; one
-step = FE_NUMERIC (cell kernels + row-gather assembly into CSR), FP16
-storage / FP32 accumulation, the FP64 path beside it.
+Under "hex_mass" and "hex_stiffness": the mass and Poisson forms on
+hexahedra (the paper's boxed cells): 38^3 jittered trilinear hexahedra
+(54,872 cells), Q4 (125 dofs/cell), the 125-point tensor Gauss-Legendre
+rule, |det J| (mass) or G = |det J| J^-1 J^-T (Poisson) per quadrature
+point; one step = FE_NUMERIC (mass: geometry pass + fused row-ownership
+pass; Poisson: cell kernels + row gather into CSR), FP16 storage / FP32
+accumulation, the FP64 path beside it.
 
 Under "weighted_p6": the weighted P6 stiffness form div(kappa grad u) on the
 32^3 x 6 mesh (196,608 cells, 84 dofs/cell, 512-point rule, kappa as above,
@@ -114,6 +116,11 @@ def parse():
                     help="also run a plain 256 MiB elementwise copy (x * 1.0), the reference "
                          "kernel for scaling hardware byte counters")
     return ap.parse_args()
+
+
+def log(msg):
+    """Progress line on stderr (the JSON line alone goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def time_steps(fn, steps, warmup):
@@ -321,8 +328,8 @@ def mixed_section(args, steps, warmup):
     return out
 
 
-def hex_section(args, steps, warmup):
-    """Mass form on trilinear hexahedra (Q4): FE_NUMERIC in FP16 and FP64."""
+def hex_section(args, steps, warmup, form="mass"):
+    """A form on trilinear hexahedra (Q4): FE_NUMERIC in FP16 and FP64."""
     import numpy as np
     import torch
 
@@ -332,17 +339,25 @@ def hex_section(args, steps, warmup):
 
     m = hex_mesh(38, 4, jitter=0.25, seed=0)
     n_cells, n_phi, n_q = m.cell_coords.shape[0], 125, 125
+    nd = 1 if form == "mass" else 3
     mv = api.MeshView.from_numpy(m.cell_coords, m.dofmap, m.n_dofs)
-    out = {"workload": "Q4 mass on 38^3 jittered trilinear hexahedra (54,872 cells, 125 dofs/cell), "
-                       "125-point tensor Gauss-Legendre rule, |det J| per point",
+    what = "|det J| per point" if form == "mass" else "G = |det J| J^-1 J^-T per point"
+    out = {"workload": f"Q4 {form} on 38^3 jittered trilinear hexahedra (54,872 cells, 125 dofs/cell), "
+                       f"125-point tensor Gauss-Legendre rule, {what}",
            "n_cells": n_cells, "n_dofs": m.n_dofs}
     res = {}
     for prec in ("fp16", "fp64"):
-        asm = api.Assembly(mv, [api.form_desc(L.FE_HEXAHEDRON, 4, 8, "mass", prec)])
+        log(f"hexahedral {form}: {prec}")
+        asm = api.Assembly(mv, [api.form_desc(L.FE_HEXAHEDRON, 4, 8, form, prec)])
         res[prec] = time_steps(asm.numeric, steps if prec == "fp16" else max(3, steps // 2), warmup)
         if prec == "fp16":
-            # the cell kernels + row gather, for comparison
-            res["gather"] = time_steps(lambda: asm.numeric(gather=True), max(3, steps // 2), warmup)
+            if form == "mass":
+                # the cell kernels + row gather, for comparison
+                res["gather"] = time_steps(lambda: asm.numeric(gather=True), max(3, steps // 2), warmup)
+            else:
+                res["local"] = time_steps(lambda: asm.numeric(part="local"), max(3, steps // 2), warmup)
+                res["assemble"] = time_steps(lambda: asm.numeric(part="assemble"), max(3, steps // 2),
+                                             warmup)
         if any(st != 0 for st in asm.status()):
             raise RuntimeError("device status after the hexahedral step")
         res[prec + "_vals"] = asm.numeric()[0][:asm.nnz].double().clone()
@@ -353,7 +368,7 @@ def hex_section(args, steps, warmup):
                 torch.linalg.vector_norm(res["fp64_vals"]))
     del res["fp16_vals"], res["fp64_vals"]
     ms = res["fp16"]
-    flops = n_cells * 2 * n_phi ** 2 * n_q
+    flops = n_cells * 2 * n_phi ** 2 * nd * n_q
     nbytes = (192 + 4 * n_phi) * n_cells + 4 * nnz
     t = ms / 1e3
     ideal = {"hbm": nbytes / (PEAK_HBM_GBS * 1e9), "mfma": flops / (PEAK_MFMA_TFLOPS["fp16"] * 1e12)}
@@ -363,28 +378,43 @@ def hex_section(args, steps, warmup):
         roof = {"bound": "mfma", "achieved": flops / t / 1e12, "peak": PEAK_MFMA_TFLOPS["fp16"],
                 "unit": "TFLOP/s"}
     roof.update({"frac": roof["achieved"] / roof["peak"], "traffic": None,
-                 "kernel": "k_box_geo + fused row-ownership pass (the whole step)",
+                 "kernel": ("k_box_geo + fused row-ownership pass (the whole step)" if form == "mass"
+                            else "cell kernels with per-point G + row gather (the whole step)"),
                  "ideal_us": {k: v * 1e6 for k, v in ideal.items()}, "alg_flops": flops,
                  "alg_bytes": nbytes})
-    out.update({"metric": "cells/s (hexahedral mass, kernels + CSR assembly)",
+    out.update({"metric": f"cells/s (hexahedral {form}, kernels + CSR assembly)",
                 "value": n_cells / t, "unit": "cells/s", "dtype": "f16 x f16 -> f32",
                 "ms_per_step": ms, "nnz": nnz,
                 "fp64_path": {"value": n_cells / (res["fp64"] / 1e3), "ms_per_step": res["fp64"]},
-                "gather_path_fp16_ms": res["gather"],
                 "speedup_vs_fp64": res["fp64"] / ms, "rel_err_vs_fp64": err, "roofline": roof})
+    if form == "mass":
+        out["gather_path_fp16_ms"] = res["gather"]
+    else:
+        out["kernels"] = {"local_matrices": {"ms": res["local"]}, "row_gather": {"ms": res["assemble"]}}
     if not args.no_cpu_baseline:
         import oracle
         import oracle.hexahedra as H
-        n = min(args.hex_cpu_cells, n_cells)
+        log(f"hexahedral {form}: oracle baseline")
+        n = min(args.hex_cpu_cells if form == "mass" else args.hex_cpu_cells // 3, n_cells)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
         rp, ci = oracle.csr_pattern(m.dofmap[:n], m.n_dofs)      # symbolic: not timed
         t0 = time.perf_counter()
-        A = H.mass_matrices(m.cell_coords[:n], 4, 8)
+        A = H.local_matrices(form, m.cell_coords[:n], 4, 8, nthreads=threads)
         oracle.assemble(m.dofmap[:n], A, m.n_dofs, rp, ci)
         dt = time.perf_counter() - t0
+        del A
+        n1 = min(1000 if form == "mass" else 300, n)
+        rp1, ci1 = oracle.csr_pattern(m.dofmap[:n1], m.n_dofs)
+        t0 = time.perf_counter()
+        A = H.local_matrices(form, m.cell_coords[:n1], 4, 8, nthreads=1)
+        oracle.assemble(m.dofmap[:n1], A, m.n_dofs, rp1, ci1)
+        dt1 = time.perf_counter() - t0
         out["cpu_baseline"] = {
-            "value": n / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} of {n_cells} cells: local mass matrices (numpy FP64, per-point "
-                      f"geometry) + CSR assembly (C, one thread), one pass of {dt:.1f} s"}
+            "value": n / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} of {n_cells} cells: local {form} matrices (FP64, per-point "
+                      f"geometry, {threads} OpenMP threads) + CSR assembly, one pass of {dt:.1f} s",
+            "single_thread": {"value": n1 / dt1, "unit": "cells/s", "cores": 1,
+                              "sample": f"first {n1} cells, one pass of {dt1:.1f} s"}}
     return out
 
 
@@ -407,6 +437,10 @@ def c3_section(args, steps, warmup):
     f_con = 2 * n_phi ** 2 * 3 * n_q
     f_coef = 2 * n_phi * n_q
     flops = (f_con + f_coef) * m.n_cells
+    # what the FP16 whole-cell kernel executes on the matrix cores: the 21
+    # tiles (I <= J) of the 6 x 6 row-tile grid (padded to 96), K = 3 n_q,
+    # plus the coefficient pass (n_q x 96 x 16-cell tiles)
+    hw_flops = (21 * 2 * 16 * 16 * 3 * n_q + 2 * n_q * 96) * m.n_cells
     out = {"workload": "P6 weighted stiffness div(kappa grad u), 32^3 x 6 jittered Kuhn tetrahedra "
                        "(196,608 cells, 84 dofs/cell), 512-point collapsed Gauss-Jacobi rule, "
                        "kappa = exp(sin(2 pi x) cos(2 pi y) z) interpolated in P6, FP64 geometry",
@@ -415,13 +449,16 @@ def c3_section(args, steps, warmup):
     modes, vals = {}, {}
     # FP64 first: its values are the reference of the other modes' errors
     for prec in ("fp64", "fp32", "bf16", "fp16"):
+        log(f"weighted P6 stiffness: {prec}")
         desc = api.form_desc(3, 6, q, "stiffness", prec, has_coeff=True)
         asm = api.Assembly(mv, [desc])
         k = steps if prec in ("fp16", "bf16") else max(3, steps // 4)
         w = warmup if prec in ("fp16", "bf16") else max(1, warmup // 2)
         ms = time_steps(asm.numeric, k, w)
-        ms_cell = time_steps(lambda: api.fe_cell_kernels(desc, asm.form_bufs[0], mv, asm.workspace),
-                             k, w)
+        # the two halves of the step: local matrices (for FP16 the
+        # coefficient at the points, then the whole-cell kernel), row gather
+        ms_cell = time_steps(lambda: asm.numeric(part="local"), k, w)
+        ms_gather = time_steps(lambda: asm.numeric(part="assemble"), k, w)
         (v,) = asm.numeric()
         torch.cuda.synchronize()
         if any(st != 0 for st in asm.status()):
@@ -434,10 +471,11 @@ def c3_section(args, steps, warmup):
             "ms_per_step": ms, "value": m.n_cells / (ms / 1e3), "unit": "cells/s",
             "dtype": {"fp16": "f16 x f16 -> f32", "bf16": "bf16 x bf16 -> f32", "fp32": "f32",
                       "fp64": "f64"}[prec],
-            "kernels": {"cell_kernel": {"ms": ms_cell}, "row_gather": {"ms": ms - ms_cell}},
+            "kernels": {"local_matrices": {"ms": ms_cell}, "row_gather": {"ms": ms_gather}},
             "roofline": {"bound": "mfma", "achieved": flops / t_cell / 1e12, "peak": peak,
                          "unit": "TFLOP/s", "frac": flops / t_cell / 1e12 / peak, "traffic": None,
-                         "kernel": "cell_kernel (a2-a5 of every cell)",
+                         "kernel": ("coefficient at the points + whole-cell kernel (a2-a5 of every "
+                                    "cell)" if prec == "fp16" else "cell_kernel (a2-a5 of every cell)"),
                          "step_frac": flops / (ms / 1e3) / 1e12 / peak},
         }
         del asm
@@ -453,6 +491,9 @@ def c3_section(args, steps, warmup):
     out["nnz"] = nnz
     out["modes"] = modes
     f16 = modes["fp16"]
+    t16 = f16["kernels"]["local_matrices"]["ms"] / 1e3
+    f16["roofline"]["mfma_executed_tflops"] = hw_flops / t16 / 1e12
+    f16["roofline"]["mfma_executed_frac"] = hw_flops / t16 / 1e12 / PEAK_MFMA_TFLOPS["fp16"]
     out.update({"metric": "cells/s (weighted P6 stiffness, kernels + CSR assembly)",
                 "value": f16["value"], "unit": "cells/s", "dtype": f16["dtype"],
                 "ms_per_step": f16["ms_per_step"], "roofline": f16["roofline"],
@@ -460,6 +501,7 @@ def c3_section(args, steps, warmup):
                 "speedup_vs_fp64": f16["speedup_vs_fp64"]})
     if not args.no_cpu_baseline:
         import oracle
+        log("weighted P6 stiffness: oracle baseline")
         n = min(args.c3_cpu_cells, m.n_cells)
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
         tab = oracle.tabulation(3, 6, q)
@@ -525,6 +567,7 @@ def main():
     import torch
 
     from fe_inputs import config_mesh
+    from paper_2410_12614_amd import _lib as L
     from paper_2410_12614_amd import api
 
     mesh = config_mesh("c2")
@@ -579,6 +622,7 @@ def main():
     # The FP64 path and the other mixed modes first (their values are kept
     # for the error of each mode against FP64), then the reported mode.
     result, v64, other = {}, None, {}
+    log("P4 mass+stiffness: FP64 path")
     if not args.no_fp64:
         asm64 = assembly("fp64")
         ms64 = time_steps(asm64.numeric, max(3, args.steps // 4), max(1, args.warmup // 5))
@@ -595,17 +639,25 @@ def main():
     for other_prec in ("split", "bf16"):
         if other_prec == prec:
             continue
+        log(f"P4 mass+stiffness: {other_prec}")
         a2 = assembly(other_prec)
         ms2 = time_steps(a2.numeric, args.steps, args.warmup)
-        ms2_fused = time_steps(lambda: a2.numeric(part="fused"), args.steps, args.warmup)
+        try:
+            # the fused pass alone, where every form of the pair takes it
+            ms2_fused = time_steps(lambda: a2.numeric(part="fused"), args.steps, args.warmup)
+            roof_kernel = "fused_pass"
+        except L.FeError:
+            ms2_fused = ms2
+            roof_kernel = "whole step (cell kernels + row gather for a form off the fused path)"
         if any(st != 0 for st in a2.status()):
             raise RuntimeError(f"device status ({other_prec})")
         roof2 = c2_roofline(other_prec, ms2_fused / 1e3, a2.nnz)
+        roof2["kernel"] = roof_kernel
         roof2["traffic"] = None
         other[other_prec] = {
             "ms_per_step": ms2, "value": mesh.n_cells / (ms2 / 1e3), "unit": "cells/s",
             "dtype": {"bf16": "bf16 x bf16 -> f32", "split": "2xf16 x 2xf16 -> f32"}[other_prec],
-            "fused_pass_ms": ms2_fused, "roofline": roof2,
+            "roofline_ms": ms2_fused, "roofline": roof2,
         }
         if v64 is not None:
             other[other_prec]["rel_err_vs_fp64"] = rel_errs(a2.numeric(), a2.nnz)
@@ -613,6 +665,7 @@ def main():
         del a2
         torch.cuda.empty_cache()
 
+    log(f"P4 mass+stiffness: {prec} (reported)")
     asm = assembly(prec)
     ms = time_steps(asm.numeric, args.steps, args.warmup)
     st = asm.status()
@@ -664,19 +717,26 @@ def main():
         **result,
     }
     if not args.no_cpu_baseline:
+        log("P4 mass+stiffness: oracle baseline")
         line["cpu_baseline"] = cpu_baseline(mesh, args.cpu_sample_cells, args.cpu_reps)
     del asm
     torch.cuda.empty_cache()
     if not args.no_action:
+        log("action + VJP")
         line["action_vjp"] = action_section(args, max(3, args.steps // 2), max(1, args.warmup // 5))
     if not args.no_mixed:
         torch.cuda.empty_cache()
+        log("mixed-degree batch")
         line["mixed_degree"] = mixed_section(args, max(3, args.steps // 4), max(1, args.warmup // 5))
     if not args.no_hex:
         torch.cuda.empty_cache()
         line["hex_mass"] = hex_section(args, max(3, args.steps // 4), max(1, args.warmup // 5))
+        torch.cuda.empty_cache()
+        line["hex_stiffness"] = hex_section(args, max(3, args.steps // 4), max(1, args.warmup // 5),
+                                            form="stiffness")
     if not args.no_c3:
         torch.cuda.empty_cache()
+        log("weighted P6 stiffness")
         line["weighted_p6"] = c3_section(args, max(3, args.steps // 4), max(1, args.warmup // 5))
     print(json.dumps(line), flush=True)
 

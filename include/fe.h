@@ -65,9 +65,11 @@ enum {
  * trilinearly; its cell_coords are [n_cells][8][3], vertex v at the reference
  * corner (v & 1, (v >> 1) & 1, (v >> 2) & 1).  Hexahedra: Lagrange Q_p on the
  * equispaced lattice (n_phi = (p+1)^3, local index i + (p+1)(j + (p+1)k)),
- * tensor Gauss-Legendre quadrature; forms: the mass form with p <= 4 (other
- * forms and degrees FE_EUNSUPPORTED); J and |det J| vary over the cell and
- * enter per quadrature point. */
+ * p <= 7, tensor Gauss-Legendre quadrature; J, |det J| and the Poisson
+ * tensor G vary over the cell and enter per quadrature point (FP64).  The
+ * Poisson form keeps G of a batch of 16 cells at every point in LDS in the
+ * arithmetic type of H: it is available up to Q7 in FE_FP16_ACC32, Q6 in the
+ * single-precision modes and Q4 in FE_FP64 (FE_EUNSUPPORTED beyond). */
 enum { FE_TRIANGLE = 2, FE_TETRAHEDRON = 3, FE_HEXAHEDRON = 8 };
 
 /* Forms of Section 3.1. */
@@ -113,7 +115,9 @@ enum {
   FE_NUMERIC = 2,
   FE_NUMERIC_GATHER = 3,
   FE_NUMERIC_GEOMETRY = 4, /* first half of the fused FE_NUMERIC */
-  FE_NUMERIC_FUSED = 5     /* second half of the fused FE_NUMERIC */
+  FE_NUMERIC_FUSED = 5,    /* second half of the fused FE_NUMERIC */
+  FE_NUMERIC_LOCAL = 6,    /* first half of FE_NUMERIC_GATHER: local matrices */
+  FE_NUMERIC_ASSEMBLE = 7  /* second half of FE_NUMERIC_GATHER: the row gather */
 };
 
 typedef struct fe_form_desc {
@@ -327,6 +331,14 @@ fe_status fe_dg_pattern(int32_t n_blocks, const int64_t *n_cells, const int32_t 
  *       FE_EUNSUPPORTED when the fused path does not apply to every form;
  *       FE_EINVAL when the schedule was built for forms of another value
  *       type or task span (checked on the host before any launch).
+ *   FE_NUMERIC_LOCAL, FE_NUMERIC_ASSEMBLE : the two halves of
+ *       FE_NUMERIC_GATHER: LOCAL writes the local matrices of every form
+ *       into the workspace, ASSEMBLE runs the row gather on what the last
+ *       LOCAL (or FE_NUMERIC / FE_NUMERIC_GATHER) call left there.
+ *   FP16 Poisson forms with a coefficient on P6 tetrahedra compute their
+ *   local matrices with a whole-cell kernel (one wave per cell, symmetric
+ *   tiles, the coefficient at the points evaluated first into the
+ *   workspace); fe_cell_kernels keeps the batched cell kernel.
  * Errors: FE_EINVAL (NULL pointers, dof entries out of range are reported
  * through the status word of the plan), FE_ESIZE, FE_EUNSUPPORTED, FE_EHIP.
  * ------------------------------------------------------------------------ */

@@ -39,6 +39,8 @@ FE_NUMERIC = 2
 FE_NUMERIC_GATHER = 3
 FE_NUMERIC_GEOMETRY = 4
 FE_NUMERIC_FUSED = 5
+FE_NUMERIC_LOCAL = 6
+FE_NUMERIC_ASSEMBLE = 7
 FE_ACTION = 0
 FE_VJP = 1
 

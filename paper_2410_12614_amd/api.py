@@ -168,10 +168,12 @@ class Assembly:
     def numeric(self, gather: bool = False, part: Optional[str] = None) -> list:
         """FE_NUMERIC (fused row-ownership path where it applies) or, with
         ``gather``, FE_NUMERIC_GATHER (cell kernels + row gather); ``part``
-        "geometry" or "fused" runs one half of the fused FE_NUMERIC."""
+        "geometry" or "fused" runs one half of the fused FE_NUMERIC, "local"
+        or "assemble" one half of FE_NUMERIC_GATHER."""
         phase = L.FE_NUMERIC_GATHER if gather else L.FE_NUMERIC
         if part is not None:
-            phase = {"geometry": L.FE_NUMERIC_GEOMETRY, "fused": L.FE_NUMERIC_FUSED}[part]
+            phase = {"geometry": L.FE_NUMERIC_GEOMETRY, "fused": L.FE_NUMERIC_FUSED,
+                     "local": L.FE_NUMERIC_LOCAL, "assemble": L.FE_NUMERIC_ASSEMBLE}[part]
         check(fe_assemble_csr(self.descs, self.form_bufs, self.mesh, phase, self.mats,
                               self.plan, self.workspace, self.stream), "fe_assemble_csr(NUMERIC)")
         return self.values

@@ -35,6 +35,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "fe_internal.h"
 
@@ -187,6 +188,7 @@ struct KArgs {
   void *A;
   int64_t n_cells, n_dofs;
   int d, nd, n_phi, n_q, n_q_pad, nks;
+  int mt0, mt_all;     // row tiles [mt0, mt0 + MT) of the form's mt_all in this launch
 };
 
 // FP64 geometry of one affine simplex: G = |det J| J^{-1} J^{-T} computed as
@@ -316,6 +318,72 @@ __device__ __forceinline__ double box_det(const double *x, const double *X) {
          J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
 }
 
+// Poisson geometry tensor of the trilinear map at X, FP64:
+// G = adj(J) adj(J)^T / |det J| with J_ij = sum_v x_v,i d_j phi_v(X).
+// Returns false when det J == 0 or a value is not finite.
+__device__ __forceinline__ bool box_poisson(const double *x, const double *X, double G[3][3]) {
+  double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int v = 0; v < 8; ++v) {
+    double f[3], df[3];
+    for (int e = 0; e < 3; ++e) {
+      const bool b = (v >> e) & 1;
+      f[e] = b ? X[e] : 1.0 - X[e];
+      df[e] = b ? 1.0 : -1.0;
+    }
+    const double g[3] = {df[0] * f[1] * f[2], f[0] * df[1] * f[2], f[0] * f[1] * df[2]};
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) J[i][j] += x[v * 3 + i] * g[j];
+  }
+  double adj[3][3];
+  adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+  adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+  adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+  adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  const double det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
+  const double r = 1.0 / fabs(det);
+  bool ok = det != 0.0 && isfinite(det);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      G[i][j] = (adj[i][0] * adj[j][0] + adj[i][1] * adj[j][1] + adj[i][2] * adj[j][2]) * r;
+      ok = ok && isfinite(G[i][j]);
+    }
+  return ok;
+}
+
+// Unique components of a symmetric 3x3 tensor: (00, 01, 02, 11, 12, 22).
+__device__ __forceinline__ int sym_comp(int s, int t) {
+  const int a = s < t ? s : t, b = s < t ? t : s;
+  return a == 0 ? b : (a == 1 ? 2 + b : 5);
+}
+
+// Exact power-of-two scale exponent e of H for one cell, from a bound
+// gabs >= max_s sum_t |G_st| of its geometry factors and the largest
+// per-point factor zmax, and the exact inverse of all the scales (the cell's
+// and those of B^T and of the half weighted table), as in cell_factors.
+template <class P>
+__device__ __forceinline__ int cell_scale_exp(const FormHeader *hdr, double gabs, double zmax,
+                                              typename P::real &inv) {
+  int esK = 0;
+  if constexpr (P::H16) {
+    const double bound = hdr->max_wb * hdr->w_scale * gabs * fmax(zmax, 1.0);
+    if (bound > 0.0 && isfinite(bound)) esK = 14 - ilogb(bound);
+  } else if constexpr (P::SCALED) {
+    const double bound = hdr->max_wb * gabs * zmax;
+    if (bound > 0.0 && isfinite(bound)) esK = 14 - ilogb(bound);
+  }
+  typedef typename P::real T;
+  if constexpr (P::H16)
+    inv = (T)ldexp(1.0, -esK - ilogb(hdr->b_scale) - ilogb(hdr->w_scale));
+  else
+    inv = (T)ldexp(1.0, -esK - ilogb(hdr->b_scale));
+  return esK;
+}
+
 // Factors of H for one cell: the geometry tensor (|det J| for the mass
 // form) times the exact power-of-two scale sigma = 2^e with
 // |H| <= sigma max|w B| max_s sum_t |G_st| max_q |z_q| < 2^15, rounded once to
@@ -325,30 +393,16 @@ template <class P>
 __device__ __forceinline__ void cell_factors(const FormHeader *hdr, int nd, bool valid, bool ok,
                                              const double G[3][3], double adet, double zmax,
                                              typename P::hreal Gp[3][3], typename P::real &inv) {
-  typedef typename P::real T;
   typedef typename P::hreal HT;
   double gabs = adet;
   if (nd > 1) {
     gabs = 0.0;
     for (int s = 0; s < 3; ++s) gabs = fmax(gabs, fabs(G[s][0]) + fabs(G[s][1]) + fabs(G[s][2]));
   }
-  double sK = 1.0;
-  int esK = 0;
-  if constexpr (P::H16) {
-    // half arithmetic: the partial sums over t and their product with z stay
-    // below 2^15 (the table carries its own scale)
-    const double bound = hdr->max_wb * hdr->w_scale * gabs * fmax(zmax, 1.0);
-    if (bound > 0.0 && isfinite(bound)) {
-      esK = 14 - ilogb(bound);
-      sK = ldexp(1.0, esK);
-    }
-  } else if constexpr (P::SCALED) {
-    const double bound = hdr->max_wb * gabs * zmax;
-    if (bound > 0.0 && isfinite(bound)) {
-      esK = 14 - ilogb(bound);
-      sK = ldexp(1.0, esK);
-    }
-  }
+  // half arithmetic: the partial sums over t and their product with z stay
+  // below 2^15 (the table carries its own scale); all scales are exact
+  // powers of two, inverted by exponents
+  const double sK = ldexp(1.0, cell_scale_exp<P>(hdr, gabs, zmax, inv));
   for (int s = 0; s < 3; ++s)
     for (int t = 0; t < 3; ++t) {
       double v = (nd == 1) ? (s == 0 && t == 0 ? adet : 0.0) : G[s][t];
@@ -356,11 +410,6 @@ __device__ __forceinline__ void cell_factors(const FormHeader *hdr, int nd, bool
       else if (!ok) v = NAN;
       Gp[s][t] = (HT)(v * sK);
     }
-  // all scales are exact powers of two: invert by exponents
-  if constexpr (P::H16)
-    inv = (T)ldexp(1.0, -esK - ilogb(hdr->b_scale) - ilogb(hdr->w_scale));
-  else
-    inv = (T)ldexp(1.0, -esK - ilogb(hdr->b_scale));
 }
 
 // H for one lane in half arithmetic: h = Gs[0] w[0] + Gs[1] w[1] + Gs[2] w[2],
@@ -395,6 +444,40 @@ __device__ __forceinline__ void form_h(const T *Gs, const T (&w)[NDT][KPL], T (&
   }
 }
 
+// H for one lane with a geometry tensor per quadrature point (hexahedral
+// Poisson form), half arithmetic: h[e] = g[0][e] w[0][e] + g[1][e] w[1][e]
+// + g[2][e] w[2][e] on pairs of entries, g[t] holding G_st at this lane's
+// eight points.
+template <int NDT>
+__device__ __forceinline__ half8_t form_h16_pp(const half8_t (&g)[NDT], const half8_t (&w)[NDT]) {
+  half8_t h;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    half2_t x = half2_t{w[0][2 * p], w[0][2 * p + 1]} * half2_t{g[0][2 * p], g[0][2 * p + 1]};
+#pragma unroll
+    for (int t = 1; t < NDT; ++t)
+      x = __builtin_elementwise_fma(half2_t{w[t][2 * p], w[t][2 * p + 1]},
+                                    half2_t{g[t][2 * p], g[t][2 * p + 1]}, x);
+    h[2 * p] = x[0];
+    h[2 * p + 1] = x[1];
+  }
+  return h;
+}
+
+// The same in the arithmetic type of H (single or double), summed t = 0, 1, 2
+// from zero.
+template <class T, int NDT, int KPL>
+__device__ __forceinline__ void form_h_pp(const T (&g)[NDT][KPL], const T (&w)[NDT][KPL],
+                                          T (&h)[KPL]) {
+#pragma unroll
+  for (int e = 0; e < KPL; ++e) {
+    T x = 0;
+#pragma unroll
+    for (int t = 0; t < NDT; ++t) x += g[t][e] * w[t][e];
+    h[e] = x;
+  }
+}
+
 // 8 (KPL = 8) or 1 consecutive entries of the weighted table
 template <class T, int KPL>
 __device__ __forceinline__ void load_w(const T *w, T (&v)[KPL]) {
@@ -421,7 +504,14 @@ __device__ __forceinline__ typename P::frag lds_frag(const unsigned char *base, 
 // chunk's slice of the weighted table pass through a double-buffered LDS
 // ring filled by the whole workgroup, the next chunk's loads in flight
 // during the current chunk's math (forms whose tables do not fit on chip).
-template <class P, int MT, int JC, int NDT, bool COEFF, int STAGE, int NW>
+//
+// PG (hexahedral Poisson form): the geometry tensor varies over the cell, so
+// G(X_q) is evaluated in FP64 at every point of the batch's 16 cells, scaled
+// by the cell's exact power of two and kept in LDS in the arithmetic type
+// of H, [6 components][16 cells][n_q_pad + pad]; H is formed per point from
+// it.  Row windows: a launch may cover the row tiles [mt0, mt0 + MT) of a
+// form with mt_all row tiles (STAGE 0 only), for forms too wide for one.
+template <class P, int MT, int JC, int NDT, bool COEFF, int STAGE, int NW, bool PG = false>
 __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
   typedef typename P::real T;
   typedef typename P::hreal HT;  // weighted table and H formation
@@ -448,11 +538,18 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
   unsigned char *s_afl = smem + frag_bytes;
   HT *s_wt = (HT *)(smem + frag_bytes * (P::SPLIT ? 2 : 1));
   unsigned char *zbase = smem + frag_bytes * (P::SPLIT ? 2 : 1) + wtab_bytes;
-  Z *zq = (Z *)zbase;                                                   // [n_q_pad][16]
+  // per-point factors z_q: the coefficient, times |det J(X_q)| for the
+  // hexahedral mass form (none for the hexahedral Poisson form without a
+  // coefficient: its per-point geometry is in gq)
+  const int zq_len = (a.coeff || (a.box && !PG)) ? n_q_pad : 0;
+  Z *zq = (Z *)zbase;                                                   // [zq_len][16]
   // [16][24] vertex coordinates of hexahedra, then [16][n_phi] coefficient dofs
-  double *zloc = (double *)(zbase + (size_t)16 * n_q_pad * sizeof(Z));
+  double *zloc = (double *)(zbase + (size_t)16 * zq_len * sizeof(Z));
   const int zoff = a.box ? 16 * 24 : 0;
   double *zred = zloc + zoff + (a.coeff ? 16 * nphi : 0);  // [NT]
+  constexpr int GPAD = 16 / (int)sizeof(HT);
+  const int gstride = n_q_pad + GPAD;
+  HT *gq = (HT *)(zred + NT);  // PG: [6][16][gstride]
 
   if constexpr (STAGE == 1 || STAGE == 2) {
     const size_t n16 = frag_bytes / 16;
@@ -537,7 +634,7 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
       __syncthreads();
       const Z *vt = (const Z *)a.vtab;
       double zpart = 0.0;  // this thread's |z_q| maximum for cell tid % 16
-      for (int idx = tid; idx < 16 * n_q_pad; idx += NT) {
+      for (int idx = tid; idx < 16 * zq_len; idx += NT) {
         const int q = idx >> 4, cc = idx & 15;
         Z z = 0;
         if (q < a.n_q) {
@@ -546,7 +643,7 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
           } else {
             z = 1;
           }
-          if (a.box && cell0 + cc < a.n_cells) {
+          if (!PG && a.box && cell0 + cc < a.n_cells) {
             const double dj = box_det(zloc + cc * 24, a.ptab + 3 * q);
             if (!(dj != 0.0 && isfinite(dj))) {
               atomicOr(a.status, STATUS_DEGENERATE);
@@ -564,7 +661,7 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
       // max_q |z_q| of this lane's cell (threads tid and tid + 16 r share tid % 16)
       double m = 0.0;
       for (int r = 0; r < NT / 16; ++r) m = fmax(m, zred[c + 16 * r]);
-      zmax = m;
+      zmax = zq_len > 0 ? m : 1.0;
     }
     // the per-point factors of this lane's cell enter H scaled by the exact
     // power of two zs that brings max_q |z_q| into [1, 2) (per-point |det J|
@@ -583,6 +680,51 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
     HT Gp[3][3];
     T inv;
     cell_factors<P>(a.hdr, a.nd, valid, ok, G, adet, zmax, Gp, inv);
+    if constexpr (PG) {
+      // G(X_q) of the batch's cells (thread tid works on cell tid % 16 = c,
+      // as NT is a multiple of 16): first the bound max_q max_s sum_t
+      // |G_st(X_q)| of each cell for its scale, then the scaled values
+      double gpart = 0.0;
+      bool okp = true;
+      for (int idx = tid; idx < 16 * a.n_q; idx += NT) {
+        const int q = idx >> 4, cc = idx & 15;
+        if (cell0 + cc < a.n_cells) {
+          double Gq[3][3];
+          if (box_poisson(zloc + cc * 24, a.ptab + 3 * q, Gq)) {
+            for (int s2 = 0; s2 < 3; ++s2)
+              gpart = fmax(gpart, fabs(Gq[s2][0]) + fabs(Gq[s2][1]) + fabs(Gq[s2][2]));
+          } else {
+            okp = false;
+          }
+        }
+      }
+      __syncthreads();  // every thread has read zred for zmax
+      zred[tid] = okp ? gpart : -1.0;
+      __syncthreads();
+      double gm = 0.0;
+      bool okc = true;
+      for (int r = 0; r < NT / 16; ++r) {
+        const double v = zred[c + 16 * r];
+        okc = okc && v >= 0.0;
+        gm = fmax(gm, v);
+      }
+      const double sK = ldexp(1.0, cell_scale_exp<P>(a.hdr, gm, zmax, inv));
+      for (int idx = tid; idx < 16 * n_q_pad; idx += NT) {
+        const int q = idx >> 4, cc = idx & 15;
+        const bool live = cell0 + cc < a.n_cells && q < a.n_q;
+        double Gq[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        if (live) box_poisson(zloc + cc * 24, a.ptab + 3 * q, Gq);
+#pragma unroll
+        for (int s2 = 0; s2 < 3; ++s2)
+#pragma unroll
+          for (int t2 = s2; t2 < 3; ++t2) {
+            const double v = live ? (okc ? Gq[s2][t2] * sK : NAN) : 0.0;
+            gq[((size_t)sym_comp(s2, t2) * 16 + cc) * gstride + q] = (HT)v;
+          }
+      }
+      if (valid && !okc && wave == 0 && kb == 0) atomicOr(a.status, STATUS_DEGENERATE);
+      __syncthreads();
+    }
     inv = (T)ldexp((double)inv, ez);
 
     const HT *wt = (const HT *)a.wtab;
@@ -627,7 +769,7 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
         for (int s = 0; s < NDT; ++s)
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
-            const size_t fi = frag_slot(mt, s, qc, MT, NDT) * 64 + lane;
+            const size_t fi = frag_slot(a.mt0 + mt, s, qc, a.mt_all, NDT) * 64 + lane;
             if constexpr (STAGE == 3) {
               afr[s][mt] = lds_frag<P>(slot, ((size_t)s * MT + mt) * 64 + lane);
             } else if constexpr (STAGE >= 1) {
@@ -639,9 +781,24 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
             }
           }
         T zf[P::KPL];
-        if constexpr (COEFF) {
+        // without PG every coefficient-path form has per-point factors; the
+        // test is then a compile-time one, so that H and its rounding to the
+        // operand format compile exactly as in the fused kernel (same bits)
+        const bool zmul = PG ? a.coeff != nullptr : COEFF;
+        if (zmul) {
 #pragma unroll
           for (int e = 0; e < P::KPL; ++e) zf[e] = (T)zq[(qb + e) * 16 + c] * zs;
+        }
+        // PG: the six components of G at this lane's points
+        typedef typename std::conditional<P::H16, half8_t, HT[P::KPL]>::type GV;
+        GV gv[PG ? 6 : 1];
+        if constexpr (PG) {
+#pragma unroll
+          for (int cp = 0; cp < 6; ++cp) {
+            const HT *src = gq + ((size_t)cp * 16 + c) * gstride + qb;
+            if constexpr (P::H16) gv[cp] = *(const half8_t *)src;
+            else load_w<HT, P::KPL>(src, gv[cp]);
+          }
         }
 #pragma unroll
         for (int jj = 0; jj < JC; ++jj) {
@@ -658,11 +815,19 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
             for (int t = 0; t < NDT; ++t) wv[t] = *(const half8_t *)(wj + (size_t)t * tstride);
 #pragma unroll
             for (int s = 0; s < NDT; ++s) {
-              half2_t g2[NDT];
+              half8_t hf;
+              if constexpr (PG) {
+                half8_t g8[NDT];
 #pragma unroll
-              for (int t = 0; t < NDT; ++t) g2[t] = half2_t{Gp[s][t], Gp[s][t]};
-              half8_t hf = form_h16<NDT>(g2, wv);
-              if constexpr (COEFF) {
+                for (int t = 0; t < NDT; ++t) g8[t] = gv[sym_comp(s, t)];
+                hf = form_h16_pp<NDT>(g8, wv);
+              } else {
+                half2_t g2[NDT];
+#pragma unroll
+                for (int t = 0; t < NDT; ++t) g2[t] = half2_t{Gp[s][t], Gp[s][t]};
+                hf = form_h16<NDT>(g2, wv);
+              }
+              if (zmul) {
                 half8_t z8;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) z8[e] = (_Float16)zf[e];
@@ -678,8 +843,17 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
 #pragma unroll
             for (int s = 0; s < NDT; ++s) {
               T h[P::KPL];
-              form_h<T, NDT, P::KPL>(Gp[s], wv, h);
-              if constexpr (COEFF) {
+              if constexpr (PG) {
+                T g8[NDT][P::KPL];
+#pragma unroll
+                for (int t = 0; t < NDT; ++t)
+#pragma unroll
+                  for (int e = 0; e < P::KPL; ++e) g8[t][e] = gv[sym_comp(s, t)][e];
+                form_h_pp<T, NDT, P::KPL>(g8, wv, h);
+              } else {
+                form_h<T, NDT, P::KPL>(Gp[s], wv, h);
+              }
+              if (zmul) {
 #pragma unroll
                 for (int e = 0; e < P::KPL; ++e) h[e] *= zf[e];
               }
@@ -735,17 +909,18 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
                 if constexpr (P::SPLIT) v[r] += acc2[mt][jj][r] * (T)(1.0 / 2048.0);
                 v[r] *= inv;
               }
-              T *dst = A + (size_t)j * nphi + mt * 16;
+              const int i_base = (a.mt0 + mt) * 16;
+              T *dst = A + (size_t)j * nphi + i_base;
               if constexpr (sizeof(T) == 4) {
                 const int i0 = 4 * kb;  // P::row(kb, r) = 4 kb + r
-                if (mt * 16 + i0 + 3 < nphi) {
+                if (i_base + i0 + 3 < nphi) {
                   *(f4u_t *)(dst + i0) = f4u_t{v[0], v[1], v[2], v[3]};
                   continue;
                 }
               }
 #pragma unroll
               for (int r = 0; r < 4; ++r)
-                if (mt * 16 + P::row(kb, r) < nphi) dst[P::row(kb, r)] = v[r];
+                if (i_base + P::row(kb, r) < nphi) dst[P::row(kb, r)] = v[r];
             }
           }
       }
@@ -753,9 +928,9 @@ __global__ __launch_bounds__(NW * 64, 8 / NW) void cell_kernel(KArgs a) {
   }
 }
 
-template <class P, int MT, int JC, int NDT, bool COEFF, int STAGE, int NW>
+template <class P, int MT, int JC, int NDT, bool COEFF, int STAGE, int NW, bool PG = false>
 static fe_status launch_one(const KArgs &k, int64_t n_cells, size_t smem, int occ, hipStream_t s) {
-  auto kern = cell_kernel<P, MT, JC, NDT, COEFF, STAGE, NW>;
+  auto kern = cell_kernel<P, MT, JC, NDT, COEFF, STAGE, NW, PG>;
   LaunchInfo li;
   if (launch_info((const void *)kern, NW * 64, smem, &li) != FE_OK) return FE_EHIP;
   const int ncu = li.ncu;
@@ -778,6 +953,49 @@ static fe_status launch_mt(const KArgs &k, int64_t n_cells, size_t smem, int occ
                  : launch_one<P, MT, JC, 1, false, STAGE, NW>(k, n_cells, smem, occ, s);
   return coeff ? launch_one<P, MT, JC, 3, true, STAGE, NW>(k, n_cells, smem, occ, s)
                : launch_one<P, MT, JC, 3, false, STAGE, NW>(k, n_cells, smem, occ, s);
+}
+
+// Hexahedral forms in row windows of at most 8 row tiles (one launch per
+// window, each forming H again): 4-wave workgroups reading the fragments and
+// the weighted table through the caches (variant 2), per-point factors in
+// LDS; the Poisson form (PG) keeps G(X_q) per point there too.
+template <class P, int MT, bool PG>
+static fe_status launch_window(KArgs k, int64_t n_cells, size_t smem, int occ, hipStream_t s) {
+  // columns per wave: the accumulators, the fragments of three slabs and the
+  // per-point tensor fit the registers of two waves per SIMD
+  constexpr int JC = PG ? (MT == 8 ? 2 : (MT == 6 ? 3 : 4))
+                        : (P::REGMUL == 1 ? (MT == 8 ? 4 : (MT == 6 ? 7 : (MT == 4 ? 7 : (MT == 2 ? 8 : 4))))
+                                          : (MT == 8 ? 2 : (MT == 6 ? 3 : (MT == 2 ? 5 : 4))));
+  constexpr int NDT = PG ? 3 : 1;
+  return launch_one<P, MT, JC, NDT, true, 0, 4, PG>(k, n_cells, smem, occ, s);
+}
+
+template <class P, bool PG>
+static fe_status launch_box(const CellLaunch &a, KArgs k, int occ) {
+  const FormLayout &L = *a.L;
+  typedef typename P::hreal HT;
+  const size_t zq = (L.has_coeff || !PG) ? (size_t)16 * L.n_q_pad * sizeof(typename P::zreal) : 0;
+  const size_t zl = (size_t)(L.has_coeff ? L.n_phi : 0) + 24;
+  const size_t gq = PG ? (size_t)6 * 16 * (L.n_q_pad + 16 / sizeof(HT)) * sizeof(HT) : 0;
+  const size_t smem = zq + (size_t)16 * zl * 8 + 256 * 8 + gq;
+  if (smem > 156 * 1024) return FE_EUNSUPPORTED;
+  hipStream_t s = (hipStream_t)a.stream;
+  k.mt_all = L.mt;
+  for (int mt0 = 0; mt0 < L.mt; mt0 += 8) {
+    const int w = std::min(8, L.mt - mt0);
+    k.mt0 = mt0;
+    fe_status st = FE_EUNSUPPORTED;
+    switch (w) {
+      case 1: st = launch_window<P, 1, PG>(k, a.n_cells, smem, occ, s); break;
+      case 2: st = launch_window<P, 2, PG>(k, a.n_cells, smem, occ, s); break;
+      case 4: st = launch_window<P, 4, PG>(k, a.n_cells, smem, occ, s); break;
+      case 6: st = launch_window<P, 6, PG>(k, a.n_cells, smem, occ, s); break;
+      case 8: st = launch_window<P, 8, PG>(k, a.n_cells, smem, occ, s); break;
+      default: break;
+    }
+    if (st != FE_OK) return st;
+  }
+  return FE_OK;
 }
 
 template <class P>
@@ -812,6 +1030,16 @@ fe_status launch_cell_impl(const CellLaunch &a) {
   k.n_q = L.n_q;
   k.n_q_pad = L.n_q_pad;
   k.nks = L.nks;
+  k.mt0 = 0;
+  k.mt_all = L.mt;
+  // Hexahedra of the Poisson form (per-point G) and forms wider than 11 row
+  // tiles (Q5..Q7: 14, 22, 32) run in row windows through the caches
+  if (L.box && (L.ndt == 3 || L.mt > 8)) {
+    if (a.tile >= 0 && a.tile % 4 != 2) return FE_EUNSUPPORTED;
+    const int occ = a.tile < 0 ? 0 : a.tile / 4;
+    if (occ > 1) return FE_EINVAL;
+    return L.ndt == 3 ? launch_box<P, true>(a, k, occ) : launch_box<P, false>(a, k, occ);
+  }
   // per-point factors of H: a coefficient, or |det J(X_q)| of hexahedra
   const bool coeff = L.has_coeff != 0 || L.box != 0;
   const size_t zl = (size_t)(L.has_coeff ? L.n_phi : 0) + (L.box ? 24 : 0);

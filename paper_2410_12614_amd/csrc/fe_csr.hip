@@ -221,8 +221,8 @@ bool build_fused_schedule(const std::vector<int64_t> &rp, const std::vector<int6
         prev_row = g;
         const int64_t ent = adj[pos];
         FusedLane L;
-        L.cell = (int32_t)(ent >> 8);
-        L.j = (uint8_t)(ent & 255);
+        L.cell = (int32_t)(ent >> ADJ_BITS);
+        L.j = (uint8_t)(ent & ADJ_MASK);
         L.rowoff = (uint16_t)(rp[g] - rp[r0]);
         L.round = rnd;
         maxr = std::max(maxr, rnd);
@@ -350,7 +350,7 @@ __global__ void k_fill_adj(const int32_t *dofmap, int64_t n_cells, int n_phi, in
     if (g < 0 || g >= n_dofs) continue;
     const int64_t K = e / n_phi, i = e - K * n_phi;
     const unsigned long long p = atomicAdd((unsigned long long *)&cursor[g], 1ull);
-    adj[adj_ptr[g] + (int64_t)p] = K * 256 + i;
+    adj[adj_ptr[g] + (int64_t)p] = (K << ADJ_BITS) + i;
   }
 }
 
@@ -392,7 +392,7 @@ __global__ __launch_bounds__(256) void k_rows(const int32_t *dofmap, int n_phi,
     int32_t v = INT32_MAX;
     if (t < n) {
       const int64_t ent = adj[a0 + t / n_phi];
-      v = dofmap[(ent >> 8) * n_phi + (t % n_phi)];
+      v = dofmap[(ent >> ADJ_BITS) * n_phi + (t % n_phi)];
     }
     buf[t] = v;
   }
@@ -526,7 +526,7 @@ __global__ __launch_bounds__(64) void k_slot_ranks(const FusedTask *tasks, const
 // in cell-ascending order.
 constexpr int GATHER_W = 512;
 constexpr int GATHER_GROUP = 4;
-constexpr int GATHER_CH = 3;  // chunks of the longest local row (n_phi <= 192)
+constexpr int GATHER_CH = 8;  // chunks of the longest local row (n_phi <= 512)
 
 template <class T, int NF, int CH>
 __global__ __launch_bounds__(256) void k_gather(const int64_t *adj_ptr, const int64_t *adj,
@@ -558,7 +558,7 @@ __global__ __launch_bounds__(256) void k_gather(const int64_t *adj_ptr, const in
         size_t row = 0;
         if (a + u < a1) {
           const int64_t ent = adj[a + u];
-          row = (size_t)(ent >> 8) * n_phi + (ent & 255);
+          row = (size_t)(ent >> ADJ_BITS) * n_phi + (ent & ADJ_MASK);
         }
 #pragma unroll
         for (int ch = 0; ch < CH; ++ch) {
@@ -595,7 +595,11 @@ fe_status launch_gather(const int64_t *adj_ptr, const int64_t *adj, const uint16
                         void *const *V, hipStream_t s) {
   if (n_phi > 64 * GATHER_CH) return FE_EUNSUPPORTED;
   const int64_t blocks = (n_rows + 3) / 4;
-  auto kern = n_phi <= 64 ? k_gather<T, NF, 1> : n_phi <= 128 ? k_gather<T, NF, 2> : k_gather<T, NF, 3>;
+  auto kern = n_phi <= 64    ? k_gather<T, NF, 1>
+              : n_phi <= 128 ? k_gather<T, NF, 2>
+              : n_phi <= 192 ? k_gather<T, NF, 3>
+              : n_phi <= 256 ? k_gather<T, NF, 4>
+                             : k_gather<T, NF, 8>;
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, adj_ptr, adj, rank,
                      row_ptr, n_rows, n_phi, (const T *)A[0], (const T *)A[1], (const T *)A[2],
                      (const T *)A[3], (T *)V[0], (T *)V[1], (T *)V[2], (T *)V[3]);
@@ -651,9 +655,20 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
   size_t zpt_bytes = 0;
   for (int f = 0; f < n_forms; ++f)
     if (L[f].box) zpt_bytes = std::max(zpt_bytes, a256((size_t)n_cells * L[f].n_q_pad * 8));
-  const size_t ws_need = std::max<size_t>(256, zpt_offset + (size_t)n_forms * zpt_bytes);
+  // coefficient forms of the whole-cell kernel: the coefficient at the
+  // points [n_cells][n_q_pad] and its maximum per cell (FP32), one region
+  // shared by those forms (they run one after the other on the stream)
+  const size_t zc_offset = zpt_offset + (size_t)n_forms * zpt_bytes;
+  size_t zc_bytes = 0, zc_pts = 0;
+  for (int f = 0; f < n_forms; ++f)
+    if (forms[f].has_coeff && cellwise_eligible(L[f])) {
+      zc_pts = std::max(zc_pts, a256((size_t)n_cells * L[f].n_q_pad * sizeof(float)));
+      zc_bytes = zc_pts + a256((size_t)n_cells * sizeof(float));
+    }
+  const size_t ws_need = std::max<size_t>(256, zc_offset + zc_bytes);
   const bool numeric = phase == FE_NUMERIC || phase == FE_NUMERIC_GATHER ||
-                       phase == FE_NUMERIC_GEOMETRY || phase == FE_NUMERIC_FUSED;
+                       phase == FE_NUMERIC_GEOMETRY || phase == FE_NUMERIC_FUSED ||
+                       phase == FE_NUMERIC_LOCAL || phase == FE_NUMERIC_ASSEMBLE;
   if (!plan || (numeric && !workspace)) {
     if (!plan_bytes && !ws_bytes) return FE_EINVAL;
     if (plan_bytes) *plan_bytes = P.total;
@@ -820,8 +835,12 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
   // large) take the cell kernels and the row gather.
   bool on_fused[4] = {false, false, false, false};
   int n_fused = 0;
+  // the halves of the gather path (LOCAL: cell kernels into the workspace,
+  // ASSEMBLE: the row gather from it) take every form through the workspace
+  const bool via_ws = phase == FE_NUMERIC_GATHER || phase == FE_NUMERIC_LOCAL ||
+                      phase == FE_NUMERIC_ASSEMBLE;
   for (int f = 0; f < n_forms; ++f) {
-    on_fused[f] = phase != FE_NUMERIC_GATHER && sched_ok && fused_eligible(L[f]);
+    on_fused[f] = !via_ws && sched_ok && fused_eligible(L[f]);
     n_fused += on_fused[f] ? 1 : 0;
   }
   if ((phase == FE_NUMERIC_GEOMETRY || phase == FE_NUMERIC_FUSED) && n_fused < n_forms)
@@ -901,10 +920,32 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
     if (forms[f].has_coeff && !mv.coeff) return FE_EINVAL;
     a.A_local = Aloc[ng];
     a.stream = stream;
-    fe_status st = launch_cell(a);
-    if (st != FE_OK) return st;
     ++ng;
+    if (phase == FE_NUMERIC_ASSEMBLE) continue;
+    fe_status st;
+    if (forms[f].has_coeff && cellwise_eligible(L[f])) {
+      // coefficient forms in FP16: the whole-cell kernel after the
+      // coefficient at the points
+      CellwiseLaunch c;
+      c.L = &L[f];
+      c.form_buf = a.form_buf;
+      c.status = a.status;
+      c.n_cells = n_cells;
+      c.coords = mv.cell_coords;
+      c.dofmap = mv.dofmap;
+      c.n_dofs = n_dofs;
+      c.coeff = mv.coeff;
+      c.zpt = (float *)((unsigned char *)workspace + zc_offset);
+      c.zmax = (float *)((unsigned char *)workspace + zc_offset + zc_pts);
+      c.A_local = (float *)Aloc[ng - 1];
+      c.stream = stream;
+      st = launch_cellwise_fp16(c);
+    } else {
+      st = launch_cell(a);
+    }
+    if (st != FE_OK) return st;
   }
+  if (phase == FE_NUMERIC_LOCAL) return FE_OK;
   fe_status st = FE_EINVAL;
   if (elt == 8) {
     switch (ng) {
@@ -972,7 +1013,7 @@ __global__ __launch_bounds__(256) void k_vgather(const VecPlanHeader *hdr, const
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t e = a + u < a1 ? adj[a + u] : -1;
-      idx[u] = e < 0 ? -1 : (e >> 8) * n_phi + (e & 255);
+      idx[u] = e < 0 ? -1 : (e >> ADJ_BITS) * n_phi + (e & ADJ_MASK);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {

@@ -20,9 +20,9 @@ fe_status check_form(const fe_form_desc *f) {
   if (!f) return FE_EINVAL;
   if (f->cell != FE_TRIANGLE && f->cell != FE_TETRAHEDRON && f->cell != FE_HEXAHEDRON)
     return FE_EINVAL;
-  // hexahedra: the mass form (the Poisson tensor varies per point as a 3x3 matrix)
-  if (f->cell == FE_HEXAHEDRON && f->form != FE_MASS) return FE_EUNSUPPORTED;
   if (f->degree < 1 || f->quad_degree < 0) return FE_EINVAL;
+  // hexahedra: Q_1 .. Q_7 (n_phi <= 512), the degrees of the paper's boxed cells
+  if (f->cell == FE_HEXAHEDRON && f->degree > FE_MAX_BOX_DEGREE) return FE_EUNSUPPORTED;
   if (f->form != FE_MASS && f->form != FE_STIFFNESS) return FE_EINVAL;
   if (f->has_coeff != 0 && f->has_coeff != 1) return FE_EINVAL;
   if (f->precision < FE_FP64 || f->precision > FE_SPLITFP16_ACC32) return FE_EINVAL;
@@ -63,6 +63,9 @@ fe_status compute_layout(const fe_form_desc *f, FormLayout *L) {
   L->nks = L->k_pad / L->kstep;
   int jc;
   tile_choice(L->n_phi, 1, &L->mt, &jc);
+  // hexahedral forms wider than 8 row tiles run in windows of 8 row tiles,
+  // the last one 8 or 6 wide (Q5: 14, Q6: 22, Q7: 32 row tiles)
+  if (L->box && L->mt > 8 && L->mt <= 32 && (L->mt % 8 == 0 || L->mt % 8 == 6)) jc = 1;
   if (jc == 0) return FE_EUNSUPPORTED;
   L->elt_bytes = mfma16 ? 2 : (f->precision == FE_FP64 ? 8 : 4);
   L->tab_bytes = (f->precision == FE_FP64) ? 8 : (f->precision == FE_FP16_ACC32 ? 2 : 4);
@@ -79,6 +82,8 @@ fe_status compute_layout(const fe_form_desc *f, FormLayout *L) {
   if (L->has_coeff) off = align256(off + (size_t)L->n_q * L->n_phi * L->vtab_bytes);
   L->off_ptab = off;
   if (L->box) off = align256(off + (size_t)L->n_q * 3 * sizeof(double));
+  L->off_wq = off;
+  off = align256(off + (size_t)L->n_q_pad * sizeof(double));
   // action tables: FP32 / FP64 forms whose dofs fit the registers of a lane;
   // the K-steps are padded to the counts of the tetrahedral degrees 1..6
   // (the kernels are compiled for those), triangles take a zero third slab
@@ -258,7 +263,13 @@ extern "C" fe_status fe_form_prepare(const fe_form_desc *f, void *form_buf, size
   if (L.box)
     for (int q = 0; q < nq; ++q)
       for (int e = 0; e < 3; ++e) put<double>(h.data(), L.off_ptab, (size_t)q * 3 + e, pts[(size_t)q * 3 + e]);
+  double max_w = 0.0;
+  for (int q = 0; q < nq; ++q) {
+    put<double>(h.data(), L.off_wq, q, w[q]);
+    max_w = std::max(max_w, std::fabs(w[q]));
+  }
   hdr.max_wb = max_wb;
+  hdr.max_w = max_w;
   hdr.lebesgue = leb;
   std::memcpy(h.data(), &hdr, sizeof(hdr));
   hipStream_t s = (hipStream_t)stream;
@@ -276,7 +287,16 @@ bool fused_eligible(const FormLayout &L) {
   // buffers of at least 8 waves; otherwise the cell kernels and the row
   // gather are faster
   const FormLayout *one[1] = {&L};
+  // hexahedral Poisson forms (a geometry tensor per point) and forms with
+  // more than 256 dofs per cell (schedule records hold j in a byte) take the
+  // gather
+  if (L.box && L.ndt == 3) return false;
+  if (L.n_phi > 256) return false;
   return !L.has_coeff && fused_lds(one, 1, 8, true) <= FUSED_LDS_BUDGET;
+}
+
+bool cellwise_eligible(const FormLayout &L) {
+  return L.prec == FE_FP16_ACC32 && !L.box && L.d == 3 && L.ndt == 3 && L.mt == 6;
 }
 
 fe_status launch_info(const void *kern, int threads, size_t smem, LaunchInfo *out) {

@@ -9,6 +9,7 @@
 
 #define FE_MAX_DEGREE 8
 #define FE_MAX_QUAD_DEGREE 17
+#define FE_MAX_BOX_DEGREE 7
 
 namespace fe {
 
@@ -17,6 +18,11 @@ void gauss_jacobi_01(int m, int alpha, double *t, double *w);
 int simplex_dim(int d, int p);
 void lattice_indices(int d, int p, std::vector<int> &out);
 void lagrange_eval(int d, int p, const double *X, double *val, double *grad);
+
+// Adjacency entries (dof -> incident (cell, local index) pairs) encode
+// cell * 2^ADJ_BITS + i: local indices up to 1023 (Q_7 hexahedra: 512).
+constexpr int ADJ_BITS = 10;
+constexpr int64_t ADJ_MASK = (1 << ADJ_BITS) - 1;
 
 // Device status word bits (stored in the first word of a form buffer or plan).
 enum : int32_t { STATUS_DEGENERATE = 1, STATUS_BAD_DOF = 2 };
@@ -32,6 +38,7 @@ enum : int32_t { STATUS_DEGENERATE = 1, STATUS_BAD_DOF = 2 };
 //   afrag_lo: split mode only, fl16((B - fl16(B)) * 2^11) in the same layout
 //   wtab    : weighted table w_q B_t(q, j), [t][j][n_q_pad], t < NDT
 //   vtab    : basis values phi_k(X_q), [n_q][n_phi] (coefficient evaluation)
+//   wq      : quadrature weights w_q, [n_q_pad] double (zero padding)
 //   act     : tables of the action kernels (FP32 and FP64 forms with
 //             n_phi <= 84), one chunk of act_chunk elements per tile of 16
 //             quadrature points qt, see fe_action.h (K-steps padded to
@@ -48,7 +55,7 @@ struct FormLayout {
   int elt_bytes;  // bytes per operand element in afrag
   int tab_bytes;  // weighted table: 2 (half, FP16 mode), 4 (float) or 8 (double, FP64 mode)
   int vtab_bytes; // value table for the coefficient: 8 unless FP16/BF16 storage
-  size_t off_afrag, off_afrag_lo, off_wtab, off_vtab, off_ptab, total;
+  size_t off_afrag, off_afrag_lo, off_wtab, off_vtab, off_ptab, off_wq, total;
   int box;  // hexahedron: per-point |det J| (quadrature points at off_ptab)
   int act_nt, act_nks, act_mt, act_nqt;  // act_nt == 0: no action tables
   size_t act_chunk, off_act;
@@ -63,6 +70,7 @@ struct FormHeader {
   double lebesgue;  // max_q sum_k |phi_k(X_q)|
   double b_scale;   // exact power of two applied to the B^T operand (FP16/BF16 modes)
   double w_scale;   // exact power of two applied to the weighted table (FP16 mode)
+  double max_w;     // max_q w_q
 };
 
 constexpr int32_t FORM_MAGIC = 0x46453335;  // "FE35"
@@ -99,6 +107,25 @@ fe_status launch_cell_fp16(const CellLaunch &a);
 fe_status launch_cell_bf16(const CellLaunch &a);
 fe_status launch_cell_split(const CellLaunch &a);
 fe_status launch_cell(const CellLaunch &a);
+
+// ---- whole-cell kernel (one wave per cell, FP16), see fe_cellwise.h ----
+struct CellwiseLaunch {
+  const FormLayout *L;
+  const unsigned char *form_buf;
+  int32_t *status;
+  int64_t n_cells;
+  const double *coords;
+  const int32_t *dofmap;
+  int64_t n_dofs;
+  const double *coeff;  // nodal coefficient or null
+  float *zpt, *zmax;    // workspace: the coefficient at the points [n_cells][n_q_pad], its max per cell
+  float *A_local;       // [n_cells][n_phi][n_phi]
+  void *stream;
+};
+// Forms the whole-cell kernel is compiled for (FP16 storage, tetrahedra,
+// the Poisson form with 6 row tiles: P6).
+bool cellwise_eligible(const FormLayout &L);
+fe_status launch_cellwise_fp16(const CellwiseLaunch &c);
 
 // ---- fused (row-ownership) numeric path, see fe_fused.h ----
 constexpr int FUSED_SPAN = 1024;    // CSR entries per task (LDS row buffer of one wave)
@@ -222,7 +249,7 @@ struct VecPlanHeader {
 };
 constexpr int32_t VPLAN_MAGIC = 0x46455650;  // "FEVP"
 
-// dof -> (cell, i) adjacency, entries cell * 256 + i ascending per dof
+// dof -> (cell, i) adjacency, entries cell * 2^ADJ_BITS + i ascending per dof
 struct VecPlanLayout {
   size_t off_adj_ptr, off_cursor, off_adj, off_scan, scan_blocks, total;
 };

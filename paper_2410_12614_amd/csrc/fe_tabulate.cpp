@@ -240,6 +240,7 @@ extern "C" fe_status fe_tabulate(int32_t cell, int32_t degree, int32_t quad_degr
   if (degree < 1 || quad_degree < 0 || (nderiv != 0 && nderiv != 1)) return FE_EINVAL;
   if (!n_phi || !n_q) return FE_EINVAL;
   if (degree > FE_MAX_DEGREE || quad_degree > FE_MAX_QUAD_DEGREE) return FE_EUNSUPPORTED;
+  if (cell == FE_HEXAHEDRON && degree > FE_MAX_BOX_DEGREE) return FE_EUNSUPPORTED;
   if (cell == FE_HEXAHEDRON)
     return tabulate_hex(degree, quad_degree, nderiv, n_phi, n_q, points, weights, table);
   const int d = cell;

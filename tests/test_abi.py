@@ -54,7 +54,7 @@ def test_tabulate_matches_oracle(lib, d, p, q):
     np.testing.assert_allclose(tab[1:], og, rtol=0, atol=1e-13 * np.abs(og).max())
 
 
-@pytest.mark.parametrize("p,q", [(1, 2), (2, 4), (3, 6), (4, 8), (2, 0)])
+@pytest.mark.parametrize("p,q", [(1, 2), (2, 4), (3, 6), (4, 8), (2, 0), (5, 10), (7, 14)])
 def test_tabulate_hexahedron_matches_oracle(lib, p, q):
     import oracle.hexahedra as H
     pts, w, tab = api.fe_tabulate(L.FE_HEXAHEDRON, p, q)

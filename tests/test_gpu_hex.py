@@ -1,7 +1,7 @@
-"""GPU parity of hexahedral (boxed-cell) mass matrices and their assembly
-against the FP64 oracle: trilinear geometry, |det J| evaluated per
-quadrature point, Q_p on the equispaced lattice (p <= 4), tensor
-Gauss-Legendre quadrature of degree 2p."""
+"""GPU parity of hexahedral (boxed-cell) mass and Poisson matrices and their
+assembly against the FP64 oracle: trilinear geometry, |det J| (mass) or
+G = |det J| J^-1 J^-T (Poisson) evaluated per quadrature point, Q_p on the
+equispaced lattice (p <= 7), tensor Gauss-Legendre quadrature of degree 2p."""
 import sys
 
 import numpy as np
@@ -85,14 +85,87 @@ def test_hex_mass_local_and_assembled(p, prec):
         assert torch.equal(got["fused"], got["gather"]), (p, prec)
 
 
+def _local_and_gather(m, p, q, form, prec):
+    """(local error, assembled error) of the cell kernels and of FE_NUMERIC
+    (the cell kernels + row gather for forms off the fused path)."""
+    A_ref = H.local_matrices(form, m.cell_coords, p, q)
+    desc = api.form_desc(L.FE_HEXAHEDRON, p, q, form, prec)
+    mv = api.MeshView.from_numpy(m.cell_coords, m.dofmap, m.n_dofs)
+    buf = api.fe_form_prepare(desc)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    out = torch.full((m.cell_coords.shape[0], m.n_phi, m.n_phi), float("nan"), dtype=dt,
+                     device="cuda")
+    api.fe_cell_kernels(desc, buf, mv, out)
+    torch.cuda.synchronize()
+    assert api.fe_get_device_status(buf) == L.FE_OK
+    e_loc = _err(out.double().cpu().numpy(), A_ref, prec)
+    del out
+    asm = api.Assembly(mv, [desc])
+    rp, ci, ref = oracle.assemble(m.dofmap, A_ref, m.n_dofs)
+    np.testing.assert_array_equal(asm.row_ptr.cpu().numpy(), rp)
+    np.testing.assert_array_equal(asm.col_idx[:asm.nnz].cpu().numpy(), ci)
+    asm.values[0].fill_(float("nan"))
+    vals = asm.numeric()[0]
+    torch.cuda.synchronize()
+    assert all(s == 0 for s in asm.status())
+    e_glob = _err(vals[:asm.nnz].double().cpu().numpy(), ref, prec)
+    return e_loc, e_glob
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16", "split", "fp32", "bf16"])
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_hex_stiffness_local_and_assembled(p, prec):
+    """The Poisson form with G(X_q) per point, on 27 jittered cells (a full
+    and a ragged batch of 16)."""
+    m = hex_mesh(3, p, jitter=0.25, seed=1)
+    say(f"[hex stiffness] p={p} {prec}: {m.cell_coords.shape[0]} cells")
+    e_loc, e_glob = _local_and_gather(m, p, 2 * p, "stiffness", prec)
+    say(f"  local {e_loc:.2e}  assembled {e_glob:.2e}")
+    assert e_loc <= TOL[prec] and e_glob <= TOL[prec]
+
+
+# Q5..Q7 (n_phi 216, 343, 512: row windows of 8 row tiles), every precision
+# whose per-point tables fit a workgroup's LDS: the mass form everywhere, the
+# Poisson form's six components per point up to Q7 in half, Q6 in single,
+# Q4 in double
+HIGH = [(p, form, prec) for p in (5, 6, 7) for form in ("mass", "stiffness")
+        for prec in ("fp64", "fp16", "split", "fp32", "bf16")
+        if form == "mass" or prec == "fp16" or (prec != "fp64" and p <= 6)]
+
+
+# With up to 512 points the single-precision accumulation term of Corollary
+# 4.10, n_q u_q (3e-5 at n_q = 512, u_q = 2^-24, worst case), dominates the
+# split pair's and FP32's storage rounding: their bars grow accordingly
+TOL_HIGH = dict(TOL, split=4e-6, fp32=2e-5)
+
+
+@pytest.mark.parametrize("p,form,prec", HIGH)
+def test_hex_high_degree_local_and_assembled(p, form, prec):
+    m = hex_mesh(2, p, jitter=0.25, seed=2)       # 8 cells: a ragged batch
+    say(f"[hex high degree] Q{p} {form} {prec}: {m.cell_coords.shape[0]} cells, n_phi {m.n_phi}")
+    e_loc, e_glob = _local_and_gather(m, p, 2 * p, form, prec)
+    say(f"  local {e_loc:.2e}  assembled {e_glob:.2e}")
+    assert e_loc <= TOL_HIGH[prec] and e_glob <= TOL_HIGH[prec]
+
+
 def test_hex_unsupported_cases():
     m = hex_mesh(1, 2)
-    mv = api.MeshView.from_numpy(m.cell_coords, m.dofmap, m.n_dofs)
-    for form, p in (("stiffness", 2), ("mass", 5)):
-        desc = api.form_desc(L.FE_HEXAHEDRON, p, 2 * p, form, "fp16")
+    desc = api.form_desc(L.FE_HEXAHEDRON, 8, 16, "mass", "fp16")   # Q8: beyond Q7
+    with pytest.raises(L.FeError) as e:
+        api.fe_form_prepare(desc)
+    assert e.value.status == L.FE_EUNSUPPORTED
+    # per-point Poisson tensors beyond the LDS of a workgroup: refused on the
+    # host before any launch
+    for p, prec in ((5, "fp64"), (7, "fp32"), (7, "bf16")):
+        mp = hex_mesh(1, p)
+        mv = api.MeshView.from_numpy(mp.cell_coords, mp.dofmap, mp.n_dofs)
+        desc = api.form_desc(L.FE_HEXAHEDRON, p, 2 * p, "stiffness", prec)
+        buf = api.fe_form_prepare(desc)
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        out = torch.zeros((1, mp.n_phi, mp.n_phi), dtype=dt, device="cuda")
         with pytest.raises(L.FeError) as e:
-            api.fe_form_prepare(desc)
-        assert e.value.status == L.FE_EUNSUPPORTED
+            api.fe_cell_kernels(desc, buf, mv, out)
+        assert e.value.status == L.FE_EUNSUPPORTED, (p, prec)
 
 
 def test_hex_degenerate_cell_reports_status():

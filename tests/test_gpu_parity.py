@@ -243,8 +243,9 @@ def test_bad_dof_is_reported():
 
 
 # Entrywise rounding-error bound of the mixed modes (Theorem 4.8 /
-# Corollary 4.10): |A_hat - A| <= (k_s u_s + (n_d^2 + n_q) u_q) M with
-# M = sum_s sum_t |B_s|^T |C_st| |B_t|, assembled.  k_s counts the roundings
+# Corollary 4.10): |A_hat - A| <= (k_s u_s + (n_d^2 + n_q) u_q) M + M_g with
+# M = sum_s sum_t |B_s|^T |C_st| |B_t|, assembled, and M_g the geometry term
+# (the FP64 geometry's own rounding error in place of |C_st|).  k_s counts the roundings
 # at the storage precision: B and H (k_s = 2), plus, when H is formed in half
 # arithmetic from a half weighted table and half geometry factors, those two
 # roundings and the three rounded steps of the sum over t (k_s = 7).
@@ -253,9 +254,24 @@ U_S = {"fp16": (7, 2.0 ** -11), "bf16": (2, 2.0 ** -8), "split": (2, 2.0 ** -22)
 U_Q = 2.0 ** -24
 
 
-def _cell_bound(B, w, z, G, i):
+U_G = 2.0 ** -53
+
+
+def _geometry_abs(x, form):
+    """(|G|, dG) of one cell: the geometry tensor and the rounding error of
+    its FP64 evaluation (the u_g term of Corollary 4.10), every entry of G
+    off by at most a few u_g kappa(J) max|G| -- so that entries of G that are
+    exactly zero (cells aligned with the axes) still get an absolute bound."""
+    J, det, Ji, G = oracle.geometry(x)
+    if form == "mass":
+        return np.array([[abs(det)]]), np.array([[8 * U_G * abs(det)]])
+    kappa = np.linalg.norm(J) * np.linalg.norm(Ji)
+    return np.abs(G), np.full(G.shape, 16 * U_G * kappa * np.abs(G).max())
+
+
+def _cell_bound(B, w, z, Gabs, i):
     """sum_s sum_t sum_q |B_s(q, i)| w_q |z_q| |G_st| |B_t(q, :)| of one cell."""
-    left = np.abs(G) @ np.abs(B[:, :, i])                      # [t][q]
+    left = Gabs @ np.abs(B[:, :, i])                           # [t][q]
     return np.einsum("tq,tqj->j", left * (w * z)[None, :], np.abs(B))
 
 
@@ -263,8 +279,9 @@ _BOUND = {}
 
 
 def _bound_csr(mesh, form, q, coeff):
-    """M = sum_K L_K (sum_s sum_t |B_s|^T |C_st| |B_t|) L_K^T in CSR order
-    (the oracle's pattern), for the entrywise bound of the mixed modes."""
+    """(M, M_g): M = sum_K L_K (sum_s sum_t |B_s|^T |C_st| |B_t|) L_K^T in CSR
+    order (the oracle's pattern), and M_g the same sum with |C_st| replaced by
+    the geometry rounding error, for the entrywise bound of the mixed modes."""
     key = (id(mesh), form, q, coeff is not None)
     if key not in _BOUND:
         _BOUND[key] = _bound_csr_uncached(mesh, form, q, coeff)
@@ -275,14 +292,15 @@ def _bound_csr_uncached(mesh, form, q, coeff):
     _, w, vals, grads = oracle.tabulation(mesh.d, mesh.degree, q)
     B = vals[None] if form == "mass" else grads
     Ml = np.zeros((mesh.n_cells, mesh.n_phi, mesh.n_phi))
+    Mg = np.zeros_like(Ml)
     for K in range(mesh.n_cells):
-        _, det, _, G = oracle.geometry(mesh.cell_coords[K])
-        if form == "mass":
-            G = np.array([[abs(det)]])
+        Gabs, dG = _geometry_abs(mesh.cell_coords[K], form)
         z = np.abs(vals @ coeff[mesh.dofmap[K]]) if coeff is not None else np.ones(len(w))
         for i in range(mesh.n_phi):
-            Ml[K, i] = _cell_bound(B, w, z, G, i)
-    return oracle.assemble(mesh.dofmap, Ml, mesh.n_dofs)[2]
+            Ml[K, i] = _cell_bound(B, w, z, Gabs, i)
+            Mg[K, i] = _cell_bound(B, w, z, dG, i)
+    return (oracle.assemble(mesh.dofmap, Ml, mesh.n_dofs)[2],
+            oracle.assemble(mesh.dofmap, Mg, mesh.n_dofs)[2])
 
 
 def _entrywise_ratio(mesh, form, q, coeff, prec, got, ref):
@@ -291,28 +309,29 @@ def _entrywise_ratio(mesh, form, q, coeff, prec, got, ref):
     k_s, u_s = U_S[prec]
     nd = 1 if form == "mass" else mesh.d
     n_q = len(oracle.tabulation(mesh.d, mesh.degree, q)[1])
-    bound = (k_s * u_s + (nd * nd + n_q) * U_Q) * _bound_csr(mesh, form, q, coeff)
+    M, Mg = _bound_csr(mesh, form, q, coeff)
+    bound = (k_s * u_s + (nd * nd + n_q) * U_Q) * M + Mg
     err = np.abs(got - ref)
     return float(np.where(bound > 0, err / np.where(bound > 0, bound, 1.0),
                           np.where(err > 0, np.inf, 0.0)).max())
 
 
 def _row_bound(mesh, form, q, coeff, g, cells, cols):
-    """M restricted to CSR row g, ordered like cols."""
+    """(M, M_g) restricted to CSR row g, ordered like cols."""
     _, w, vals, grads = oracle.tabulation(mesh.d, mesh.degree, q)
     B = vals[None] if form == "mass" else grads                 # [s][q][k]
-    M = {}
+    M, Mg = {}, {}
     for K in cells:
-        _, det, _, G = oracle.geometry(mesh.cell_coords[K])
-        if form == "mass":
-            G = np.array([[abs(det)]])
+        Gabs, dG = _geometry_abs(mesh.cell_coords[K], form)
         z = np.abs(vals @ coeff[mesh.dofmap[K]]) if coeff is not None else np.ones(len(w))
         i = int(np.nonzero(mesh.dofmap[K] == g)[0][0])
-        Mi = _cell_bound(B, w, z, G, i)
+        Mi = _cell_bound(B, w, z, Gabs, i)
+        Mgi = _cell_bound(B, w, z, dG, i)
         for j in range(mesh.n_phi):
             h = int(mesh.dofmap[K, j])
             M[h] = M.get(h, 0.0) + Mi[j]
-    return np.array([M[h] for h in cols])
+            Mg[h] = Mg.get(h, 0.0) + Mgi[j]
+    return np.array([M[h] for h in cols]), np.array([Mg[h] for h in cols])
 
 
 def _sampled_rows_check(mesh, forms, prec, q, coeff, rows, asm, vals):
@@ -343,7 +362,8 @@ def _sampled_rows_check(mesh, forms, prec, q, coeff, rows, asm, vals):
                 k_s, u_s = U_S[prec]
                 nd = 1 if f == "mass" else mesh.d
                 n_q = len(oracle.tabulation(mesh.d, mesh.degree, q)[1])
-                bound = (k_s * u_s + (nd * nd + n_q) * U_Q) * _row_bound(mesh, f, q, coeff, g, cells, cols)
+                M, Mg = _row_bound(mesh, f, q, coeff, g, cells, cols)
+                bound = (k_s * u_s + (nd * nd + n_q) * U_Q) * M + Mg
                 err = np.abs(got - r)
                 # an entry whose bound is zero (no nonzero terms) must be exact
                 ratio = np.where(bound > 0, err / np.where(bound > 0, bound, 1.0),
