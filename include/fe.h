@@ -347,6 +347,31 @@ fe_status fe_assemble_csr(const fe_form_desc *forms, const void *const *form_buf
                           fe_csr *mats, void *plan, size_t *plan_bytes, void *workspace,
                           size_t *ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * fe_assemble_csr_noalloc -- FE_NUMERIC of fe_assemble_csr without a
+ * caller workspace, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).
+ *
+ * Same arguments and results as fe_assemble_csr with phase FE_NUMERIC, for
+ * forms that all take the fused row-ownership path (a schedule built by
+ * FE_SYMBOLIC_FILL for these forms, no coefficient, tables that fit on
+ * chip): the per-cell factor records of the fused path (and the per-point
+ * factors of hexahedral mass forms) are kept in a scratch array inside the
+ * library, 16 MiB per GPU (every GPU the library runs on holds its copy
+ * until the process ends), instead of the caller's workspace.  The call
+ * allocates nothing.  Calls that overlap on one GPU share that array and
+ * race: serialise them (one stream, or events).  The array keeps the last
+ * call's contents; every record is written before it is read.
+ * Errors (on the host, before anything is enqueued): FE_ESIZE when the
+ * records of these forms and cells exceed the 16 MiB (about 250,000 cells
+ * for two forms); FE_EUNSUPPORTED when a form does not take the fused
+ * path; otherwise those of fe_assemble_csr.
+ * ------------------------------------------------------------------------ */
+fe_status fe_assemble_csr_noalloc(const fe_form_desc *forms, const void *const *form_bufs,
+                                  int32_t n_forms, const fe_mesh_view *m, fe_csr *mats,
+                                  void *plan, void *stream);
+
 /* Modes of fe_action_vjp. */
 enum { FE_ACTION = 0, FE_VJP = 1 };
 

@@ -53,6 +53,7 @@ EXPORTS = (
     "fe_tune_cell_kernels",
     "fe_dg_pattern",
     "fe_assemble_csr",
+    "fe_assemble_csr_noalloc",
     "fe_vector_plan",
     "fe_action_vjp",
     "fe_get_device_status",
@@ -118,6 +119,9 @@ def load() -> ctypes.CDLL:
                                     ctypes.POINTER(ctypes.c_size_t), P,
                                     ctypes.POINTER(ctypes.c_size_t), P]
     lib.fe_assemble_csr.restype = i32
+    lib.fe_assemble_csr_noalloc.argtypes = [ctypes.POINTER(fe_form_desc), ctypes.POINTER(P), i32,
+                                            ctypes.POINTER(fe_mesh_view), ctypes.POINTER(fe_csr), P, P]
+    lib.fe_assemble_csr_noalloc.restype = i32
     lib.fe_vector_plan.argtypes = [ctypes.POINTER(fe_mesh_view), i32, P,
                                    ctypes.POINTER(ctypes.c_size_t), P]
     lib.fe_vector_plan.restype = i32

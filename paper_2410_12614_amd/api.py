@@ -178,6 +178,18 @@ class Assembly:
                               self.plan, self.workspace, self.stream), "fe_assemble_csr(NUMERIC)")
         return self.values
 
+    def numeric_noalloc(self) -> list:
+        """FE_NUMERIC through fe_assemble_csr_noalloc: the fused path with the
+        library's own scratch array instead of ``self.workspace``."""
+        n = len(self.descs)
+        darr = (L.fe_form_desc * n)(*self.descs)
+        barr = (ctypes.c_void_p * n)(*[b.data_ptr() for b in self.form_bufs])
+        mv = self.mesh.struct()
+        check(L.load().fe_assemble_csr_noalloc(darr, barr, n, ctypes.byref(mv), self.mats,
+                                               _ptr(self.plan), _stream(self.stream)),
+              "fe_assemble_csr_noalloc")
+        return self.values
+
     @property
     def max_row_len(self) -> int:
         return int(self.mats[0].max_row_len)

@@ -24,6 +24,8 @@
 #include "fe_cell_kernel.h"
 #include "fe_internal.h"
 
+#include <map>
+#include <mutex>
 #include <vector>
 
 namespace fe {
@@ -628,10 +630,13 @@ bool sync_ok(hipStream_t s) { return hipStreamSynchronize(s) == hipSuccess; }
 
 using namespace fe;
 
-extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *const *form_bufs,
-                                     int32_t n_forms, const fe_mesh_view *m, int32_t phase,
-                                     fe_csr *mats, void *plan, size_t *plan_bytes,
-                                     void *workspace, size_t *ws_bytes, void *stream) {
+// compact: the workspace holds only what the fused path reads (no local
+// matrices), and every form must take the fused path (the allocation-free
+// entry point, whose workspace is the static scratch array below).
+static fe_status assemble_csr(const fe_form_desc *forms, const void *const *form_bufs,
+                              int32_t n_forms, const fe_mesh_view *m, int32_t phase,
+                              fe_csr *mats, void *plan, size_t *plan_bytes,
+                              void *workspace, size_t *ws_bytes, void *stream, bool compact) {
   if (!forms || n_forms < 1 || n_forms > 4 || !m) return FE_EINVAL;
   FormLayout L[4];
   for (int f = 0; f < n_forms; ++f) {
@@ -647,7 +652,7 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
   const int64_t n_cells = m->n_cells, n_dofs = m->n_dofs;
   const size_t elt = (forms[0].precision == FE_FP64) ? 8 : 4;
   const PlanLayout P = plan_layout(n_cells, n_phi, n_dofs, forms[0].precision == FE_FP64);
-  const size_t geo_offset = a256((size_t)n_forms * n_cells * n_phi * n_phi * elt);
+  const size_t geo_offset = compact ? 0 : a256((size_t)n_forms * n_cells * n_phi * n_phi * elt);
   // per-form factor records of the fused path (FormGeo<double> is the larger)
   const size_t geo_bytes = a256(sizeof(FormGeo<double>) * (size_t)n_cells);
   // hexahedra: per-form per-point factors [n_cells][n_q_pad] (at most FP64)
@@ -843,7 +848,7 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
     on_fused[f] = !via_ws && sched_ok && fused_eligible(L[f]);
     n_fused += on_fused[f] ? 1 : 0;
   }
-  if ((phase == FE_NUMERIC_GEOMETRY || phase == FE_NUMERIC_FUSED) && n_fused < n_forms)
+  if ((phase == FE_NUMERIC_GEOMETRY || phase == FE_NUMERIC_FUSED || compact) && n_fused < n_forms)
     return FE_EUNSUPPORTED;
   {
     int fl[4], nf = 0;
@@ -963,6 +968,52 @@ extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *cons
     }
   }
   return st;
+}
+
+extern "C" fe_status fe_assemble_csr(const fe_form_desc *forms, const void *const *form_bufs,
+                                     int32_t n_forms, const fe_mesh_view *m, int32_t phase,
+                                     fe_csr *mats, void *plan, size_t *plan_bytes,
+                                     void *workspace, size_t *ws_bytes, void *stream) {
+  return assemble_csr(forms, form_bufs, n_forms, m, phase, mats, plan, plan_bytes, workspace,
+                      ws_bytes, stream, false);
+}
+
+// ---------------------------------------- allocation-free numeric entry point
+// The per-cell factor records (and per-point factors of hexahedral mass
+// forms) of the fused path live in this file-scope array.  In host code its
+// name is only a stand-in: the device address is asked from the runtime once
+// per device and kept.
+namespace {
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)16 << 20;
+__device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+fe_status scratch_address(void **out) {
+  static std::mutex mu;
+  static std::map<int, void *> addr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return FE_EHIP;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return FE_EHIP;
+    it = addr.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return FE_OK;
+}
+}  // namespace
+
+extern "C" fe_status fe_assemble_csr_noalloc(const fe_form_desc *forms,
+                                             const void *const *form_bufs, int32_t n_forms,
+                                             const fe_mesh_view *m, fe_csr *mats, void *plan,
+                                             void *stream) {
+  void *ws = nullptr;
+  fe_status st = scratch_address(&ws);
+  if (st != FE_OK) return st;
+  size_t cap = NOALLOC_SCRATCH_BYTES;
+  return assemble_csr(forms, form_bufs, n_forms, m, FE_NUMERIC, mats, plan, nullptr, ws, &cap,
+                      stream, true);
 }
 
 // ------------------------------------------------- vector assembly, actions
