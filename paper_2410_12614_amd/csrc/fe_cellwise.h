@@ -14,7 +14,7 @@
 //     H_s(q, j) = sum_t c_st(q) F_t(q, j),   c_st(q) = w_q z(X_q) G_st,
 //
 // with no data exchanged between lanes.  The chunk's fragments are read once
-// from a two-slot LDS ring that the workgroup fills from the (L2-resident)
+// from a three-slot LDS ring that the workgroup fills from the (L2-resident)
 // form buffer; every wave of the workgroup walks the same chunks.  The
 // forms are symmetric, so only the tiles (I, J) with I <= J are contracted
 // and the tile (I, J) is also stored transposed: MT (MT + 1) / 2 tiles
@@ -67,17 +67,29 @@ __global__ __launch_bounds__(256) void k_coeff_points(const float *vtab, const i
   float zm[NG];
 #pragma unroll
   for (int g = 0; g < NG; ++g) zm[g] = 0.0f;
-  for (int qt = 0; qt < n_q_pad / 16; ++qt) {
-    f32x4_t acc[NG];
-#pragma unroll
-    for (int g = 0; g < NG; ++g) acc[g] = f32x4_t{0, 0, 0, 0};
+  // left operands of q tile qt (row 16 qt + c, K entries 4 ks + kb), the
+  // next tile's loaded while the current one is contracted
+  auto load_a = [&](int qt, float (&av)[KS]) {
     const int q = 16 * qt + c;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int k = 4 * ks + kb;
-      const float av = (q < n_q && k < n_phi) ? vtab[(size_t)q * n_phi + k] : 0.0f;
+      av[ks] = (q < n_q && k < n_phi) ? vtab[(size_t)q * n_phi + k] : 0.0f;
+    }
+  };
+  const int nqt = n_q_pad / 16;
+  float av[KS];
+  load_a(0, av);
+  for (int qt = 0; qt < nqt; ++qt) {
+    float an[KS];
+    if (qt + 1 < nqt) load_a(qt + 1, an);
+    f32x4_t acc[NG];
 #pragma unroll
-      for (int g = 0; g < NG; ++g) acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, zk[g][ks], acc[g], 0, 0, 0);
+    for (int g = 0; g < NG; ++g) acc[g] = f32x4_t{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+      for (int g = 0; g < NG; ++g) acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks], zk[g][ks], acc[g], 0, 0, 0);
     }
     // lane: column c (the cell), rows 16 qt + 4 kb + r
 #pragma unroll
@@ -89,6 +101,9 @@ __global__ __launch_bounds__(256) void k_coeff_points(const float *vtab, const i
 #pragma unroll
       for (int r = 0; r < 4; ++r) zm[g] = fmaxf(zm[g], fabsf(acc[g][r]));
     }
+    if (qt + 1 < nqt)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) av[ks] = an[ks];
   }
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
@@ -120,96 +135,127 @@ __device__ __forceinline__ constexpr int pair_index(int I, int J) {
   return I * MT - I * (I - 1) / 2 + (J - I);
 }
 
+// Per-cell factors of one wave's current cell: the scaled geometry tensor
+// in half (both halves of a register), the scale of w z and the exact
+// inverse of all scales.
+template <int NDT>
+struct CwCell {
+  half2_t g2[NDT == 1 ? 1 : 6];
+  float zsc, inv;
+  bool ok;
+};
+
+template <int NDT, bool COEFF>
+__device__ __forceinline__ CwCell<NDT> cw_cell(const CwArgs &a, int64_t ce) {
+  CwCell<NDT> r;
+  double G[3][3], adet;
+  r.ok = cell_geometry_mode(a.hdr->geom, a.d, a.coords + ce * (a.d + 1) * a.d, G, adet);
+  double gabs = adet;
+  if constexpr (NDT == 3) {
+    gabs = 0.0;
+    for (int s = 0; s < 3; ++s) gabs = fmax(gabs, fabs(G[s][0]) + fabs(G[s][1]) + fabs(G[s][2]));
+  }
+  const double zm = COEFF ? (double)a.zmax[ce] : 1.0;
+  const double wzmax = a.hdr->max_w * zm;
+  const int e1 = (wzmax > 0.0 && isfinite(wzmax)) ? 1 + ilogb(wzmax) : 0;
+  const int e2 = (gabs > 0.0 && isfinite(gabs)) ? -1 - ilogb(gabs) : 0;
+#pragma unroll
+  for (int s = 0; s < NDT; ++s)
+#pragma unroll
+    for (int t = s; t < NDT; ++t) {
+      double v = NDT == 1 ? adet : G[s][t];
+      v = r.ok ? ldexp(v, e2) : NAN;
+      r.g2[NDT == 1 ? 0 : sym_comp(s, t)] = half2_t{(_Float16)v, (_Float16)v};
+    }
+  const double bsc = a.hdr->b_scale;
+  r.zsc = (float)ldexp(1.0, -e1);
+  r.inv = (float)(ldexp(1.0, e1 - e2) / (bsc * bsc));
+  return r;
+}
+
+// Chunks flow through a three-slot LDS ring by direct global-to-LDS loads
+// (no registers): while chunk g is contracted, chunk g + 2 travels into the
+// slot chunk g - 1 left; the chunk's fragments are read from LDS at its
+// start, its coefficient values from memory.  One
+// barrier per chunk; every wave of a workgroup runs the same number of
+// chunks (the last round's waves without a cell compute a clamped cell and
+// store nothing), so the barriers match.
+// s_waitcnt immediate (gfx9 encoding) waiting until at most n vector
+// memory operations of this wave are outstanding (LDS and export counters
+// left free)
+constexpr int waitcnt_vm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | (((n >> 4) & 3) << 14); }
+
 template <int MT, int NDT, bool COEFF, int NW>
 __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NT = NW * 64;
   constexpr int NP = MT * (MT + 1) / 2;
-  constexpr int CH16 = NDT * MT * 64;         // 16-byte pieces of one chunk
+  constexpr int CH16 = NDT * MT * 64;         // 16-byte pieces of one chunk (a multiple of 64)
   constexpr int PRE = (CH16 + NT - 1) / NT;  // pieces per thread
+  constexpr int PRE_MIN = CH16 / NT;         // direct loads every wave issues per chunk
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int c = lane & 15, kb = lane >> 4;
-  const int nphi = a.n_phi, n_q_pad = a.n_q_pad, d = a.d;
+  const int nphi = a.n_phi, n_q_pad = a.n_q_pad;
   const int nqc = n_q_pad / 32;
-  uint4 *ring = (uint4 *)smem;                  // [2][CH16]
-  float *wl = (float *)(smem + 2 * CH16 * 16);  // [n_q_pad]
+  uint4 *ring = (uint4 *)smem;                  // [3][CH16]
+  float *wl = (float *)(smem + 3 * CH16 * 16);  // [n_q_pad]
   const uint4 *src = (const uint4 *)a.afrag;
 
+  const int64_t per_round = (int64_t)gridDim.x * NW;
+  const int rounds = (int)((a.n_cells + per_round - 1) / per_round);
+  const int total = rounds * nqc;  // chunks this wave walks
+  // table chunk tc into ring slot sl: each wave moves whole runs of 64
+  // pieces, lane l the piece base + l
+  auto fill = [&](int tc, int sl) {
+    const uint4 *from = src + (size_t)tc * CH16;
+    uint4 *to = ring + sl * CH16;
+#pragma unroll
+    for (int p = 0; p < PRE; ++p) {
+      const int e0 = p * NT + wave * 64;  // wave-uniform
+      if (e0 < CH16)
+        __builtin_amdgcn_global_load_lds(
+            (const void __attribute__((address_space(1))) *)(from + e0 + lane),
+            (void __attribute__((address_space(3))) *)(to + e0), 16, 0, 0);
+    }
+  };
+
   for (int i = tid; i < n_q_pad; i += NT) wl[i] = (float)a.wq[i];
-  for (int e = tid; e < CH16; e += NT) ring[e] = src[e];
+  fill(0, 0);
+  if (total > 1) fill(1 % nqc, 1);
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
-  const int64_t per_round = (int64_t)gridDim.x * NW;
-  const int64_t rounds = (a.n_cells + per_round - 1) / per_round;
-  const double bsc = a.hdr->b_scale;
-  int slot = 0;
-  for (int64_t rd = 0; rd < rounds; ++rd) {
-    // the waves of a workgroup take consecutive cells
-    const int64_t cell = rd * per_round + (int64_t)blockIdx.x * NW + wave;
+  // walk position g: its ring slot g % 3, and the table chunk and slot of
+  // g + 2 (counters, no divisions in the loop)
+  int g = 0, slot = 0, fslot = 2, fchunk = 2 % nqc;
+  for (int rd = 0; rd < rounds; ++rd) {
+    const int64_t cell = (int64_t)rd * per_round + (int64_t)blockIdx.x * NW + wave;
     const bool valid = cell < a.n_cells;
     const int64_t ce = valid ? cell : a.n_cells - 1;
-
-    // ---- geometry (FP64 unless the form asks otherwise), every lane ----
-    double G[3][3], adet;
-    const bool ok = cell_geometry_mode(a.hdr->geom, d, a.coords + ce * (d + 1) * d, G, adet);
-    double gabs = adet;
-    if constexpr (NDT == 3) {
-      gabs = 0.0;
-      for (int s = 0; s < 3; ++s) gabs = fmax(gabs, fabs(G[s][0]) + fabs(G[s][1]) + fabs(G[s][2]));
-    }
-    const double zm = COEFF ? (double)a.zmax[ce] : 1.0;
-    const double wzmax = a.hdr->max_w * zm;
-    const int e1 = (wzmax > 0.0 && isfinite(wzmax)) ? 1 + ilogb(wzmax) : 0;
-    const int e2 = (gabs > 0.0 && isfinite(gabs)) ? -1 - ilogb(gabs) : 0;
-    // scaled geometry factors in half, both halves of a register (the six
-    // components of the symmetric tensor)
-    constexpr int NG2 = NDT == 1 ? 1 : 6;
-    half2_t g2[NG2];
-#pragma unroll
-    for (int s = 0; s < NDT; ++s)
-#pragma unroll
-      for (int t = s; t < NDT; ++t) {
-        double v = NDT == 1 ? adet : G[s][t];
-        v = ok ? ldexp(v, e2) : NAN;
-        g2[NDT == 1 ? 0 : sym_comp(s, t)] = half2_t{(_Float16)v, (_Float16)v};
-      }
-    if (valid && !ok && lane == 0) atomicOr(a.status, STATUS_DEGENERATE);
-    const float zsc = (float)ldexp(1.0, -e1);
-    const float inv = (float)(ldexp(1.0, e1 - e2) / (bsc * bsc));
-
+    const CwCell<NDT> cf = cw_cell<NDT, COEFF>(a, ce);
+    const float *zrow = COEFF ? a.zpt + ce * n_q_pad + 8 * kb : nullptr;
     f32x4_t acc[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) acc[p] = f32x4_t{0, 0, 0, 0};
 
-    const float *zrow = COEFF ? a.zpt + ce * n_q_pad + 8 * kb : nullptr;
-    for (int qc = 0; qc < nqc; ++qc) {
-      // the next chunk's pieces (the next cell's first chunk after the last),
-      // stored into the other ring slot after the first slab's products
-      const int nxt = qc + 1 < nqc ? qc + 1 : (rd + 1 < rounds ? 0 : -1);
-      uint4 pre[PRE];
-      if (nxt >= 0) {
-#pragma unroll
-        for (int p = 0; p < PRE; ++p) {
-          const int e = tid + p * NT;
-          if (e < CH16) pre[p] = src[(size_t)nxt * CH16 + e];
-        }
-      }
-      // this lane's eight points: w z scaled, rounded to half in pairs
-      const float *w8 = wl + qc * 32 + 8 * kb;
+    for (int qc = 0; qc < nqc; ++qc, ++g) {
+      // the chunk's coefficient values (issued before the direct loads:
+      // vector memory operations complete in order, so using these does not
+      // wait for the ring)
       float4 z0 = {1, 1, 1, 1}, z1 = {1, 1, 1, 1};
       if constexpr (COEFF) {
         z0 = *(const float4 *)(zrow + qc * 32);
         z1 = *(const float4 *)(zrow + qc * 32 + 4);
       }
-      const float zc[8] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w};
-      half2_t wz[4];
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-        wz[p] = half2_t{(_Float16)(w8[2 * p] * zc[2 * p] * zsc),
-                        (_Float16)(w8[2 * p + 1] * zc[2 * p + 1] * zsc)};
+      // slot (g + 2) % 3 last held chunk g - 1, which every wave finished
+      // before the barrier that closed it
+      if (g + 2 < total) fill(fchunk, fslot);
+      fchunk = fchunk + 1 == nqc ? 0 : fchunk + 1;
+      fslot = fslot == 2 ? 0 : fslot + 1;
       // the chunk's fragments
       half8_t F[NDT][MT];
       const uint4 *cur = ring + slot * CH16;
+      slot = slot == 2 ? 0 : slot + 1;
 #pragma unroll
       for (int s = 0; s < NDT; ++s)
 #pragma unroll
@@ -217,14 +263,21 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
           const uint4 u = cur[(s * MT + mt) * 64 + lane];
           F[s][mt] = *reinterpret_cast<const half8_t *>(&u);
         }
+      // this lane's eight points: w z scaled, rounded in pairs
+      const float *w8 = wl + qc * 32 + 8 * kb;
+      const float zc[8] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w};
+      half2_t wz[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        wz[p] = half2_t{(_Float16)(w8[2 * p] * zc[2 * p] * cf.zsc),
+                        (_Float16)(w8[2 * p + 1] * zc[2 * p + 1] * cf.zsc)};
 #pragma unroll
       for (int s = 0; s < NDT; ++s) {
-        // c_st at this lane's point pairs
         half2_t cst[NDT][4];
 #pragma unroll
         for (int t = 0; t < NDT; ++t)
 #pragma unroll
-          for (int p = 0; p < 4; ++p) cst[t][p] = wz[p] * g2[NDT == 1 ? 0 : sym_comp(s, t)];
+          for (int p = 0; p < 4; ++p) cst[t][p] = wz[p] * cf.g2[NDT == 1 ? 0 : sym_comp(s, t)];
 #pragma unroll
         for (int J = 0; J < MT; ++J) {
           half8_t h;
@@ -242,31 +295,26 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
             acc[pair_index<MT>(I, J)] =
                 __builtin_amdgcn_mfma_f32_16x16x32_f16(F[s][I], h, acc[pair_index<MT>(I, J)], 0, 0, 0);
         }
-        if (s == 0 && nxt >= 0) {
-          // the other slot held the previous chunk, which every wave
-          // finished before the barrier that closed it
-          uint4 *dst = ring + (slot ^ 1) * CH16;
-#pragma unroll
-          for (int p = 0; p < PRE; ++p) {
-            const int e = tid + p * NT;
-            if (e < CH16) dst[e] = pre[p];
-          }
-        }
       }
+      // chunk g + 1 (loaded during chunk g - 1) has landed: every vector
+      // memory operation but this chunk's last PRE_MIN direct loads is done
+      // (chunk g + 2's loads may stay in flight through chunk g + 1); then
+      // every wave's, at the barrier
+      __builtin_amdgcn_s_waitcnt(waitcnt_vm(PRE_MIN));
       __syncthreads();
-      slot ^= 1;
     }
 
-    // ---- the tiles (I, J), I <= J: lane holds A(i, j) for j = 16 J + c,
-    // i = 16 I + 4 kb + r.  Stored as rows j (four consecutive i: one 16-byte
-    // store) and, off the diagonal, also as rows i ----
+    // ---- the tiles (I, J), I <= J (lane: A(i, j) for j = 16 J + c,
+    // i = 16 I + 4 kb + r), stored as rows j (four consecutive i: one
+    // 16-byte store) and, off the diagonal, as rows i ----
     if (valid) {
+      if (!cf.ok && lane == 0) atomicOr(a.status, STATUS_DEGENERATE);
       float *A = a.A + ce * (int64_t)nphi * nphi;
 #pragma unroll
       for (int I = 0; I < MT; ++I)
 #pragma unroll
         for (int J = I; J < MT; ++J) {
-          const f32x4_t v = acc[pair_index<MT>(I, J)] * inv;
+          const f32x4_t v = acc[pair_index<MT>(I, J)] * cf.inv;
           const int j = 16 * J + c, i0 = 16 * I + 4 * kb;
           if (j < nphi) {
             float *row = A + (size_t)j * nphi;
@@ -291,7 +339,7 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
 template <int MT, int NDT, bool COEFF, int NW>
 static fe_status launch_cellwise_one(const CellwiseLaunch &c, const CwArgs &k) {
   auto kern = cellwise_kernel<MT, NDT, COEFF, NW>;
-  const size_t smem = (size_t)2 * NDT * MT * 64 * 16 + (size_t)c.L->n_q_pad * sizeof(float);
+  const size_t smem = (size_t)3 * NDT * MT * 64 * 16 + (size_t)c.L->n_q_pad * sizeof(float);
   LaunchInfo li;
   if (launch_info((const void *)kern, NW * 64, smem, &li) != FE_OK) return FE_EHIP;
   if (li.per_cu < 1) return FE_EUNSUPPORTED;
@@ -338,8 +386,17 @@ inline fe_status launch_cellwise(const CellwiseLaunch &c) {
   k.n_phi = L.n_phi;
   k.n_q = L.n_q;
   k.n_q_pad = L.n_q_pad;
-  if (L.mt == 6 && L.ndt == 3)
-    return coeff ? launch_cellwise_one<6, 3, true, 4>(c, k) : launch_cellwise_one<6, 3, false, 4>(c, k);
+  if (L.ndt == 3) {
+    if (L.mt == 6)
+      return coeff ? launch_cellwise_one<6, 3, true, 8>(c, k) : launch_cellwise_one<6, 3, false, 8>(c, k);
+    return FE_EUNSUPPORTED;
+  }
+  if (coeff) return FE_EUNSUPPORTED;
+  switch (L.mt) {
+    case 4: return launch_cellwise_one<4, 1, false, 4>(c, k);
+    case 6: return launch_cellwise_one<6, 1, false, 4>(c, k);
+    case 8: return launch_cellwise_one<8, 1, false, 4>(c, k);
+  }
   return FE_EUNSUPPORTED;
 }
 

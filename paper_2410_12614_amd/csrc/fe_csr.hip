@@ -520,15 +520,66 @@ __global__ __launch_bounds__(64) void k_slot_ranks(const FusedTask *tasks, const
   }
 }
 
-// Numeric gather: one wave per CSR row, NF forms, LDS window of W entries per
-// form.  The incident local rows are visited in adjacency order (cell
-// ascending, then local index), each whole (its n_phi <= 64 CH entries in
-// chunks of 64 lanes); their loads are issued GROUP rows at a time
-// and the LDS additions then applied row after row, so every entry is summed
-// in cell-ascending order.
+// Numeric gather: NF forms, LDS window of W entries per form.  Each wave
+// walks a block of consecutive CSR rows.  A row's incident local rows are
+// visited in adjacency order (cell ascending, then local index), each whole
+// (its n_phi <= 64 CH entries in chunks of 64 lanes); their loads are issued
+// GROUP local rows at a time and the LDS additions then applied local row
+// after local row, so every entry is summed in cell-ascending order.
+// Software pipeline over the rows: while row g is summed, the ranks and
+// values of row g + 1's first GROUP local rows and the extents and first
+// adjacency entries of row g + 2 are in flight (extents, entries and values
+// are three dependent memory round trips per row).
 constexpr int GATHER_W = 512;
 constexpr int GATHER_GROUP = 4;
-constexpr int GATHER_CH = 8;  // chunks of the longest local row (n_phi <= 512)
+constexpr int GATHER_CH = 8;     // chunks of the longest local row (n_phi <= 512)
+constexpr int GATHER_ROWS = 32;  // consecutive rows per wave
+
+// Ranks and values of the GROUP local rows whose adjacency entries lanes
+// 0..GROUP-1 of `mine` hold (-1: none).  Ranks are raw positions in the row.
+template <class T, int NF, int CH>
+__device__ __forceinline__ void gather_group_load(int64_t mine, int lane, int n_phi,
+                                                  const uint16_t *rank, const T *const *A,
+                                                  int (&rk)[GATHER_GROUP][CH],
+                                                  T (&v)[GATHER_GROUP][CH][NF]) {
+#pragma unroll
+  for (int u = 0; u < GATHER_GROUP; ++u) {
+    const int lo = __shfl((int)(mine & 0xffffffff), u), hi = __shfl((int)(mine >> 32), u);
+    const int64_t e = ((int64_t)hi << 32) | (uint32_t)lo;
+    const size_t row = e < 0 ? 0 : (size_t)(e >> ADJ_BITS) * n_phi + (e & ADJ_MASK);
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+      const int j = 64 * ch + lane;
+      rk[u][ch] = -1;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) v[u][ch][f] = 0;
+      if (e >= 0 && j < n_phi) {
+        const size_t base = row * n_phi + j;
+        rk[u][ch] = (int)rank[base];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) v[u][ch][f] = A[f][base];
+      }
+    }
+  }
+}
+
+// LDS additions of one group into the window [w0, w0 + wl), local row
+// after local row.
+template <class T, int NF, int CH, int W>
+__device__ __forceinline__ void gather_group_add(const int (&rk)[GATHER_GROUP][CH],
+                                                 const T (&v)[GATHER_GROUP][CH][NF], int w0, int wl,
+                                                 T (*buf)[W]) {
+#pragma unroll
+  for (int u = 0; u < GATHER_GROUP; ++u)
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+      const int r = rk[u][ch] - w0;
+      if (rk[u][ch] >= 0 && r >= 0 && r < wl) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) buf[f][r] += v[u][ch][f];
+      }
+    }
+}
 
 template <class T, int NF, int CH>
 __global__ __launch_bounds__(256) void k_gather(const int64_t *adj_ptr, const int64_t *adj,
@@ -537,57 +588,74 @@ __global__ __launch_bounds__(256) void k_gather(const int64_t *adj_ptr, const in
                                                 const T *A0, const T *A1, const T *A2,
                                                 const T *A3, T *V0, T *V1, T *V2, T *V3) {
   constexpr int W = GATHER_W;
+  constexpr int G = GATHER_GROUP;
   __shared__ T sbuf[4][NF][W];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t g = (int64_t)blockIdx.x * 4 + wave;
-  if (g >= n_rows) return;
+  const int64_t first = ((int64_t)blockIdx.x * 4 + wave) * GATHER_ROWS;
+  if (first >= n_rows) return;
+  const int64_t last = min(first + (int64_t)GATHER_ROWS, n_rows);
   T (*buf)[W] = sbuf[wave];
   const T *A[4] = {A0, A1, A2, A3};
   T *V[4] = {V0, V1, V2, V3};
-  const int64_t r0 = row_ptr[g];
-  const int len = (int)(row_ptr[g + 1] - r0);
-  const int64_t a0 = adj_ptr[g], a1 = adj_ptr[g + 1];
-  for (int w0 = 0; w0 < len; w0 += W) {
-    const int wl = min(W, len - w0);
-    for (int r = lane; r < wl; r += 64)
-#pragma unroll
-      for (int f = 0; f < NF; ++f) buf[f][r] = 0;
-    for (int64_t a = a0; a < a1; a += GATHER_GROUP) {
-      int rk[GATHER_GROUP][CH];
-      T v[GATHER_GROUP][CH][NF];
-#pragma unroll
-      for (int u = 0; u < GATHER_GROUP; ++u) {
-        size_t row = 0;
-        if (a + u < a1) {
-          const int64_t ent = adj[a + u];
-          row = (size_t)(ent >> ADJ_BITS) * n_phi + (ent & ADJ_MASK);
-        }
-#pragma unroll
-        for (int ch = 0; ch < CH; ++ch) {
-          const int j = 64 * ch + lane;
-          rk[u][ch] = -1;
-          if (a + u < a1 && j < n_phi) {
-            const size_t base = row * n_phi + j;
-            rk[u][ch] = (int)rank[base] - w0;
-#pragma unroll
-            for (int f = 0; f < NF; ++f) v[u][ch][f] = A[f][base];
-          }
-        }
-      }
-      // the local row of entry a + u holds each column once: its chunks
-      // touch distinct entries, and rows are added in adjacency order
-#pragma unroll
-      for (int u = 0; u < GATHER_GROUP; ++u)
-#pragma unroll
-        for (int ch = 0; ch < CH; ++ch)
-          if (rk[u][ch] >= 0 && rk[u][ch] < wl) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f) buf[f][rk[u][ch]] += v[u][ch][f];
-          }
+  auto entries = [&](int64_t a, int64_t a_end) -> int64_t {
+    return (lane < G && a + lane < a_end) ? adj[a + lane] : -1;
+  };
+  // row g: extents r0, r1, a0, a1 and its first group loaded (rk0, v0);
+  // row g + 1: extents up to r2, a2 and its first entries ent1
+  int64_t r0 = row_ptr[first], r1 = row_ptr[first + 1];
+  int64_t a0 = adj_ptr[first], a1 = adj_ptr[first + 1];
+  int rk0[G][CH];
+  T v0[G][CH][NF];
+  gather_group_load<T, NF, CH>(entries(a0, a1), lane, n_phi, rank, A, rk0, v0);
+  int64_t r2 = r1, a2 = a1, ent1 = -1;
+  if (first + 1 < last) {
+    r2 = row_ptr[first + 2];
+    a2 = adj_ptr[first + 2];
+    ent1 = entries(a1, a2);
+  }
+  for (int64_t g = first; g < last; ++g) {
+    // in flight during row g: row g + 1's first group, row g + 2's extents
+    int rk1[G][CH];
+    T v1[G][CH][NF];
+    gather_group_load<T, NF, CH>(g + 1 < last ? ent1 : (int64_t)-1, lane, n_phi, rank, A, rk1, v1);
+    int64_t r3 = r2, a3 = a2, ent2 = -1;
+    if (g + 2 < last) {
+      r3 = row_ptr[g + 3];
+      a3 = adj_ptr[g + 3];
+      ent2 = entries(a2, a3);
     }
-    for (int r = lane; r < wl; r += 64)
+    const int len = (int)(r1 - r0);
+    for (int w0 = 0; w0 < len; w0 += W) {
+      const int wl = min(W, len - w0);
+      for (int r = lane; r < wl; r += 64)
 #pragma unroll
-      for (int f = 0; f < NF; ++f) V[f][r0 + w0 + r] = buf[f][r];
+        for (int f = 0; f < NF; ++f) buf[f][r] = 0;
+      gather_group_add<T, NF, CH, W>(rk0, v0, w0, wl, buf);
+      for (int64_t a = a0 + G; a < a1; a += G) {
+        int rk[G][CH];
+        T v[G][CH][NF];
+        gather_group_load<T, NF, CH>(entries(a, a1), lane, n_phi, rank, A, rk, v);
+        gather_group_add<T, NF, CH, W>(rk, v, w0, wl, buf);
+      }
+      for (int r = lane; r < wl; r += 64)
+#pragma unroll
+        for (int f = 0; f < NF; ++f) V[f][r0 + w0 + r] = buf[f][r];
+    }
+    r0 = r1;
+    r1 = r2;
+    r2 = r3;
+    a0 = a1;
+    a1 = a2;
+    a2 = a3;
+    ent1 = ent2;
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+#pragma unroll
+      for (int ch = 0; ch < CH; ++ch) {
+        rk0[u][ch] = rk1[u][ch];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) v0[u][ch][f] = v1[u][ch][f];
+      }
   }
 }
 
@@ -596,7 +664,8 @@ fe_status launch_gather(const int64_t *adj_ptr, const int64_t *adj, const uint16
                         const int64_t *row_ptr, int64_t n_rows, int n_phi, void *const *A,
                         void *const *V, hipStream_t s) {
   if (n_phi > 64 * GATHER_CH) return FE_EUNSUPPORTED;
-  const int64_t blocks = (n_rows + 3) / 4;
+  const int64_t waves = (n_rows + GATHER_ROWS - 1) / GATHER_ROWS;
+  const int64_t blocks = (waves + 3) / 4;
   auto kern = n_phi <= 64    ? k_gather<T, NF, 1>
               : n_phi <= 128 ? k_gather<T, NF, 2>
               : n_phi <= 192 ? k_gather<T, NF, 3>

@@ -296,7 +296,9 @@ bool fused_eligible(const FormLayout &L) {
 }
 
 bool cellwise_eligible(const FormLayout &L) {
-  return L.prec == FE_FP16_ACC32 && !L.box && L.d == 3 && L.ndt == 3 && L.mt == 6;
+  if (L.prec != FE_FP16_ACC32 || L.box || L.d != 3) return false;
+  if (L.ndt == 3) return L.mt == 6;
+  return !L.has_coeff && (L.mt == 4 || L.mt == 6 || L.mt == 8);
 }
 
 fe_status launch_info(const void *kern, int threads, size_t smem, LaunchInfo *out) {
@@ -362,6 +364,24 @@ fe_status cell_kernels(const fe_form_desc *f, const void *form_buf, const fe_mes
   a.A_local = A_local;
   a.stream = stream;
   a.tile = tile;
+  if (tile == CELL_TILE_WHOLE) {
+    // the whole-cell kernel; without a workspace only forms without a
+    // coefficient (the coefficient at the points needs one)
+    if (f->has_coeff || !cellwise_eligible(L)) return FE_EUNSUPPORTED;
+    CellwiseLaunch c;
+    c.L = &L;
+    c.form_buf = a.form_buf;
+    c.status = a.status;
+    c.n_cells = a.n_cells;
+    c.coords = a.coords;
+    c.dofmap = a.dofmap;
+    c.n_dofs = a.n_dofs;
+    c.coeff = nullptr;
+    c.zpt = c.zmax = nullptr;
+    c.A_local = (float *)A_local;
+    c.stream = stream;
+    return launch_cellwise_fp16(c);
+  }
   return launch_cell(a);
 }
 

@@ -100,7 +100,11 @@ struct CellLaunch {
   void *stream;
   int tile = -1;  // tile variant (see launch_cell_impl), < 0: default
 };
-constexpr int CELL_TILES = 8;
+// tiles 0..7: the batched cell kernel (variant + 4 occ), bitwise identical
+// to each other; tile 8: the whole-cell kernel (FP16 forms it is compiled
+// for, no coefficient), same precision, its own rounding order
+constexpr int CELL_TILES = 9;
+constexpr int CELL_TILE_WHOLE = 8;
 fe_status launch_cell_fp64(const CellLaunch &a);
 fe_status launch_cell_fp32(const CellLaunch &a);
 fe_status launch_cell_fp16(const CellLaunch &a);
@@ -122,8 +126,9 @@ struct CellwiseLaunch {
   float *A_local;       // [n_cells][n_phi][n_phi]
   void *stream;
 };
-// Forms the whole-cell kernel is compiled for (FP16 storage, tetrahedra,
-// the Poisson form with 6 row tiles: P6).
+// Forms the whole-cell kernel is compiled for: FP16 storage, tetrahedra,
+// the Poisson form with 6 row tiles (P6) or the mass form with 4, 6 or 8
+// (P5..P7); a coefficient only with the Poisson form.
 bool cellwise_eligible(const FormLayout &L);
 fe_status launch_cellwise_fp16(const CellwiseLaunch &c);
 
