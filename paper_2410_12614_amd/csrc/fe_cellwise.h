@@ -32,17 +32,66 @@
 
 namespace fe {
 
+// Per-cell factors of the whole-cell kernel: the scaled geometry tensor in
+// half (both halves of a register), the scale of w z and the exact inverse
+// of all scales.
+template <int NDT>
+struct CwCell {
+  half2_t g2[NDT == 1 ? 1 : 6];
+  float zsc, inv;
+  bool ok;
+};
+
+template <int NDT>
+__device__ __forceinline__ CwCell<NDT> cell_scales(const FormHeader *hdr, int d, const double *xc,
+                                                   double zm) {
+  CwCell<NDT> r;
+  double G[3][3], adet;
+  r.ok = cell_geometry_mode(hdr->geom, d, xc, G, adet);
+  double gabs = adet;
+  if constexpr (NDT == 3) {
+    gabs = 0.0;
+    for (int s = 0; s < 3; ++s) gabs = fmax(gabs, fabs(G[s][0]) + fabs(G[s][1]) + fabs(G[s][2]));
+  }
+  const double wzmax = hdr->max_w * zm;
+  const int e1 = (wzmax > 0.0 && isfinite(wzmax)) ? 1 + ilogb(wzmax) : 0;
+  const int e2 = (gabs > 0.0 && isfinite(gabs)) ? -1 - ilogb(gabs) : 0;
+#pragma unroll
+  for (int s = 0; s < NDT; ++s)
+#pragma unroll
+    for (int t = s; t < NDT; ++t) {
+      double v = NDT == 1 ? adet : G[s][t];
+      v = r.ok ? ldexp(v, e2) : NAN;
+      r.g2[NDT == 1 ? 0 : sym_comp(s, t)] = half2_t{(_Float16)v, (_Float16)v};
+    }
+  const double bsc = hdr->b_scale;
+  r.zsc = (float)ldexp(1.0, -e1);
+  r.inv = (float)(ldexp(1.0, e1 - e2) / (bsc * bsc));
+  return r;
+}
+
+// The factors of a coefficient form's cell as the coefficient pass stores
+// them (two 16-byte words)
+struct CwRec {
+  half2_t g2[6];
+  float zsc, inv;
+};
+
 // ---- coefficient at the quadrature points (FE function evaluation) ----
 // z_K(X_q) = sum_k z_{dof(K,k)} phi_k(X_q) for every cell, as a batched
 // product (n_q x n_phi) (n_phi x cells) on the FP32 matrix cores
 // (16 x 16 x 4): each wave takes 16 NG cells along N, the value table
 // phi_k(X_q) is the left operand (rows q).  Writes z [n_cells][n_q_pad]
-// (zero past n_q) and max_q |z_K(X_q)| per cell.
+// (zero past n_q) and max_q |z_K(X_q)| per cell, and then, one lane per
+// cell, the cell's factors for the whole-cell kernel (FP64 geometry, the
+// scales of H; a degenerate cell raises the status flag).
 template <int KS, int NG>
 __global__ __launch_bounds__(256) void k_coeff_points(const float *vtab, const int32_t *dofmap,
                                                       const double *coeff, int64_t n_cells,
                                                       int64_t n_dofs, int n_phi, int n_q, int n_q_pad,
-                                                      float *zpt, float *zmax, int32_t *status) {
+                                                      const FormHeader *hdr, const double *coords,
+                                                      int d, float *zpt, float *zmax, CwRec *rec,
+                                                      int32_t *status) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c = lane & 15, kb = lane >> 4;
   const int64_t cell0 = ((int64_t)blockIdx.x * 4 + wave) * 16 * NG;
@@ -111,7 +160,17 @@ __global__ __launch_bounds__(256) void k_coeff_points(const float *vtab, const i
     m = fmaxf(m, __shfl_xor(m, 16));
     m = fmaxf(m, __shfl_xor(m, 32));
     const int64_t cell = cell0 + 16 * g + c;
-    if (kb == 0 && cell < n_cells) zmax[cell] = m;
+    if (kb == 0 && cell < n_cells) {
+      zmax[cell] = m;
+      const CwCell<3> r = cell_scales<3>(hdr, d, coords + cell * (d + 1) * d, (double)m);
+      CwRec w;
+#pragma unroll
+      for (int e = 0; e < 6; ++e) w.g2[e] = r.g2[e];
+      w.zsc = r.zsc;
+      w.inv = r.inv;
+      rec[cell] = w;
+      if (!r.ok) atomicOr(status, STATUS_DEGENERATE);
+    }
   }
 }
 
@@ -123,6 +182,7 @@ struct CwArgs {
   const double *coords;
   const float *zpt;   // [n_cells][n_q_pad] coefficient at the points, or null (z = 1)
   const float *zmax;  // [n_cells] max_q |z|, or null
+  const CwRec *rec;   // [n_cells] factors from the coefficient pass, or null (computed here)
   float *A;           // [n_cells][n_phi][n_phi]
   int64_t n_cells;
   int d, n_phi, n_q, n_q_pad;
@@ -135,127 +195,171 @@ __device__ __forceinline__ constexpr int pair_index(int I, int J) {
   return I * MT - I * (I - 1) / 2 + (J - I);
 }
 
-// Per-cell factors of one wave's current cell: the scaled geometry tensor
-// in half (both halves of a register), the scale of w z and the exact
-// inverse of all scales.
-template <int NDT>
-struct CwCell {
-  half2_t g2[NDT == 1 ? 1 : 6];
-  float zsc, inv;
-  bool ok;
-};
-
 template <int NDT, bool COEFF>
 __device__ __forceinline__ CwCell<NDT> cw_cell(const CwArgs &a, int64_t ce) {
-  CwCell<NDT> r;
-  double G[3][3], adet;
-  r.ok = cell_geometry_mode(a.hdr->geom, a.d, a.coords + ce * (a.d + 1) * a.d, G, adet);
-  double gabs = adet;
-  if constexpr (NDT == 3) {
-    gabs = 0.0;
-    for (int s = 0; s < 3; ++s) gabs = fmax(gabs, fabs(G[s][0]) + fabs(G[s][1]) + fabs(G[s][2]));
-  }
-  const double zm = COEFF ? (double)a.zmax[ce] : 1.0;
-  const double wzmax = a.hdr->max_w * zm;
-  const int e1 = (wzmax > 0.0 && isfinite(wzmax)) ? 1 + ilogb(wzmax) : 0;
-  const int e2 = (gabs > 0.0 && isfinite(gabs)) ? -1 - ilogb(gabs) : 0;
-#pragma unroll
-  for (int s = 0; s < NDT; ++s)
-#pragma unroll
-    for (int t = s; t < NDT; ++t) {
-      double v = NDT == 1 ? adet : G[s][t];
-      v = r.ok ? ldexp(v, e2) : NAN;
-      r.g2[NDT == 1 ? 0 : sym_comp(s, t)] = half2_t{(_Float16)v, (_Float16)v};
-    }
-  const double bsc = a.hdr->b_scale;
-  r.zsc = (float)ldexp(1.0, -e1);
-  r.inv = (float)(ldexp(1.0, e1 - e2) / (bsc * bsc));
-  return r;
+  return cell_scales<NDT>(a.hdr, a.d, a.coords + ce * (a.d + 1) * a.d, COEFF ? (double)a.zmax[ce] : 1.0);
 }
 
 // Chunks flow through a three-slot LDS ring by direct global-to-LDS loads
 // (no registers): while chunk g is contracted, chunk g + 2 travels into the
 // slot chunk g - 1 left; the chunk's fragments are read from LDS at its
-// start, its coefficient values from memory.  One
-// barrier per chunk; every wave of a workgroup runs the same number of
-// chunks (the last round's waves without a cell compute a clamped cell and
-// store nothing), so the barriers match.
+// start.  One barrier per chunk; every wave of a workgroup runs the same
+// number of chunks (the last round's waves without a cell compute a clamped
+// cell and store nothing), so the barriers match.
+//
+// Waits.  The three slots are separate LDS arrays and every read and direct
+// load names its slot statically (a cell's chunk loop exists in three
+// copies, one per slot of its first chunk, each unrolled by three), so the
+// compiler knows that loads into one slot do not alias reads of another and
+// does not wait for the prefetch before reading the ring.  Every wave
+// issues the same number of direct loads per chunk (PRE: a wave with fewer
+// pieces repeats its previous one, and the last two chunks of the walk load
+// a spare copy of chunk 0 into the free slot), so the counts of vector
+// memory operations are the same on every path.  A coefficient form's cell
+// factors (computed by the coefficient pass) and the coefficient values at
+// all the cell's points (by direct loads into an LDS row of the wave) are
+// loaded while the previous cell's rows are stored.  The explicit wait
+// closing a chunk (at most the PRE direct loads just issued outstanding)
+// covers the loads of the next chunk, and the barrier after it is a bare
+// s_barrier (the workgroup-scope fence of __syncthreads() would wait for
+// the prefetch as well).
+//
+// Stores.  The rows of the local matrix leave in blocks of 16 (rows
+// 16 J .. 16 J + 15, contiguous in memory): the tiles (I, J), I <= J, give
+// their columns 16 I .. + 15 directly (lane: rows 16 J + c, four
+// consecutive columns), the tiles (J, I), I > J, transposed (lane: rows
+// 16 J + 4 kb + r, column 16 I + c); both are written into a row block in
+// the wave's LDS, which then goes out in 16-byte pieces, consecutive lanes
+// on consecutive addresses.  n_phi is a multiple of four, so a 16-byte
+// piece is either inside the matrix or not.
 // s_waitcnt immediate (gfx9 encoding) waiting until at most n vector
 // memory operations of this wave are outstanding (LDS and export counters
 // left free)
 constexpr int waitcnt_vm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | (((n >> 4) & 3) << 14); }
 
+// Workgroup barrier without a memory fence (signal fences emit no
+// instruction; they keep the compiler from moving memory operations across)
+__device__ __forceinline__ void bare_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+template <int S>
+using slot_t = std::integral_constant<int, S>;
+
+constexpr int CW_ZMAX = 512;  // points of a coefficient form (n_q_pad) the LDS row holds
+
 template <int MT, int NDT, bool COEFF, int NW>
 __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NT = NW * 64;
   constexpr int NP = MT * (MT + 1) / 2;
   constexpr int CH16 = NDT * MT * 64;         // 16-byte pieces of one chunk (a multiple of 64)
-  constexpr int PRE = (CH16 + NT - 1) / NT;  // pieces per thread
-  constexpr int PRE_MIN = CH16 / NT;         // direct loads every wave issues per chunk
+  constexpr int PRE = (CH16 + NT - 1) / NT;  // direct loads per wave and chunk
+  static_assert(CH16 >= NT, "a chunk covers every thread at least once");
+  __shared__ uint4 ring0[CH16], ring1[CH16], ring2[CH16];
+  __shared__ float4 rbuf[NW][16 * MT * 4];  // a wave's row block (16 rows x n_phi)
+  __shared__ float zbuf[COEFF ? NW : 1][COEFF ? CW_ZMAX : 4];
+  extern __shared__ float wl[];              // quadrature weights [n_q_pad]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int c = lane & 15, kb = lane >> 4;
   const int nphi = a.n_phi, n_q_pad = a.n_q_pad;
   const int nqc = n_q_pad / 32;
-  uint4 *ring = (uint4 *)smem;                  // [3][CH16]
-  float *wl = (float *)(smem + 3 * CH16 * 16);  // [n_q_pad]
   const uint4 *src = (const uint4 *)a.afrag;
+  float *rb = (float *)rbuf[wave];
 
   const int64_t per_round = (int64_t)gridDim.x * NW;
   const int rounds = (int)((a.n_cells + per_round - 1) / per_round);
   const int total = rounds * nqc;  // chunks this wave walks
-  // table chunk tc into ring slot sl: each wave moves whole runs of 64
-  // pieces, lane l the piece base + l
-  auto fill = [&](int tc, int sl) {
+  auto cell_of = [&](int rd) -> int64_t {
+    const int64_t cell = (int64_t)rd * per_round + (int64_t)blockIdx.x * NW + wave;
+    return cell < a.n_cells ? cell : a.n_cells - 1;
+  };
+  // table chunk tc into ring slot S: each wave moves whole runs of 64
+  // pieces, lane l the piece base + l; a run past the chunk repeats the
+  // wave's previous run (same data to the same place)
+  auto fill = [&](int tc, auto sl) {
+    constexpr int S = decltype(sl)::value;
+    uint4 *to = S == 0 ? ring0 : S == 1 ? ring1 : ring2;
     const uint4 *from = src + (size_t)tc * CH16;
-    uint4 *to = ring + sl * CH16;
 #pragma unroll
     for (int p = 0; p < PRE; ++p) {
-      const int e0 = p * NT + wave * 64;  // wave-uniform
-      if (e0 < CH16)
-        __builtin_amdgcn_global_load_lds(
-            (const void __attribute__((address_space(1))) *)(from + e0 + lane),
-            (void __attribute__((address_space(3))) *)(to + e0), 16, 0, 0);
+      int e0 = p * NT + wave * 64;  // wave-uniform
+      if (e0 >= CH16) e0 -= NT;
+      __builtin_amdgcn_global_load_lds(
+          (const void __attribute__((address_space(1))) *)(from + e0 + lane),
+          (void __attribute__((address_space(3))) *)(to + e0), 16, 0, 0);
     }
+  };
+  // coefficient values at all points of cell ce into the wave's LDS row:
+  // CW_ZMAX / 256 direct loads, lanes past the row repeat its last piece
+  // into the unused end of the LDS row
+  auto load_z = [&](int64_t ce) {
+    const uint4 *zr = (const uint4 *)(a.zpt + ce * n_q_pad);
+    const int last = n_q_pad / 4 - 1;
+#pragma unroll
+    for (int p = 0; p < CW_ZMAX / 256; ++p)
+      __builtin_amdgcn_global_load_lds(
+          (const void __attribute__((address_space(1))) *)(zr + min(64 * p + lane, last)),
+          (void __attribute__((address_space(3))) *)((uint4 *)zbuf[wave] + 64 * p), 16, 0, 0);
+  };
+  auto load_rec = [&](int64_t ce, uint4 &r0, uint4 &r1) {
+    const uint4 *rp = (const uint4 *)(a.rec + ce);
+    r0 = rp[0];
+    r1 = rp[1];
   };
 
   for (int i = tid; i < n_q_pad; i += NT) wl[i] = (float)a.wq[i];
-  fill(0, 0);
-  if (total > 1) fill(1 % nqc, 1);
+  fill(0, slot_t<0>());
+  fill(1 % nqc, slot_t<1>());
+  // prefetched: the next cell's factors (and its coefficient values)
+  uint4 rn0 = {0, 0, 0, 0}, rn1 = {0, 0, 0, 0};
+  if constexpr (COEFF) {
+    load_z(cell_of(0));
+    load_rec(cell_of(0), rn0, rn1);
+  }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
-  // walk position g: its ring slot g % 3, and the table chunk and slot of
-  // g + 2 (counters, no divisions in the loop)
-  int g = 0, slot = 0, fslot = 2, fchunk = 2 % nqc;
   for (int rd = 0; rd < rounds; ++rd) {
     const int64_t cell = (int64_t)rd * per_round + (int64_t)blockIdx.x * NW + wave;
     const bool valid = cell < a.n_cells;
     const int64_t ce = valid ? cell : a.n_cells - 1;
-    const CwCell<NDT> cf = cw_cell<NDT, COEFF>(a, ce);
-    const float *zrow = COEFF ? a.zpt + ce * n_q_pad + 8 * kb : nullptr;
+    const int64_t ce_next = cell_of(rd + 1 < rounds ? rd + 1 : rd);
+    CwCell<NDT> cf;
+    if constexpr (COEFF) {
+      CwRec r;
+      *reinterpret_cast<uint4 *>(&r) = rn0;
+      *(reinterpret_cast<uint4 *>(&r) + 1) = rn1;
+#pragma unroll
+      for (int e = 0; e < (NDT == 1 ? 1 : 6); ++e) cf.g2[e] = r.g2[e];
+      cf.zsc = r.zsc;
+      cf.inv = r.inv;
+      cf.ok = true;  // the coefficient pass raised the flag
+    } else {
+      cf = cw_cell<NDT, COEFF>(a, ce);
+    }
     f32x4_t acc[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) acc[p] = f32x4_t{0, 0, 0, 0};
+    const int g0 = rd * nqc;  // walk position of the cell's first chunk
 
-    for (int qc = 0; qc < nqc; ++qc, ++g) {
-      // the chunk's coefficient values (issued before the direct loads:
-      // vector memory operations complete in order, so using these does not
-      // wait for the ring)
-      float4 z0 = {1, 1, 1, 1}, z1 = {1, 1, 1, 1};
-      if constexpr (COEFF) {
-        z0 = *(const float4 *)(zrow + qc * 32);
-        z1 = *(const float4 *)(zrow + qc * 32 + 4);
+    // chunk qc of the cell (walk position g0 + qc) from slot S; chunk
+    // g0 + qc + 2 into slot (S + 2) % 3
+    auto step = [&](int qc, auto sl) {
+      constexpr int S = decltype(sl)::value;
+      const uint4 *cur = S == 0 ? ring0 : S == 1 ? ring1 : ring2;
+      // the direct loads of chunk g + 2 into the slot chunk g - 1 left
+      // (every wave finished that before the barrier that closed it; past
+      // the walk's end a spare copy of chunk 0)
+      {
+        const int g = g0 + qc;
+        int fc = qc + 2;
+        if (fc >= nqc) fc -= nqc;
+        fill(g + 2 < total ? fc : 0, slot_t<(S + 2) % 3>());
       }
-      // slot (g + 2) % 3 last held chunk g - 1, which every wave finished
-      // before the barrier that closed it
-      if (g + 2 < total) fill(fchunk, fslot);
-      fchunk = fchunk + 1 == nqc ? 0 : fchunk + 1;
-      fslot = fslot == 2 ? 0 : fslot + 1;
       // the chunk's fragments
       half8_t F[NDT][MT];
-      const uint4 *cur = ring + slot * CH16;
-      slot = slot == 2 ? 0 : slot + 1;
 #pragma unroll
       for (int s = 0; s < NDT; ++s)
 #pragma unroll
@@ -265,6 +369,11 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
         }
       // this lane's eight points: w z scaled, rounded in pairs
       const float *w8 = wl + qc * 32 + 8 * kb;
+      float4 z0 = {1, 1, 1, 1}, z1 = {1, 1, 1, 1};
+      if constexpr (COEFF) {
+        z0 = *(const float4 *)(zbuf[wave] + qc * 32 + 8 * kb);
+        z1 = *(const float4 *)(zbuf[wave] + qc * 32 + 8 * kb + 4);
+      }
       const float zc[8] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w};
       half2_t wz[4];
 #pragma unroll
@@ -296,42 +405,59 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
                 __builtin_amdgcn_mfma_f32_16x16x32_f16(F[s][I], h, acc[pair_index<MT>(I, J)], 0, 0, 0);
         }
       }
-      // chunk g + 1 (loaded during chunk g - 1) has landed: every vector
-      // memory operation but this chunk's last PRE_MIN direct loads is done
-      // (chunk g + 2's loads may stay in flight through chunk g + 1); then
-      // every wave's, at the barrier
-      __builtin_amdgcn_s_waitcnt(waitcnt_vm(PRE_MIN));
-      __syncthreads();
-    }
+      // chunk g + 1 (loaded during chunk g - 1) and the next coefficient
+      // values have landed: at most the PRE direct loads of chunk g + 2 are
+      // outstanding; then every wave's, at the barrier
+      __builtin_amdgcn_s_waitcnt(waitcnt_vm(PRE));
+      bare_barrier();
+    };
+    // the cell's chunks, slot of chunk qc = (PH + qc) % 3
+    auto chunks = [&](auto ph) {
+      constexpr int PH = decltype(ph)::value;
+      for (int qc = 0; qc < nqc; qc += 3) {
+        step(qc, slot_t<PH>());
+        if (qc + 1 < nqc) step(qc + 1, slot_t<(PH + 1) % 3>());
+        if (qc + 2 < nqc) step(qc + 2, slot_t<(PH + 2) % 3>());
+      }
+    };
+    const int ph = g0 % 3;
+    if (ph == 0) chunks(slot_t<0>());
+    else if (ph == 1) chunks(slot_t<1>());
+    else chunks(slot_t<2>());
 
-    // ---- the tiles (I, J), I <= J (lane: A(i, j) for j = 16 J + c,
-    // i = 16 I + 4 kb + r), stored as rows j (four consecutive i: one
-    // 16-byte store) and, off the diagonal, as rows i ----
+    // the next cell's factors and coefficient values, then this cell's rows
+    if constexpr (COEFF) {
+      load_rec(ce_next, rn0, rn1);
+      load_z(ce_next);
+    }
     if (valid) {
-      if (!cf.ok && lane == 0) atomicOr(a.status, STATUS_DEGENERATE);
-      float *A = a.A + ce * (int64_t)nphi * nphi;
+      if (!COEFF && !cf.ok && lane == 0) atomicOr(a.status, STATUS_DEGENERATE);
+      float *A = a.A + ce * (int64_t)nphi * nphi;  // wave-uniform
 #pragma unroll
-      for (int I = 0; I < MT; ++I)
+      for (int J = 0; J < MT; ++J) {
+        // row block J: rows 16 J + x, x < 16, at rb[x n_phi + col]
 #pragma unroll
-        for (int J = I; J < MT; ++J) {
-          const f32x4_t v = acc[pair_index<MT>(I, J)] * cf.inv;
-          const int j = 16 * J + c, i0 = 16 * I + 4 * kb;
-          if (j < nphi) {
-            float *row = A + (size_t)j * nphi;
-            if (i0 + 3 < nphi) {
-              *(f4u_t *)(row + i0) = f4u_t{v[0], v[1], v[2], v[3]};
-            } else {
+        for (int I = 0; I < MT; ++I) {
+          if (I <= J) {
+            // tile (I, J): lane holds A(16 I + 4 kb + r, 16 J + c) = A(16 J + c, 16 I + 4 kb + r)
+            const f32x4_t v = acc[pair_index<MT>(I, J)] * cf.inv;
+            const int col = 16 * I + 4 * kb;
+            if (col < nphi) *(float4 *)(rb + c * nphi + col) = float4{v[0], v[1], v[2], v[3]};
+          } else {
+            // tile (J, I): lane holds A(16 J + 4 kb + r, 16 I + c)
+            const f32x4_t v = acc[pair_index<MT>(J, I)] * cf.inv;
+            const int col = 16 * I + c;
+            if (col < nphi)
 #pragma unroll
-              for (int r = 0; r < 4; ++r)
-                if (i0 + r < nphi) row[i0 + r] = v[r];
-            }
-            if (I != J) {
-#pragma unroll
-              for (int r = 0; r < 4; ++r)
-                if (i0 + r < nphi) A[(size_t)(i0 + r) * nphi + j] = v[r];
-            }
+              for (int r = 0; r < 4; ++r) rb[(4 * kb + r) * nphi + col] = v[r];
           }
         }
+        // the block's rows (those inside the matrix) are contiguous
+        const int nrow = min(16, nphi - 16 * J);
+        const int n16 = nrow * nphi / 4;
+        float4 *dst = (float4 *)(A + 16 * J * nphi);
+        for (int t = lane; t < n16; t += 64) dst[t] = rbuf[wave][t];
+      }
     }
   }
 }
@@ -339,7 +465,9 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
 template <int MT, int NDT, bool COEFF, int NW>
 static fe_status launch_cellwise_one(const CellwiseLaunch &c, const CwArgs &k) {
   auto kern = cellwise_kernel<MT, NDT, COEFF, NW>;
-  const size_t smem = (size_t)3 * NDT * MT * 64 * 16 + (size_t)c.L->n_q_pad * sizeof(float);
+  // dynamic: the quadrature weights (the ring and the transpose buffers are
+  // static)
+  const size_t smem = (size_t)c.L->n_q_pad * sizeof(float);
   LaunchInfo li;
   if (launch_info((const void *)kern, NW * 64, smem, &li) != FE_OK) return FE_EHIP;
   if (li.per_cu < 1) return FE_EUNSUPPORTED;
@@ -356,7 +484,8 @@ static fe_status launch_coeff_points(const CellwiseLaunch &c) {
   const int64_t waves = (c.n_cells + 16 * NG - 1) / (16 * NG);
   hipLaunchKernelGGL((k_coeff_points<KS, NG>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0,
                      (hipStream_t)c.stream, (const float *)(c.form_buf + L.off_vtab), c.dofmap, c.coeff, c.n_cells,
-                     c.n_dofs, L.n_phi, L.n_q, L.n_q_pad, c.zpt, c.zmax, c.status);
+                     c.n_dofs, L.n_phi, L.n_q, L.n_q_pad, (const FormHeader *)c.form_buf, c.coords, L.d,
+                     c.zpt, c.zmax, (CwRec *)c.rec, c.status);
   return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
 }
 
@@ -366,7 +495,7 @@ inline fe_status launch_cellwise(const CellwiseLaunch &c) {
   if (c.n_cells == 0) return FE_OK;
   const bool coeff = c.coeff != nullptr;
   if (coeff) {
-    if (!c.zpt || !c.zmax) return FE_EINVAL;
+    if (!c.zpt || !c.zmax || !c.rec) return FE_EINVAL;
     const int ks = (L.n_phi + 3) / 4;
     fe_status st = FE_EUNSUPPORTED;
     if (ks == 21) st = launch_coeff_points<21>(c);
@@ -380,6 +509,7 @@ inline fe_status launch_cellwise(const CellwiseLaunch &c) {
   k.coords = c.coords;
   k.zpt = c.zpt;
   k.zmax = c.zmax;
+  k.rec = coeff ? (const CwRec *)c.rec : nullptr;
   k.A = c.A_local;
   k.n_cells = c.n_cells;
   k.d = L.d;

@@ -471,52 +471,22 @@ __global__ __launch_bounds__(256) void k_ranks(const int32_t *dofmap, int64_t n_
 // i.e. local row i = 16 mt + row(kb, r)), the LDS byte offset of the entry
 // inside the owning wave's row buffer: rowoff + rank of dof(K, i) in row
 // dof(K, j), or, for padding rows i >= n_phi, the private slot
-// span + 16 kb + n of that lane.  Bit 15 marks the first contribution
-// to its entry in the order the fused kernel applies them (tile, then
-// round): that one is stored rather than added, so the row buffer needs no
-// clearing.  One workgroup per task.
-constexpr uint16_t SRANK_FIRST = 0x8000;
-
+// span + 16 kb + n of that lane.  One workgroup per task.
 __global__ __launch_bounds__(64) void k_slot_ranks(const FusedTask *tasks, const FusedLane *lanes,
                                                    const uint16_t *rank, int n_phi, int sstride,
                                                    bool f64rows, int elt, int span, uint16_t *srank) {
-  __shared__ int owner[FUSED_SPAN_BOX];
   const FusedTask tk = tasks[blockIdx.x];
   const int nent = tk.nt * 16 * sstride;
-  for (int u = threadIdx.x; u < span; u += 64) owner[u] = 0x7fffffff;
-  __syncthreads();
-  // pass 1: the earliest (tile, round) contributing to every entry
   for (int u = threadIdx.x; u < nent; u += 64) {
     const int slot = u / sstride, e = u - slot * sstride;
     const FusedLane L = lanes[(size_t)tk.t0 * 16 + slot];
     if (L.cell < 0) continue;  // the pairs of a tile fill its first lanes
-    const int mt = e >> 4, kb = (e & 15) >> 2, r = e & 3;
-    const int i = mt * 16 + (f64rows ? kb + 4 * r : 4 * kb + r);
-    if (i < n_phi) {
-      const int pos = L.rowoff + rank[((size_t)L.cell * n_phi + L.j) * n_phi + i];
-      atomicMin(&owner[pos], (slot >> 4) * 16 + (L.round & 15));
-    }
-  }
-  __syncthreads();
-  // pass 2: offsets and first-contribution marks
-  for (int u = threadIdx.x; u < nent; u += 64) {
-    const int slot = u / sstride, e = u - slot * sstride;
-    const FusedLane L = lanes[(size_t)tk.t0 * 16 + slot];
-    if (L.cell < 0) continue;
     const int n = slot & 15, mt = e >> 4, kb = (e & 15) >> 2, r = e & 3;
     const int pair = tk.p0 + ((tk.pre >> (8 * (slot >> 4))) & 0xff) + n;
     const int i = mt * 16 + (f64rows ? kb + 4 * r : 4 * kb + r);
-    int off;
-    bool first;
-    if (i < n_phi) {
-      const int pos = L.rowoff + rank[((size_t)L.cell * n_phi + L.j) * n_phi + i];
-      off = pos;
-      first = owner[pos] == (slot >> 4) * 16 + (L.round & 15);
-    } else {
-      off = span + 16 * kb + n;
-      first = true;
-    }
-    srank[(size_t)pair * sstride + e] = (uint16_t)(off * elt) | (first ? SRANK_FIRST : 0);
+    const int off = i < n_phi ? L.rowoff + rank[((size_t)L.cell * n_phi + L.j) * n_phi + i]
+                              : span + 16 * kb + n;
+    srank[(size_t)pair * sstride + e] = (uint16_t)(off * elt);
   }
 }
 
@@ -730,14 +700,15 @@ static fe_status assemble_csr(const fe_form_desc *forms, const void *const *form
   for (int f = 0; f < n_forms; ++f)
     if (L[f].box) zpt_bytes = std::max(zpt_bytes, a256((size_t)n_cells * L[f].n_q_pad * 8));
   // coefficient forms of the whole-cell kernel: the coefficient at the
-  // points [n_cells][n_q_pad] and its maximum per cell (FP32), one region
+  // points [n_cells][n_q_pad], its maximum per cell (FP32) and the cell
+  // factors (32 bytes per cell), one region
   // shared by those forms (they run one after the other on the stream)
   const size_t zc_offset = zpt_offset + (size_t)n_forms * zpt_bytes;
   size_t zc_bytes = 0, zc_pts = 0;
   for (int f = 0; f < n_forms; ++f)
     if (forms[f].has_coeff && cellwise_eligible(L[f])) {
       zc_pts = std::max(zc_pts, a256((size_t)n_cells * L[f].n_q_pad * sizeof(float)));
-      zc_bytes = zc_pts + a256((size_t)n_cells * sizeof(float));
+      zc_bytes = zc_pts + a256((size_t)n_cells * sizeof(float)) + a256((size_t)n_cells * 32);
     }
   const size_t ws_need = std::max<size_t>(256, zc_offset + zc_bytes);
   const bool numeric = phase == FE_NUMERIC || phase == FE_NUMERIC_GATHER ||
@@ -1011,6 +982,7 @@ static fe_status assemble_csr(const fe_form_desc *forms, const void *const *form
       c.coeff = mv.coeff;
       c.zpt = (float *)((unsigned char *)workspace + zc_offset);
       c.zmax = (float *)((unsigned char *)workspace + zc_offset + zc_pts);
+      c.rec = (unsigned char *)workspace + zc_offset + zc_pts + a256((size_t)n_cells * sizeof(float));
       c.A_local = (float *)Aloc[ng - 1];
       c.stream = stream;
       st = launch_cellwise_fp16(c);

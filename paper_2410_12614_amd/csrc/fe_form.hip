@@ -296,8 +296,8 @@ bool fused_eligible(const FormLayout &L) {
 }
 
 bool cellwise_eligible(const FormLayout &L) {
-  if (L.prec != FE_FP16_ACC32 || L.box || L.d != 3) return false;
-  if (L.ndt == 3) return L.mt == 6;
+  if (L.prec != FE_FP16_ACC32 || L.box || L.d != 3 || L.n_phi % 4 != 0) return false;
+  if (L.ndt == 3) return L.mt == 6 && L.n_q_pad <= 512;
   return !L.has_coeff && (L.mt == 4 || L.mt == 6 || L.mt == 8);
 }
 
@@ -378,6 +378,7 @@ fe_status cell_kernels(const fe_form_desc *f, const void *form_buf, const fe_mes
     c.n_dofs = a.n_dofs;
     c.coeff = nullptr;
     c.zpt = c.zmax = nullptr;
+    c.rec = nullptr;
     c.A_local = (float *)A_local;
     c.stream = stream;
     return launch_cellwise_fp16(c);

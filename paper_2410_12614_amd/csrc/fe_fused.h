@@ -251,12 +251,11 @@ __device__ __forceinline__ void tile_factors(const FormGeo<typename P::real> &cg
 
 // LDS byte offsets (in units of the row-buffer element) of this lane's
 // outputs inside the row buffer, in lane order (four per row tile: one
-// 8-byte load).  Padding rows point at the lane's private slot; bit 15 marks
-// the first contribution to an entry.
+// 8-byte load).  Padding rows point at the lane's private slot.
 template <class T, int MT, int TT>
 __device__ __forceinline__ void tile_addr(const uint16_t *const *rk, int rstride, int span, int lane,
                                           int kb, int (&addr)[TT][MT][4]) {
-  const int dummy = (span * (int)sizeof(T) + lane * (int)sizeof(T)) | 0x8000;
+  const int dummy = span * (int)sizeof(T) + lane * (int)sizeof(T);
 #pragma unroll
   for (int u = 0; u < TT; ++u)
 #pragma unroll
@@ -314,7 +313,10 @@ __device__ __forceinline__ void tile_contract(const FormLds<P> &S, const FusedFo
 #pragma unroll
   for (int u = 0; u < TT; ++u)
     zrow[u] = PZ ? (const HT *)F.zpt + (size_t)zc[u] * F.n_q_pad + kb * KPL : nullptr;
-  for (int qc = 0; qc < nqc; ++qc) {
+  // (a padded rule holds at least one chunk: a loop entered once at least
+  // keeps the compiler from clearing the accumulators twice)
+  int qc = 0;
+  do {
     if constexpr (P::H16) {
       // the chunk's table reads first, then per s its fragments, H and the
       // contraction
@@ -388,7 +390,7 @@ __device__ __forceinline__ void tile_contract(const FormLds<P> &S, const FusedFo
         }
       }
     }
-  }
+  } while (++qc < nqc);
 }
 
 // The tile's results of one accumulator set, unscaled: val = acc (+ 2^-11
@@ -448,22 +450,16 @@ __device__ __forceinline__ void fused_tiles(const FormLds<P> &S, const FusedForm
     for (int r = 0; r <= col[u].maxr; ++r) {
       if (col[u].rnd == r) {
         // read all, then write all: a lane's entries are distinct and the
-        // lanes of one round hold distinct rows.  The first contribution to
-        // an entry is stored as it is (0 + v = v exactly: v is never -0), so
-        // only the later ones read.
+        // lanes of one round hold distinct rows (the buffer starts at zero)
         T old[MT][4];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            old[mt][q] = 0;
-            if (!(addr[u][mt][q] & 0x8000)) old[mt][q] = *(const T *)(rb + addr[u][mt][q]);
-          }
+          for (int q = 0; q < 4; ++q) old[mt][q] = *(const T *)(rb + addr[u][mt][q]);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
-            *(T *)(rb + (addr[u][mt][q] & 0x7fff)) = old[mt][q] + val[mt][q];
+          for (int q = 0; q < 4; ++q) *(T *)(rb + addr[u][mt][q]) = old[mt][q] + val[mt][q];
       }
     }
   }
@@ -524,16 +520,12 @@ __device__ __forceinline__ void fused_tile_pair(const FormLds<P> &S0, const Form
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            old[mt][q] = T2{0, 0};
-            if (!(addr[u][mt][q] & 0x8000))
-              old[mt][q] = *(const T2 *)(rb + 2 * addr[u][mt][q]);
-          }
+          for (int q = 0; q < 4; ++q) old[mt][q] = *(const T2 *)(rb + 2 * addr[u][mt][q]);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
           for (int q = 0; q < 4; ++q)
-            *(T2 *)(rb + 2 * (addr[u][mt][q] & 0x7fff)) =
+            *(T2 *)(rb + 2 * addr[u][mt][q]) =
                 T2{old[mt][q].x + val0[u][mt][q], old[mt][q].y + val1[u][mt][q]};
       }
     }
@@ -558,6 +550,9 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
   unsigned char *end = stage_form<P, MT, NDT0, STAGE_A, NW>(smem, a.f[0], nphi, tid, S0);
   if constexpr (NF == 2) end = stage_form<P, MT, NDT1, STAGE_A, NW>(end, a.f[1], nphi, tid, S1);
   T *rowbuf = (T *)end + (size_t)wave * (a.span + 64) * (PR ? 2 : 1);
+  // the row buffer's entries start at zero; the write-back of every task
+  // clears what it read
+  for (int t = lane; t < a.span * (PR ? 2 : 1); t += 64) rowbuf[t] = 0;
   __syncthreads();
 
   const int ntasks = a.ntasks;
@@ -683,12 +678,15 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
           for (int t = 4 * lane; t < s4; t += 256) {
             const float4 p = *(const float4 *)(rowbuf + 2 * t);
             const float4 q = *(const float4 *)(rowbuf + 2 * t + 4);
+            *(float4 *)(rowbuf + 2 * t) = float4{0, 0, 0, 0};
+            *(float4 *)(rowbuf + 2 * t + 4) = float4{0, 0, 0, 0};
             *(f4u_t *)(V0 + t) = f4u_t{p.x, p.z, q.x, q.z};
             *(f4u_t *)(V1 + t) = f4u_t{p.y, p.w, q.y, q.w};
           }
         }
         for (int t = s4 + lane; t < span; t += 64) {
           const T2 v = ((const T2 *)rowbuf)[t];
+          ((T2 *)rowbuf)[t] = T2{0, 0};
           V0[t] = v.x;
           V1[t] = v.y;
         }
@@ -697,10 +695,14 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(FusedArgs a) {
         if constexpr (sizeof(T) == 4) {
           for (int t = 4 * lane; t < s4; t += 256) {
             const float4 p = *(const float4 *)(rowbuf + t);
+            *(float4 *)(rowbuf + t) = float4{0, 0, 0, 0};
             *(f4u_t *)(V + t) = f4u_t{p.x, p.y, p.z, p.w};
           }
         }
-        for (int t = s4 + lane; t < span; t += 64) V[t] = rowbuf[t];
+        for (int t = s4 + lane; t < span; t += 64) {
+          V[t] = rowbuf[t];
+          rowbuf[t] = 0;
+        }
       }
     }
     task = next;

@@ -123,12 +123,14 @@ struct CellwiseLaunch {
   int64_t n_dofs;
   const double *coeff;  // nodal coefficient or null
   float *zpt, *zmax;    // workspace: the coefficient at the points [n_cells][n_q_pad], its max per cell
+  void *rec;            // workspace: the cell factors of a coefficient form, 32 bytes per cell
   float *A_local;       // [n_cells][n_phi][n_phi]
   void *stream;
 };
 // Forms the whole-cell kernel is compiled for: FP16 storage, tetrahedra,
 // the Poisson form with 6 row tiles (P6) or the mass form with 4, 6 or 8
-// (P5..P7); a coefficient only with the Poisson form.
+// (P5..P7), n_phi a multiple of four; a coefficient only with the Poisson
+// form.
 bool cellwise_eligible(const FormLayout &L);
 fe_status launch_cellwise_fp16(const CellwiseLaunch &c);
 
