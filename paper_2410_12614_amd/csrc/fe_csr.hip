@@ -629,11 +629,184 @@ __global__ __launch_bounds__(256) void k_gather(const int64_t *adj_ptr, const in
   }
 }
 
+// Numeric gather over a flat stream of local rows.  A wave owns FLAT_ROWS
+// consecutive CSR rows; their incident local rows are consecutive in the
+// adjacency, so the wave walks them as one stream in groups of FLAT_G,
+// whatever row each belongs to.  The rows are cut into windows of at most
+// W CSR entries (whole rows) kept in LDS; a group never straddles two
+// windows.  Three stages overlap: the adjacency entries of group k + 2, the
+// ranks and values of group k + 1 and the LDS additions of group k (local
+// row after local row, so every entry is still summed in adjacency order,
+// cell ascending).  A window is written out (coalesced) after its last
+// group and cleared as it is read, so it starts at zero.  Every load is
+// issued unconditionally (clamped addresses, out-of-range parts marked) so
+// that the compiler's counts of memory operations in flight are exact.
+// Rows must be at most W entries long (checked by the caller).
+constexpr int FLAT_ROWS = 32;
+constexpr int FLAT_G = 8;
+
+struct FlatGroup {
+  int a, n;       // first adjacency index (relative to the wave's first row) and count
+  int r0, r1;     // the window's rows [r0, r1) (relative)
+  bool valid, last;
+};
+
+template <class T, int NF, int CH, int W>
+__global__ __launch_bounds__(256) void k_gather_flat(const int64_t *adj_ptr, const int64_t *adj,
+                                                     const uint16_t *rank, const int64_t *row_ptr,
+                                                     int64_t n_rows, int n_phi, const T *A0, const T *A1,
+                                                     const T *A2, const T *A3, T *V0, T *V1, T *V2,
+                                                     T *V3) {
+  constexpr int G = FLAT_G;
+  __shared__ T sbuf[4][NF][W];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t first = ((int64_t)blockIdx.x * 4 + wave) * FLAT_ROWS;
+  if (first >= n_rows) return;
+  const int nr = (int)min((int64_t)FLAT_ROWS, n_rows - first);
+  T (*buf)[W] = sbuf[wave];
+  const T *A[4] = {A0, A1, A2, A3};
+  T *V[4] = {V0, V1, V2, V3};
+  // lane l <= nr: the starts of row first + l in the CSR values and in the
+  // adjacency, relative to row first's
+  const int64_t rbase = row_ptr[first], abase = adj_ptr[first];
+  const int64_t alast = adj_ptr[n_rows] - 1;  // the last adjacency entry (the mesh has cells)
+  int rp = 0, ap = 0;
+  if (lane <= nr) {
+    rp = (int)(row_ptr[first + lane] - rbase);
+    ap = (int)(adj_ptr[first + lane] - abase);
+  }
+  auto rp_of = [&](int r) { return __builtin_amdgcn_readlane(rp, r); };
+  auto ap_of = [&](int r) { return __builtin_amdgcn_readlane(ap, r); };
+  // the window starting at row r0: the rows whose entries fit W
+  auto window_end = [&](int r0) {
+    const unsigned long long m = __ballot(lane <= nr && lane > r0 && rp - rp_of(r0) <= W);
+    return 63 - __builtin_clzll(m);
+  };
+  for (int t = lane; t < W; t += 64)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) buf[f][t] = 0;
+
+  // group cursor
+  int cr0 = 0, cr1 = window_end(0), ca = 0, ca_end = ap_of(cr1);
+  auto next_group = [&]() {
+    FlatGroup g;
+    g.valid = cr0 < nr;
+    g.a = ca;
+    g.n = g.valid ? min(G, ca_end - ca) : 0;
+    g.r0 = cr0;
+    g.r1 = cr1;
+    g.last = g.valid && ca + g.n == ca_end;
+    if (g.valid) {
+      ca += g.n;
+      if (ca == ca_end) {
+        cr0 = cr1;
+        if (cr0 < nr) {
+          cr1 = window_end(cr0);
+          ca_end = ap_of(cr1);
+        }
+      }
+    }
+    return g;
+  };
+  // adjacency entries of a group: lane u < G holds entry a + u (clamped to
+  // the group; -1 marks lanes past it and invalid groups)
+  auto load_entries = [&](const FlatGroup &g, int64_t &ent) {
+    const int u = lane < G ? lane : 0;
+    const int idx = g.n > 0 ? g.a + min(u, g.n - 1) : 0;
+    // (the loaded value is used on both sides, so the load is not made
+    // conditional on the lane)
+    const int64_t e = adj[min(abase + idx, alast)];
+    ent = e | ((g.valid && lane < g.n) ? (int64_t)0 : INT64_MIN);
+  };
+  // ranks and values of a group's local rows (rank -1: nothing to add)
+  auto load_rows = [&](int64_t ent, int (&rk)[G][CH], T (&v)[G][CH][NF]) {
+    const int64_t e0 = ((int64_t)__shfl((int)(ent >> 32), 0) << 32) | (uint32_t)__shfl((int)(ent & 0xffffffff), 0);
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int lo = __shfl((int)(ent & 0xffffffff), u), hi = __shfl((int)(ent >> 32), u);
+      const int64_t e = ((int64_t)hi << 32) | (uint32_t)lo;
+      const int64_t ec = e >= 0 ? e : (e0 >= 0 ? e0 : 0);  // a valid local row to read
+      const size_t row = (size_t)(ec >> ADJ_BITS) * n_phi + (ec & ADJ_MASK);
+#pragma unroll
+      for (int ch = 0; ch < CH; ++ch) {
+        const int j = 64 * ch + lane;
+        const size_t base = row * n_phi + min(j, n_phi - 1);
+        const int r = (int)rank[base];
+        rk[u][ch] = r - ((e >= 0 && j < n_phi) ? 0 : 0x10000);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) v[u][ch][f] = A[f][base];
+      }
+    }
+  };
+  // additions of a group into the window of rows [r0, r1)
+  auto add_rows = [&](const FlatGroup &g, const int (&rk)[G][CH], const T (&v)[G][CH][NF]) {
+    const int w0 = rp_of(g.r0);
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      if (u >= g.n) break;
+      // the row of local row a + u: the last row starting at or before it
+      const int ridx = __popcll(__ballot(lane <= nr && ap <= g.a + u)) - 1;
+      const int off = rp_of(ridx) - w0;
+#pragma unroll
+      for (int ch = 0; ch < CH; ++ch)
+        if (rk[u][ch] >= 0)
+#pragma unroll
+          for (int f = 0; f < NF; ++f) buf[f][off + rk[u][ch]] += v[u][ch][f];
+    }
+    if (g.last) {
+      // the window's rows out, the window cleared
+      const int span = rp_of(g.r1) - w0;
+      const int64_t o = rbase + w0;
+      for (int t = lane; t < span; t += 64)
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          V[f][o + t] = buf[f][t];
+          buf[f][t] = 0;
+        }
+    }
+  };
+
+  // two register sets used in turn (no copies of loaded registers: a copy
+  // would wait for the load): group g0's rows in set A, group g1's entries
+  // in eB
+  FlatGroup g0 = next_group(), g1 = next_group();
+  int64_t eA, eB;
+  load_entries(g0, eA);
+  load_entries(g1, eB);
+  int rkA[G][CH], rkB[G][CH];
+  T vA[G][CH][NF], vB[G][CH][NF];
+  load_rows(eA, rkA, vA);
+  while (g0.valid) {
+    const FlatGroup g2 = next_group();
+    load_entries(g2, eA);
+    load_rows(eB, rkB, vB);
+    add_rows(g0, rkA, vA);
+    if (!g1.valid) break;
+    const FlatGroup g3 = next_group();
+    load_entries(g3, eB);
+    load_rows(eA, rkA, vA);
+    add_rows(g1, rkB, vB);
+    g0 = g2;
+    g1 = g3;
+  }
+}
+
 template <class T, int NF>
 fe_status launch_gather(const int64_t *adj_ptr, const int64_t *adj, const uint16_t *rank,
-                        const int64_t *row_ptr, int64_t n_rows, int n_phi, void *const *A,
-                        void *const *V, hipStream_t s) {
+                        const int64_t *row_ptr, int64_t n_rows, int n_phi, int64_t max_len,
+                        void *const *A, void *const *V, hipStream_t s) {
   if (n_phi > 64 * GATHER_CH) return FE_EUNSUPPORTED;
+  // the flat stream where the rows fit its window (and the local rows its
+  // chunks)
+  constexpr int FW = sizeof(T) * NF <= 4 ? 2048 : 1024;
+  if (sizeof(T) * NF <= 8 && max_len <= FW && n_phi <= 128) {
+    const int64_t waves = (n_rows + FLAT_ROWS - 1) / FLAT_ROWS;
+    auto kern = n_phi <= 64 ? k_gather_flat<T, NF, 1, FW> : k_gather_flat<T, NF, 2, FW>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, adj_ptr, adj, rank,
+                       row_ptr, n_rows, n_phi, (const T *)A[0], (const T *)A[1], (const T *)A[2],
+                       (const T *)A[3], (T *)V[0], (T *)V[1], (T *)V[2], (T *)V[3]);
+    return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
+  }
   const int64_t waves = (n_rows + GATHER_ROWS - 1) / GATHER_ROWS;
   const int64_t blocks = (waves + 3) / 4;
   auto kern = n_phi <= 64    ? k_gather<T, NF, 1>
@@ -995,17 +1168,17 @@ static fe_status assemble_csr(const fe_form_desc *forms, const void *const *form
   fe_status st = FE_EINVAL;
   if (elt == 8) {
     switch (ng) {
-      case 1: st = launch_gather<double, 1>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
-      case 2: st = launch_gather<double, 2>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
-      case 3: st = launch_gather<double, 3>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
-      case 4: st = launch_gather<double, 4>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
+      case 1: st = launch_gather<double, 1>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, mats[0].max_row_len, Aloc, V, s); break;
+      case 2: st = launch_gather<double, 2>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, mats[0].max_row_len, Aloc, V, s); break;
+      case 3: st = launch_gather<double, 3>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, mats[0].max_row_len, Aloc, V, s); break;
+      case 4: st = launch_gather<double, 4>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, mats[0].max_row_len, Aloc, V, s); break;
     }
   } else {
     switch (ng) {
-      case 1: st = launch_gather<float, 1>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
-      case 2: st = launch_gather<float, 2>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
-      case 3: st = launch_gather<float, 3>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
-      case 4: st = launch_gather<float, 4>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, Aloc, V, s); break;
+      case 1: st = launch_gather<float, 1>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, mats[0].max_row_len, Aloc, V, s); break;
+      case 2: st = launch_gather<float, 2>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, mats[0].max_row_len, Aloc, V, s); break;
+      case 3: st = launch_gather<float, 3>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, mats[0].max_row_len, Aloc, V, s); break;
+      case 4: st = launch_gather<float, 4>(adj_ptr, adj, rank, row_ptr, n_dofs, n_phi, mats[0].max_row_len, Aloc, V, s); break;
     }
   }
   return st;
