@@ -123,13 +123,24 @@ def log(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
+WARM_S = 0.25  # least wall time of untimed calls before a timed window
+
+
 def time_steps(fn, steps, warmup):
     """Average ms per call of ``fn`` over ``steps`` calls, HIP events on the
-    current stream (the stream the library launches on)."""
+    current stream (the stream the library launches on).  Untimed calls
+    first: ``warmup`` of them, and more until WARM_S seconds have passed, so
+    that the GPU clocks have left their idle state (a window timed right
+    after host-side set-up reads up to 15 % slow)."""
     import torch
+    t0 = time.perf_counter()
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    while time.perf_counter() - t0 < WARM_S:
+        for _ in range(4):
+            fn()
+        torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
