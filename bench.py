@@ -73,10 +73,15 @@ PEAK_MFMA_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "split": 2500.0, "fp32": 157
 # pair rate (unpacked FP32 is half of it, 78.6)
 PEAK_VALU_TFLOPS = 157.3
 
-# Measured HBM traffic of the fused pass (rocprofv3 FETCH_SIZE / WRITE_SIZE,
-# scaled by a plain copy) and the sources it was measured with.
+# Measured HBM traffic (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a
+# plain copy) of the dominant kernels, and the sources each was measured
+# with (a figure is reported only for the code it was measured on).
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_pass_c2_fp16_traffic.txt")
 KERNEL_SOURCES = ["fe_fused.h", "fe_cell_kernel.h", "fe_internal.h", "fe_cell_fp16.hip", "fe_csr.hip"]
+CW_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cellwise_c3_fp16_traffic.txt")
+CW_SOURCES = ["fe_cellwise.h", "fe_cell_kernel.h", "fe_internal.h", "fe_cell_fp16.hip"]
+GATHER_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gather_c3_fp16_traffic.txt")
+GATHER_SOURCES = ["fe_csr.hip", "fe_internal.h"]
 
 WORKLOAD = ("P4 Lagrange mass+stiffness, 24^3 x 6 jittered Kuhn tetrahedra (82,944 cells, "
             "35 dofs/cell), 5% flattened to aspect 1e3, 125-point collapsed Gauss-Jacobi rule")
@@ -505,6 +510,14 @@ def c3_section(args, steps, warmup):
     t16 = f16["kernels"]["local_matrices"]["ms"] / 1e3
     f16["roofline"]["mfma_executed_tflops"] = hw_flops / t16 / 1e12
     f16["roofline"]["mfma_executed_frac"] = hw_flops / t16 / 1e12 / PEAK_MFMA_TFLOPS["fp16"]
+    # HBM bytes of the whole-cell kernel and of the row gather (measured,
+    # per launch); the gather is bound by HBM
+    f16["roofline"]["traffic"] = measured_traffic(CW_TRAFFIC_FILE, CW_SOURCES)
+    gb = measured_traffic(GATHER_TRAFFIC_FILE, GATHER_SOURCES)
+    if gb is not None:
+        tg = f16["kernels"]["row_gather"]["ms"] / 1e3
+        f16["kernels"]["row_gather"].update({"traffic": gb, "gbs": gb / tg / 1e9,
+                                            "frac_hbm": gb / tg / 1e9 / PEAK_HBM_GBS})
     out.update({"metric": "cells/s (weighted P6 stiffness, kernels + CSR assembly)",
                 "value": f16["value"], "unit": "cells/s", "dtype": f16["dtype"],
                 "ms_per_step": f16["ms_per_step"], "roofline": f16["roofline"],
@@ -539,28 +552,28 @@ def c3_section(args, steps, warmup):
     return out
 
 
-def sources_digest():
-    """SHA-256 over the sources of the fused pass (traffic is reported only
-    for the code it was measured on)."""
+def sources_digest(sources=None):
+    """SHA-256 over a kernel's sources (traffic is reported only for the
+    code it was measured on)."""
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources or KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2410_12614_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic():
-    """(fetch + write bytes per launch of the fused pass, digest) from the
-    committed counter summary, or None when absent or measured on other code."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(path=TRAFFIC_FILE, sources=None):
+    """Fetch + write bytes per launch of a kernel from its committed counter
+    summary, or None when absent or measured on other code."""
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("sources_sha256") != sources_digest():
+    if vals.get("sources_sha256") != sources_digest(sources):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
