@@ -188,13 +188,6 @@ struct CwArgs {
   int d, n_phi, n_q, n_q_pad;
 };
 
-// Index of the symmetric tile pair (I, J), I <= J, in row-major order of
-// the upper triangle of an MT x MT tile grid.
-template <int MT>
-__device__ __forceinline__ constexpr int pair_index(int I, int J) {
-  return I * MT - I * (I - 1) / 2 + (J - I);
-}
-
 template <int NDT, bool COEFF>
 __device__ __forceinline__ CwCell<NDT> cw_cell(const CwArgs &a, int64_t ce) {
   return cell_scales<NDT>(a.hdr, a.d, a.coords + ce * (a.d + 1) * a.d, COEFF ? (double)a.zmax[ce] : 1.0);
@@ -230,8 +223,20 @@ __device__ __forceinline__ CwCell<NDT> cw_cell(const CwArgs &a, int64_t ce) {
 // consecutive columns), the tiles (J, I), I > J, transposed (lane: rows
 // 16 J + 4 kb + r, column 16 I + c); both are written into a row block in
 // the wave's LDS, which then goes out in 16-byte pieces, consecutive lanes
-// on consecutive addresses.  n_phi is a multiple of four, so a 16-byte
-// piece is either inside the matrix or not.
+// on consecutive addresses.  With fewer than 11 row tiles n_phi is a
+// multiple of four, so a 16-byte piece is either inside the matrix or not;
+// with 11 (P8, n_phi = 165) the block is staged as far into the LDS buffer
+// as it starts past a 16-byte boundary in memory, and leaves as a few
+// dwords, whole 16-byte pieces and a few dwords.  The 66 accumulator tiles
+// of that form take all 256 AGPRs and a few VGPRs; they are read out of
+// the AGPRs where they are stored (otherwise the compiler copies them all
+// to VGPRs at the end of the chunk loop and spills).
+//
+// Phases.  Workgroups start their walks a quarter, a half or three
+// quarters of a cell apart (a prefix of chunks computed and dropped), so
+// that not every wave of the chip stores its rows at the same time: a
+// wave's next table load waits for its stores (loads and stores share one
+// in-order counter).
 // s_waitcnt immediate (gfx9 encoding) waiting until at most n vector
 // memory operations of this wave are outstanding (LDS and export counters
 // left free)
@@ -248,17 +253,47 @@ __device__ __forceinline__ void bare_barrier() {
 template <int S>
 using slot_t = std::integral_constant<int, S>;
 
+// An accumulator tile read out of its AGPRs where it is used (volatile asm,
+// AGPR operands), times a scale. Plain code would copy every accumulator
+// to VGPRs at the end of the chunk loop, which the forms with 66 tiles do
+// not have room for. (The MFMA result hazard is the caller's: the
+// compiler does not pad inline asm.)
+__device__ __forceinline__ f32x4_t agpr_tile_scaled(const f32x4_t &x, float s) {
+  float y0, y1, y2, y3;
+  asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(y0) : "a"(x[0]));
+  asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(y1) : "a"(x[1]));
+  asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(y2) : "a"(x[2]));
+  asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(y3) : "a"(x[3]));
+  return f32x4_t{y0 * s, y1 * s, y2 * s, y3 * s};
+}
+
 constexpr int CW_ZMAX = 512;  // points of a coefficient form (n_q_pad) the LDS row holds
 
-template <int MT, int NDT, bool COEFF, int NW>
+// Column ranges: a launch may compute only the tiles (I, J) with
+// J0 <= J < J1 (and I <= J), so that a form whose MT (MT + 1) / 2 tiles do
+// not fit the accumulator registers (P8 mass: 66) runs as two launches over
+// the same cells; such a launch loads only the row tiles below J1 (mass
+// forms: a prefix of each chunk) and stores tile by tile.
+template <int MT, int J0, int J1>
+__device__ __forceinline__ constexpr int range_index(int I, int J) {
+  return (J * (J + 1) - J0 * (J0 + 1)) / 2 + I;
+}
+
+template <int MT, int NDT, bool COEFF, int NW, int J0 = 0, int J1 = MT>
 __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
+  constexpr bool FULL = J0 == 0 && J1 == MT;
+  static_assert(FULL || NDT == 1, "column ranges of a chunk are contiguous for one slab only");
   constexpr int NT = NW * 64;
-  constexpr int NP = MT * (MT + 1) / 2;
-  constexpr int CH16 = NDT * MT * 64;         // 16-byte pieces of one chunk (a multiple of 64)
+  constexpr int NP = (J1 * (J1 + 1) - J0 * (J0 + 1)) / 2;
+  constexpr int MTL = J1;                     // row tiles loaded per slab
+  constexpr int CH16 = NDT * MTL * 64;        // 16-byte pieces of one chunk loaded (a multiple of 64)
+  constexpr int CHS = NDT * MT * 64;          // pieces of one chunk of the table
   constexpr int PRE = (CH16 + NT - 1) / NT;  // direct loads per wave and chunk
   static_assert(CH16 >= NT, "a chunk covers every thread at least once");
   __shared__ uint4 ring0[CH16], ring1[CH16], ring2[CH16];
-  __shared__ float4 rbuf[NW][16 * MT * 4];  // a wave's row block (16 rows x n_phi)
+  // a wave's row block (16 rows x n_phi) for the whole-matrix stores, or its
+  // tile-transpose buffer for the stores by tiles
+  __shared__ float4 rbuf[NW][FULL ? 16 * MT * 4 : 16 * 5];
   __shared__ float zbuf[COEFF ? NW : 1][COEFF ? CW_ZMAX : 4];
   extern __shared__ float wl[];              // quadrature weights [n_q_pad]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -270,7 +305,12 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
 
   const int64_t per_round = (int64_t)gridDim.x * NW;
   const int rounds = (int)((a.n_cells + per_round - 1) / per_round);
-  const int total = rounds * nqc;  // chunks this wave walks
+  // workgroups start their walks at four phases of a cell: a prefix of
+  // the last `off` chunks of a cell, computed and dropped, so that the
+  // stores at the ends of cells do not come from every workgroup at once
+  // (a wave's next table load waits for its stores: one in-order counter)
+  const int off = (((int)blockIdx.x >> 3) & 3) * nqc / 4;
+  const int total = off + rounds * nqc;  // chunks this wave walks
   auto cell_of = [&](int rd) -> int64_t {
     const int64_t cell = (int64_t)rd * per_round + (int64_t)blockIdx.x * NW + wave;
     return cell < a.n_cells ? cell : a.n_cells - 1;
@@ -281,7 +321,7 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
   auto fill = [&](int tc, auto sl) {
     constexpr int S = decltype(sl)::value;
     uint4 *to = S == 0 ? ring0 : S == 1 ? ring1 : ring2;
-    const uint4 *from = src + (size_t)tc * CH16;
+    const uint4 *from = src + (size_t)tc * CHS;
 #pragma unroll
     for (int p = 0; p < PRE; ++p) {
       int e0 = p * NT + wave * 64;  // wave-uniform
@@ -310,8 +350,9 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
   };
 
   for (int i = tid; i < n_q_pad; i += NT) wl[i] = (float)a.wq[i];
-  fill(0, slot_t<0>());
-  fill(1 % nqc, slot_t<1>());
+  // walk position g holds chunk (g - off) mod nqc
+  fill((nqc - off) % nqc, slot_t<0>());
+  fill((nqc - off + 1) % nqc, slot_t<1>());
   // prefetched: the next cell's factors (and its coefficient values)
   uint4 rn0 = {0, 0, 0, 0}, rn1 = {0, 0, 0, 0};
   if constexpr (COEFF) {
@@ -321,8 +362,9 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
-  for (int rd = 0; rd < rounds; ++rd) {
-    const int64_t cell = (int64_t)rd * per_round + (int64_t)blockIdx.x * NW + wave;
+  // (round -1: the prefix, as a cell past the end)
+  for (int rd = off > 0 ? -1 : 0; rd < rounds; ++rd) {
+    const int64_t cell = rd < 0 ? a.n_cells : (int64_t)rd * per_round + (int64_t)blockIdx.x * NW + wave;
     const bool valid = cell < a.n_cells;
     const int64_t ce = valid ? cell : a.n_cells - 1;
     const int64_t ce_next = cell_of(rd + 1 < rounds ? rd + 1 : rd);
@@ -342,7 +384,8 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
     f32x4_t acc[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) acc[p] = f32x4_t{0, 0, 0, 0};
-    const int g0 = rd * nqc;  // walk position of the cell's first chunk
+    const int g0 = off + rd * nqc;      // walk position of the cell's chunk 0
+    const int q0 = rd < 0 ? nqc - off : 0;  // its first chunk walked
 
     // chunk qc of the cell (walk position g0 + qc) from slot S; chunk
     // g0 + qc + 2 into slot (S + 2) % 3
@@ -356,15 +399,16 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
         const int g = g0 + qc;
         int fc = qc + 2;
         if (fc >= nqc) fc -= nqc;
+        if (fc >= nqc) fc -= nqc;
         fill(g + 2 < total ? fc : 0, slot_t<(S + 2) % 3>());
       }
       // the chunk's fragments
-      half8_t F[NDT][MT];
+      half8_t F[NDT][MTL];
 #pragma unroll
       for (int s = 0; s < NDT; ++s)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const uint4 u = cur[(s * MT + mt) * 64 + lane];
+        for (int mt = 0; mt < MTL; ++mt) {
+          const uint4 u = cur[(s * MTL + mt) * 64 + lane];
           F[s][mt] = *reinterpret_cast<const half8_t *>(&u);
         }
       // this lane's eight points: w z scaled, rounded in pairs
@@ -388,7 +432,7 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
 #pragma unroll
           for (int p = 0; p < 4; ++p) cst[t][p] = wz[p] * cf.g2[NDT == 1 ? 0 : sym_comp(s, t)];
 #pragma unroll
-        for (int J = 0; J < MT; ++J) {
+        for (int J = J0; J < J1; ++J) {
           half8_t h;
 #pragma unroll
           for (int p = 0; p < 4; ++p) {
@@ -401,8 +445,8 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
           }
 #pragma unroll
           for (int I = 0; I <= J; ++I)
-            acc[pair_index<MT>(I, J)] =
-                __builtin_amdgcn_mfma_f32_16x16x32_f16(F[s][I], h, acc[pair_index<MT>(I, J)], 0, 0, 0);
+            acc[range_index<MT, J0, J1>(I, J)] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                F[s][I], h, acc[range_index<MT, J0, J1>(I, J)], 0, 0, 0);
         }
       }
       // chunk g + 1 (loaded during chunk g - 1) and the next coefficient
@@ -411,16 +455,16 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
       __builtin_amdgcn_s_waitcnt(waitcnt_vm(PRE));
       bare_barrier();
     };
-    // the cell's chunks, slot of chunk qc = (PH + qc) % 3
+    // the cell's chunks from q0, slot of chunk qc = (PH + qc - q0) % 3
     auto chunks = [&](auto ph) {
       constexpr int PH = decltype(ph)::value;
-      for (int qc = 0; qc < nqc; qc += 3) {
+      for (int qc = q0; qc < nqc; qc += 3) {
         step(qc, slot_t<PH>());
         if (qc + 1 < nqc) step(qc + 1, slot_t<(PH + 1) % 3>());
         if (qc + 2 < nqc) step(qc + 2, slot_t<(PH + 2) % 3>());
       }
     };
-    const int ph = g0 % 3;
+    const int ph = (g0 + q0) % 3;
     if (ph == 0) chunks(slot_t<0>());
     else if (ph == 1) chunks(slot_t<1>());
     else chunks(slot_t<2>());
@@ -430,41 +474,149 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
       load_rec(ce_next, rn0, rn1);
       load_z(ce_next);
     }
-    if (valid) {
+    if (valid && FULL) {
       if (!COEFF && !cf.ok && lane == 0) atomicOr(a.status, STATUS_DEGENERATE);
-      float *A = a.A + ce * (int64_t)nphi * nphi;  // wave-uniform
+      // the forms with fewer than 11 row tiles have n_phi a multiple of
+      // four (rows of whole float4s); with 11 (n_phi = 165) the rows are
+      // packed at any n_phi, and n_phi passes through an empty asm so that
+      // the store offsets are formed here, per cell, instead of being kept
+      // live across the walk
+      constexpr bool V4_ONLY = MT < 11;
+      int np = nphi;
+      if constexpr (!V4_ONLY) asm volatile("" : "+s"(np));
+      float *A = a.A + ce * (int64_t)np * np;  // wave-uniform
+      constexpr bool v4 = V4_ONLY;
+      // (at least 19 wait states between the last MFMA and the first
+      // accumulator read in asm)
+      if constexpr (!v4) asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7");
 #pragma unroll
       for (int J = 0; J < MT; ++J) {
-        // row block J: rows 16 J + x, x < 16, at rb[x n_phi + col]
+        // row block J: rows 16 J + x, x < 16, at rs[x n_phi + col], with rs
+        // as far into the LDS buffer as the block's start is past a 16-byte
+        // boundary in global memory (whole float4s on both sides)
+        float *blk = A + 16 * J * np;
+        float *rs = v4 ? rb : rb + (int)(((uintptr_t)blk >> 2) & 3);
+        // the scale as a new value per row block (an empty asm), so that a
+        // tile's two scaled copies (mirror in row block I, direct in row
+        // block J) are formed where they are stored, not kept in VGPRs
+        // from the first to the second
+        float inv = cf.inv;
+        asm volatile("" : "+v"(inv));
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
-        for (int I = 0; I < MT; ++I) {
+        for (int ii = 0; ii < MT; ++ii) {
+          // v4: the tiles in column order, columns past n_phi skipped;
+          // otherwise the last tile column first and nothing skipped: its
+          // columns past n_phi run into the first columns of the next row,
+          // which the later tiles overwrite (the wave's LDS writes complete
+          // in order; the fence keeps the compiler from reordering them)
+          const int I = v4 ? ii : ii == 0 ? MT - 1 : ii - 1;
           if (I <= J) {
             // tile (I, J): lane holds A(16 I + 4 kb + r, 16 J + c) = A(16 J + c, 16 I + 4 kb + r)
-            const f32x4_t v = acc[pair_index<MT>(I, J)] * cf.inv;
+            const f32x4_t v = v4 ? acc[range_index<MT, J0, J1>(I, J)] * inv
+                                 : agpr_tile_scaled(acc[range_index<MT, J0, J1>(I, J)], inv);
             const int col = 16 * I + 4 * kb;
-            if (col < nphi) *(float4 *)(rb + c * nphi + col) = float4{v[0], v[1], v[2], v[3]};
+            if (v4) {
+              if (col < np) *(float4 *)(rb + c * np + col) = float4{v[0], v[1], v[2], v[3]};
+            } else {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) rs[c * np + col + r] = v[r];
+            }
           } else {
             // tile (J, I): lane holds A(16 J + 4 kb + r, 16 I + c)
-            const f32x4_t v = acc[pair_index<MT>(J, I)] * cf.inv;
+            const f32x4_t v = v4 ? acc[range_index<MT, J0, J1>(J, I)] * inv
+                                 : agpr_tile_scaled(acc[range_index<MT, J0, J1>(J, I)], inv);
             const int col = 16 * I + c;
-            if (col < nphi)
+            if (v4) {
+              if (col < np)
 #pragma unroll
-              for (int r = 0; r < 4; ++r) rb[(4 * kb + r) * nphi + col] = v[r];
+                for (int r = 0; r < 4; ++r) rb[(4 * kb + r) * np + col] = v[r];
+            } else {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) rs[(4 * kb + r) * np + col] = v[r];
+            }
           }
+          if (!v4 && ii == 0) __atomic_signal_fence(__ATOMIC_SEQ_CST);
         }
+        // (the wave's own LDS accesses complete in order; the fences keep
+        // the compiler from moving them across one another)
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         // the block's rows (those inside the matrix) are contiguous
-        const int nrow = min(16, nphi - 16 * J);
-        const int n16 = nrow * nphi / 4;
-        float4 *dst = (float4 *)(A + 16 * J * nphi);
-        for (int t = lane; t < n16; t += 64) dst[t] = rbuf[wave][t];
+        const int nrow = min(16, np - 16 * J);
+        if (v4) {
+          const int n16 = nrow * np / 4;
+          float4 *dst = (float4 *)blk;
+          for (int t = lane; t < n16; t += 64) dst[t] = rbuf[wave][t];
+        } else {
+          // dwords up to the first 16-byte boundary, whole float4s (two
+          // LDS reads ahead of their stores), then the last dwords
+          const int n = nrow * np;
+          const int hd = (4 - (int)(((uintptr_t)blk >> 2) & 3)) & 3;
+          if (lane < hd) blk[lane] = rs[lane];
+          const int nb = (n - hd) >> 2;
+          const float4 *s4 = (const float4 *)(rs + hd);  // 16-byte aligned
+          float4 *d4 = (float4 *)(blk + hd);               // 16-byte aligned
+          int k = lane;
+          for (; k + 64 < nb; k += 2 * 64) {
+            const float4 w0 = s4[k], w1 = s4[k + 64];
+            d4[k] = w0;
+            d4[k + 64] = w1;
+          }
+          if (k < nb) d4[k] = s4[k];
+          const int tl = hd + 4 * nb;
+          if (tl + lane < n) blk[tl + lane] = rs[tl + lane];
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
       }
+    }
+    if (valid && !FULL) {
+      // tile by tile: M(y, x) = A(16 I + y, 16 J + x) into the wave's LDS
+      // tile, then rows 16 J + x (columns 16 I + y) and, off the diagonal,
+      // rows 16 I + y (columns 16 J + x), four rows of 16 consecutive
+      // columns per store (any n_phi)
+      if (J0 == 0 && !cf.ok && lane == 0) atomicOr(a.status, STATUS_DEGENERATE);
+      // (n_phi passed through an empty asm so that the store offsets are
+      // formed here, per cell, instead of being kept live across the walk)
+      int np = nphi;
+      asm volatile("" : "+s"(np));
+      float *A = a.A + ce * (int64_t)np * np;  // wave-uniform
+      constexpr int TS = 20;
+      const int lx = lane & 15, ly = lane >> 4;
+#pragma unroll
+      for (int J = J0; J < J1; ++J)
+#pragma unroll
+        for (int I = 0; I <= J; ++I) {
+          const f32x4_t v = acc[range_index<MT, J0, J1>(I, J)] * cf.inv;
+          // (the wave's own LDS accesses complete in order; the fences keep
+          // the compiler from moving them across one another)
+          __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) rb[(4 * kb + r) * TS + c] = v[r];
+          __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int x = 4 * k + ly;  // direct: row 16 J + x, column 16 I + lx
+            const float w = rb[lx * TS + x];
+            const int row = 16 * J + x, col = 16 * I + lx;
+            if (row < np && col < np) A[row * np + col] = w;
+          }
+          if (I != J)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int y = 4 * k + ly;  // mirror: row 16 I + y, column 16 J + lx
+              const float w = rb[y * TS + lx];
+              const int row = 16 * I + y, col = 16 * J + lx;
+              if (row < np && col < np) A[row * np + col] = w;
+            }
+        }
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
   }
 }
 
-template <int MT, int NDT, bool COEFF, int NW>
+template <int MT, int NDT, bool COEFF, int NW, int J0 = 0, int J1 = MT>
 static fe_status launch_cellwise_one(const CellwiseLaunch &c, const CwArgs &k) {
-  auto kern = cellwise_kernel<MT, NDT, COEFF, NW>;
+  auto kern = cellwise_kernel<MT, NDT, COEFF, NW, J0, J1>;
   // dynamic: the quadrature weights (the ring and the transpose buffers are
   // static)
   const size_t smem = (size_t)c.L->n_q_pad * sizeof(float);
@@ -526,6 +678,7 @@ inline fe_status launch_cellwise(const CellwiseLaunch &c) {
     case 4: return launch_cellwise_one<4, 1, false, 4>(c, k);
     case 6: return launch_cellwise_one<6, 1, false, 4>(c, k);
     case 8: return launch_cellwise_one<8, 1, false, 4>(c, k);
+    case 11: return launch_cellwise_one<11, 1, false, 4>(c, k);
   }
   return FE_EUNSUPPORTED;
 }

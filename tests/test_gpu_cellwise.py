@@ -1,7 +1,8 @@
 """The whole-cell FP16 kernel (one wave per cell, symmetric tiles, B^T
 fragments shared through an LDS ring): local matrices of the forms it is
 compiled for against the FP64 oracle (tile 8 of fe_cell_kernels_tile:
-mass P5..P7, Poisson P6; the Poisson P6 form with a coefficient through
+mass P5..P8 (P8 as two launches over column ranges, n_phi = 165 not a
+multiple of four), Poisson P6; the Poisson P6 form with a coefficient through
 FE_NUMERIC, where the coefficient at the points goes to the workspace), the
 entrywise rounding-error bound of the FP16 mode, ragged batches, degenerate
 cells and the two halves of the gather path."""
@@ -41,7 +42,7 @@ def _local(mesh, p, q, form, tile):
     return buf, out.double().cpu().numpy()
 
 
-@pytest.mark.parametrize("form,p", [("mass", 5), ("mass", 6), ("mass", 7), ("stiffness", 6)])
+@pytest.mark.parametrize("form,p", [("mass", 5), ("mass", 6), ("mass", 7), ("mass", 8), ("stiffness", 6)])
 def test_whole_cell_kernel_local_matrices(form, p):
     # 2^3 x 6 = 48 cells, 5 % flattened: the cells of a workgroup's last
     # round are ragged (48 is not a multiple of the grid's waves)
@@ -82,7 +83,7 @@ def test_whole_cell_kernel_refuses_other_forms():
     m = config_mesh("c2", n=1, degree=4)
     mv = api.MeshView.from_numpy(m.cell_coords, m.dofmap, m.n_dofs)
     for prec, p, form in (("fp32", 6, "mass"), ("fp16", 4, "mass"), ("fp16", 5, "stiffness"),
-                          ("fp16", 8, "mass")):
+                          ("fp16", 8, "stiffness"), ("bf16", 8, "mass")):
         mm = config_mesh("c2", n=1, degree=p)
         mvv = api.MeshView.from_numpy(mm.cell_coords, mm.dofmap, mm.n_dofs)
         desc = api.form_desc(3, p, 2 * p, form, prec)
