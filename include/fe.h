@@ -221,7 +221,8 @@ fe_status fe_cell_kernels(const fe_form_desc *f, const void *form_buf, const fe_
 /* ------------------------------------------------------------------------
  * fe_cell_kernels_tile -- fe_cell_kernels with an explicit tile variant.
  *
- * tile = variant + 4 * occ, 0 <= tile < 8, tile 8, or -1 for the default:
+ * tile = variant + 4 * occ, 0 <= tile < 8, tile 8, tile 9, or -1 for the
+ * default:
  *   variant 0: 8-wave workgroups, B^T fragments and the weighted table
  *              staged in LDS (forms with at most 4 row tiles of 16 whose
  *              tables fit)
@@ -236,10 +237,16 @@ fe_status fe_cell_kernels(const fe_form_desc *f, const void *form_buf, const fe_
  *              workgroup, only the tiles of one triangle of the symmetric
  *              matrix contracted) for FE_FP16_ACC32 tetrahedral forms
  *              without a coefficient: mass P5..P8, Poisson P6.
+ *   tile 9   : the smallest FE_FP16_ACC32 mass forms without a coefficient
+ *              (n_phi 3, 4, 6 or 10: P1, P2 tetrahedra, P1..P3 triangles,
+ *              at most 128 quadrature points) on the vector ALUs, one
+ *              thread per row of a local matrix (Section 3, Algorithm 1).
  * Tiles 0..7 sum every entry in the same order: results are bitwise
  * identical across them.  Tile 8 forms H from the fragments and per-point
  * products c_st(q) = w_q G_st rounded to half (the same precision, its own
- * rounding order): within the same error bound, not bitwise equal.
+ * rounding order): within the same error bound, not bitwise equal.  Tile 9
+ * forms the same half H as tiles 0..7 and sums the exact products in
+ * single in its own order: within the same bound, not bitwise equal.
  * FE_EUNSUPPORTED when the variant does not apply to the form; FE_EINVAL
  * for a tile out of range; otherwise as fe_cell_kernels.
  * ------------------------------------------------------------------------ */
@@ -250,7 +257,7 @@ fe_status fe_cell_kernels_tile(const fe_form_desc *f, const void *form_buf, cons
  * fe_tune_cell_kernels -- autotuner of the cell-kernel tile for one form and
  * mesh: runs every tile variant that applies (one warm-up launch, then
  * `reps` timed launches with HIP events on the stream) and returns the
- * fastest in *best_tile; times_ms (NULL or [9]) receives the average time
+ * fastest in *best_tile; times_ms (NULL or [10]) receives the average time
  * per launch of each tile, -1 where the tile does not apply.  A_local is
  * overwritten (the result of the last tile run).  SYNCHRONISES the stream.
  * Errors: FE_EINVAL (reps < 1, NULL best_tile), FE_EUNSUPPORTED (no tile

@@ -316,7 +316,7 @@ def fe_tune_cell_kernels(desc: L.fe_form_desc, form_buf: torch.Tensor, mesh: Mes
     """(best tile, per-tile ms with -1 where a tile does not apply)."""
     mv = mesh.struct()
     best = ctypes.c_int32(-1)
-    times = (ctypes.c_float * 9)()
+    times = (ctypes.c_float * 10)()
     check(L.load().fe_tune_cell_kernels(ctypes.byref(desc), _ptr(form_buf), ctypes.byref(mv),
                                         _ptr(A_local), int(reps), ctypes.byref(best),
                                         ctypes.cast(times, ctypes.c_void_p), _stream(stream)),

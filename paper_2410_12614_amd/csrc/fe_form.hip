@@ -365,6 +365,7 @@ fe_status cell_kernels(const fe_form_desc *f, const void *form_buf, const fe_mes
   a.A_local = A_local;
   a.stream = stream;
   a.tile = tile;
+  if (tile == CELL_TILE_SMALL) return launch_small_fp16(a);
   if (tile == CELL_TILE_WHOLE) {
     // the whole-cell kernel; without a workspace only forms without a
     // coefficient (the coefficient at the points needs one)

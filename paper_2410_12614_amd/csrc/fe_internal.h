@@ -102,15 +102,19 @@ struct CellLaunch {
 };
 // tiles 0..7: the batched cell kernel (variant + 4 occ), bitwise identical
 // to each other; tile 8: the whole-cell kernel (FP16 forms it is compiled
-// for, no coefficient), same precision, its own rounding order
-constexpr int CELL_TILES = 9;
+// for, no coefficient), same precision, its own rounding order; tile 9: the
+// vector-ALU kernel of the smallest FP16 mass forms (fe_smallcell.h), the
+// same H, its own summation order
+constexpr int CELL_TILES = 10;
 constexpr int CELL_TILE_WHOLE = 8;
+constexpr int CELL_TILE_SMALL = 9;
 fe_status launch_cell_fp64(const CellLaunch &a);
 fe_status launch_cell_fp32(const CellLaunch &a);
 fe_status launch_cell_fp16(const CellLaunch &a);
 fe_status launch_cell_bf16(const CellLaunch &a);
 fe_status launch_cell_split(const CellLaunch &a);
 fe_status launch_cell(const CellLaunch &a);
+fe_status launch_small_fp16(const CellLaunch &a);  // FE_EUNSUPPORTED unless the form is one of its own
 
 // ---- whole-cell kernel (one wave per cell, FP16), see fe_cellwise.h ----
 struct CellwiseLaunch {

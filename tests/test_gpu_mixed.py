@@ -83,22 +83,24 @@ def test_mixed_degree_values_and_pattern(prec):
 
 
 def test_tiles_are_bitwise_identical_and_tuner_picks_one():
-    """Tiles 0..7 (the batched cell kernel) give the same bits; tile 8 (the
-    whole-cell kernel, its own rounding order) is held to the oracle."""
+    """Tiles 0..7 (the batched cell kernel) give the same bits; tiles 8 (the
+    whole-cell kernel) and 9 (the vector-ALU kernel of the smallest forms),
+    each with its own summation order, are held to the oracle."""
     blocks = small_blocks()
     md = _md(blocks, "fp16")
     for b, blk in zip(md.blocks, blocks):
-        out = torch.full_like(b["values"], float("nan"))
-        try:
-            api.fe_cell_kernels_tile(b["desc"], b["form_buf"], b["mesh"], out, 8)
-            torch.cuda.synchronize()
-            ref8 = _oracle_block(blk).reshape(-1)
-            got = out[:ref8.size].double().cpu().numpy()
-            err = np.linalg.norm(got - ref8) / np.linalg.norm(ref8)
-            say(f"  p{b['degree']}: whole-cell kernel err {err:.2e}")
-            assert err <= 1e-3, (b["degree"], err)
-        except api.L.FeError as e:
-            assert e.status == L.FE_EUNSUPPORTED and b["degree"] not in (5, 6, 7)
+        for tile, degrees in ((8, (5, 6, 7, 8)), (9, (1, 2))):
+            out = torch.full_like(b["values"], float("nan"))
+            try:
+                api.fe_cell_kernels_tile(b["desc"], b["form_buf"], b["mesh"], out, tile)
+                torch.cuda.synchronize()
+                ref8 = _oracle_block(blk).reshape(-1)
+                got = out[:ref8.size].double().cpu().numpy()
+                err = np.linalg.norm(got - ref8) / np.linalg.norm(ref8)
+                say(f"  p{b['degree']}: tile {tile} err {err:.2e}")
+                assert err <= 1e-3, (b["degree"], tile, err)
+            except api.L.FeError as e:
+                assert e.status == L.FE_EUNSUPPORTED and b["degree"] not in degrees, (b["degree"], tile)
         ref = None
         for tile in range(8):
             out = torch.full_like(b["values"], float("nan"))
@@ -115,7 +117,7 @@ def test_tiles_are_bitwise_identical_and_tuner_picks_one():
         assert ref is not None
     tuned = md.tune(reps=2)
     for deg, tile, times in tuned:
-        assert 0 <= tile < 9 and times[tile] > 0, (deg, tile, times)
+        assert 0 <= tile < 10 and times[tile] > 0, (deg, tile, times)
         assert times[tile] == min(t for t in times if t >= 0)
         say(f"  p{deg}: tile {tile}, ms {['%.4f' % t for t in times]}")
 
