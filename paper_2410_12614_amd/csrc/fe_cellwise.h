@@ -269,33 +269,21 @@ __device__ __forceinline__ f32x4_t agpr_tile_scaled(const f32x4_t &x, float s) {
 
 constexpr int CW_ZMAX = 512;  // points of a coefficient form (n_q_pad) the LDS row holds
 
-// Column ranges: a launch may compute only the tiles (I, J) with
-// J0 <= J < J1 (and I <= J), so that a form whose MT (MT + 1) / 2 tiles do
-// not fit the accumulator registers (P8 mass: 66) runs as two launches over
-// the same cells; such a launch loads only the row tiles below J1 (mass
-// forms: a prefix of each chunk) and stores tile by tile.
-template <int MT, int J0, int J1>
-__device__ __forceinline__ constexpr int range_index(int I, int J) {
-  return (J * (J + 1) - J0 * (J0 + 1)) / 2 + I;
-}
+// Accumulator of the symmetric tile (I, J), I <= J, column by column.
+__device__ __forceinline__ constexpr int tile_index(int I, int J) { return J * (J + 1) / 2 + I; }
 
-template <int MT, int NDT, bool COEFF, int NW, int J0 = 0, int J1 = MT>
+template <int MT, int NDT, bool COEFF, int NW>
 __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
-  constexpr bool FULL = J0 == 0 && J1 == MT;
-  static_assert(FULL || NDT == 1, "column ranges of a chunk are contiguous for one slab only");
   constexpr int NT = NW * 64;
-  constexpr int NP = (J1 * (J1 + 1) - J0 * (J0 + 1)) / 2;
-  constexpr int MTL = J1;                     // row tiles loaded per slab
-  constexpr int CH16 = NDT * MTL * 64;        // 16-byte pieces of one chunk loaded (a multiple of 64)
-  constexpr int CHS = NDT * MT * 64;          // pieces of one chunk of the table
+  constexpr int NP = MT * (MT + 1) / 2;
+  constexpr int CH16 = NDT * MT * 64;        // 16-byte pieces of one chunk (a multiple of 64)
   constexpr int PRE = (CH16 + NT - 1) / NT;  // direct loads per wave and chunk
   static_assert(CH16 >= NT, "a chunk covers every thread at least once");
   __shared__ uint4 ring0[CH16], ring1[CH16], ring2[CH16];
-  // a wave's row block (16 rows x n_phi) for the whole-matrix stores, or its
-  // tile-transpose buffer for the stores by tiles
-  __shared__ float4 rbuf[NW][FULL ? 16 * MT * 4 : 16 * 5];
+  // a wave's row block (16 rows x n_phi)
+  __shared__ float4 rbuf[NW][16 * MT * 4];
   __shared__ float zbuf[COEFF ? NW : 1][COEFF ? CW_ZMAX : 4];
-  extern __shared__ float wl[];              // quadrature weights [n_q_pad]
+  extern __shared__ float wl[];  // quadrature weights [n_q_pad]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int c = lane & 15, kb = lane >> 4;
   const int nphi = a.n_phi, n_q_pad = a.n_q_pad;
@@ -321,7 +309,7 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
   auto fill = [&](int tc, auto sl) {
     constexpr int S = decltype(sl)::value;
     uint4 *to = S == 0 ? ring0 : S == 1 ? ring1 : ring2;
-    const uint4 *from = src + (size_t)tc * CHS;
+    const uint4 *from = src + (size_t)tc * CH16;
 #pragma unroll
     for (int p = 0; p < PRE; ++p) {
       int e0 = p * NT + wave * 64;  // wave-uniform
@@ -403,13 +391,13 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
         fill(g + 2 < total ? fc : 0, slot_t<(S + 2) % 3>());
       }
       // the chunk's fragments
-      half8_t F[NDT][MTL];
+      half8_t F[NDT][MT];
 #pragma unroll
       for (int s = 0; s < NDT; ++s)
 #pragma unroll
-        for (int mt = 0; mt < MTL; ++mt) {
-          const uint4 u = cur[(s * MTL + mt) * 64 + lane];
-          F[s][mt] = *reinterpret_cast<const half8_t *>(&u);
+        for (int mt = 0; mt < MT; ++mt) {
+          const uint4 v = cur[(s * MT + mt) * 64 + lane];
+          F[s][mt] = *reinterpret_cast<const half8_t *>(&v);
         }
       // this lane's eight points: w z scaled, rounded in pairs
       const float *w8 = wl + qc * 32 + 8 * kb;
@@ -432,7 +420,7 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
 #pragma unroll
           for (int p = 0; p < 4; ++p) cst[t][p] = wz[p] * cf.g2[NDT == 1 ? 0 : sym_comp(s, t)];
 #pragma unroll
-        for (int J = J0; J < J1; ++J) {
+        for (int J = 0; J < MT; ++J) {
           half8_t h;
 #pragma unroll
           for (int p = 0; p < 4; ++p) {
@@ -445,8 +433,8 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
           }
 #pragma unroll
           for (int I = 0; I <= J; ++I)
-            acc[range_index<MT, J0, J1>(I, J)] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                F[s][I], h, acc[range_index<MT, J0, J1>(I, J)], 0, 0, 0);
+            acc[tile_index(I, J)] =
+                __builtin_amdgcn_mfma_f32_16x16x32_f16(F[s][I], h, acc[tile_index(I, J)], 0, 0, 0);
         }
       }
       // chunk g + 1 (loaded during chunk g - 1) and the next coefficient
@@ -474,7 +462,7 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
       load_rec(ce_next, rn0, rn1);
       load_z(ce_next);
     }
-    if (valid && FULL) {
+    if (valid) {
       if (!COEFF && !cf.ok && lane == 0) atomicOr(a.status, STATUS_DEGENERATE);
       // the forms with fewer than 11 row tiles have n_phi a multiple of
       // four (rows of whole float4s); with 11 (n_phi = 165) the rows are
@@ -513,8 +501,8 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
           const int I = v4 ? ii : ii == 0 ? MT - 1 : ii - 1;
           if (I <= J) {
             // tile (I, J): lane holds A(16 I + 4 kb + r, 16 J + c) = A(16 J + c, 16 I + 4 kb + r)
-            const f32x4_t v = v4 ? acc[range_index<MT, J0, J1>(I, J)] * inv
-                                 : agpr_tile_scaled(acc[range_index<MT, J0, J1>(I, J)], inv);
+            const f32x4_t v = v4 ? acc[tile_index(I, J)] * inv
+                                 : agpr_tile_scaled(acc[tile_index(I, J)], inv);
             const int col = 16 * I + 4 * kb;
             if (v4) {
               if (col < np) *(float4 *)(rb + c * np + col) = float4{v[0], v[1], v[2], v[3]};
@@ -524,8 +512,8 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
             }
           } else {
             // tile (J, I): lane holds A(16 J + 4 kb + r, 16 I + c)
-            const f32x4_t v = v4 ? acc[range_index<MT, J0, J1>(J, I)] * inv
-                                 : agpr_tile_scaled(acc[range_index<MT, J0, J1>(J, I)], inv);
+            const f32x4_t v = v4 ? acc[tile_index(J, I)] * inv
+                                 : agpr_tile_scaled(acc[tile_index(J, I)], inv);
             const int col = 16 * I + c;
             if (v4) {
               if (col < np)
@@ -569,55 +557,13 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
       }
     }
-    if (valid && !FULL) {
-      // tile by tile: M(y, x) = A(16 I + y, 16 J + x) into the wave's LDS
-      // tile, then rows 16 J + x (columns 16 I + y) and, off the diagonal,
-      // rows 16 I + y (columns 16 J + x), four rows of 16 consecutive
-      // columns per store (any n_phi)
-      if (J0 == 0 && !cf.ok && lane == 0) atomicOr(a.status, STATUS_DEGENERATE);
-      // (n_phi passed through an empty asm so that the store offsets are
-      // formed here, per cell, instead of being kept live across the walk)
-      int np = nphi;
-      asm volatile("" : "+s"(np));
-      float *A = a.A + ce * (int64_t)np * np;  // wave-uniform
-      constexpr int TS = 20;
-      const int lx = lane & 15, ly = lane >> 4;
-#pragma unroll
-      for (int J = J0; J < J1; ++J)
-#pragma unroll
-        for (int I = 0; I <= J; ++I) {
-          const f32x4_t v = acc[range_index<MT, J0, J1>(I, J)] * cf.inv;
-          // (the wave's own LDS accesses complete in order; the fences keep
-          // the compiler from moving them across one another)
-          __atomic_signal_fence(__ATOMIC_SEQ_CST);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) rb[(4 * kb + r) * TS + c] = v[r];
-          __atomic_signal_fence(__ATOMIC_SEQ_CST);
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int x = 4 * k + ly;  // direct: row 16 J + x, column 16 I + lx
-            const float w = rb[lx * TS + x];
-            const int row = 16 * J + x, col = 16 * I + lx;
-            if (row < np && col < np) A[row * np + col] = w;
-          }
-          if (I != J)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const int y = 4 * k + ly;  // mirror: row 16 I + y, column 16 J + lx
-              const float w = rb[y * TS + lx];
-              const int row = 16 * I + y, col = 16 * J + lx;
-              if (row < np && col < np) A[row * np + col] = w;
-            }
-        }
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    }
   }
 }
 
-template <int MT, int NDT, bool COEFF, int NW, int J0 = 0, int J1 = MT>
+template <int MT, int NDT, bool COEFF, int NW>
 static fe_status launch_cellwise_one(const CellwiseLaunch &c, const CwArgs &k) {
-  auto kern = cellwise_kernel<MT, NDT, COEFF, NW, J0, J1>;
-  // dynamic: the quadrature weights (the ring and the transpose buffers are
+  auto kern = cellwise_kernel<MT, NDT, COEFF, NW>;
+  // dynamic: the quadrature weights (the ring and the row-block buffers are
   // static)
   const size_t smem = (size_t)c.L->n_q_pad * sizeof(float);
   LaunchInfo li;

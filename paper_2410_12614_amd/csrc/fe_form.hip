@@ -298,7 +298,7 @@ bool fused_eligible(const FormLayout &L) {
 bool cellwise_eligible(const FormLayout &L) {
   if (L.prec != FE_FP16_ACC32 || L.box || L.d != 3) return false;
   if (L.ndt == 3) return L.mt == 6 && L.n_phi % 4 == 0 && L.n_q_pad <= 512;
-  // (11 row tiles: two launches over column ranges, stored tile by tile)
+  // (11 row tiles: rows packed at any n_phi)
   return !L.has_coeff && (((L.mt == 4 || L.mt == 6 || L.mt == 8) && L.n_phi % 4 == 0) || L.mt == 11);
 }
 

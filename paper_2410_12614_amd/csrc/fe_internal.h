@@ -133,8 +133,8 @@ struct CellwiseLaunch {
 };
 // Forms the whole-cell kernel is compiled for: FP16 storage, tetrahedra,
 // the Poisson form with 6 row tiles (P6) or the mass form with 4, 6 or 8
-// (P5..P7), n_phi a multiple of four, or the mass form with 11 (P8); a
-// coefficient only with the Poisson form.
+// (P5..P7), n_phi a multiple of four, or with 11 (P8); a coefficient only
+// with the Poisson form.
 bool cellwise_eligible(const FormLayout &L);
 fe_status launch_cellwise_fp16(const CellwiseLaunch &c);
 

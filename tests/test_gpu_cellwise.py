@@ -1,8 +1,8 @@
 """The whole-cell FP16 kernel (one wave per cell, symmetric tiles, B^T
 fragments shared through an LDS ring): local matrices of the forms it is
 compiled for against the FP64 oracle (tile 8 of fe_cell_kernels_tile:
-mass P5..P8 (P8 as two launches over column ranges, n_phi = 165 not a
-multiple of four), Poisson P6; the Poisson P6 form with a coefficient through
+mass P5..P8 (P8 with rows packed at n_phi = 165, not a multiple of
+four), Poisson P6; the Poisson P6 form with a coefficient through
 FE_NUMERIC, where the coefficient at the points goes to the workspace), the
 entrywise rounding-error bound of the FP16 mode, ragged batches, degenerate
 cells and the two halves of the gather path."""
