@@ -164,6 +164,7 @@ class Assembly:
             self.mats[k].values = self.values[k].data_ptr()
         check(fe_assemble_csr(self.descs, self.form_bufs, mesh, L.FE_SYMBOLIC_FILL, self.mats,
                               self.plan, None, stream), "fe_assemble_csr(FILL)")
+        self.graph = None
 
     def numeric(self, gather: bool = False, part: Optional[str] = None) -> list:
         """FE_NUMERIC (fused row-ownership path where it applies) or, with
@@ -176,6 +177,26 @@ class Assembly:
                      "local": L.FE_NUMERIC_LOCAL, "assemble": L.FE_NUMERIC_ASSEMBLE}[part]
         check(fe_assemble_csr(self.descs, self.form_bufs, self.mesh, phase, self.mats,
                               self.plan, self.workspace, self.stream), "fe_assemble_csr(NUMERIC)")
+        return self.values
+
+    def capture(self, gather: bool = False, part: Optional[str] = None) -> None:
+        """Record numeric(gather, part) as one HIP graph (the numeric phases
+        launch kernels only: no copies, fills or synchronisations), which
+        replay() then runs; on torch's current stream, so the assembly's
+        own stream must be the default (None)."""
+        if self.stream is not None:
+            raise ValueError("capture() records on torch's current stream; the assembly has its own")
+        self.numeric(gather, part)           # first launches outside the capture
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.numeric(gather, part)
+        self.graph = g
+
+    def replay(self) -> list:
+        if self.graph is None:
+            raise RuntimeError("replay() before capture()")
+        self.graph.replay()
         return self.values
 
     def numeric_noalloc(self) -> list:
