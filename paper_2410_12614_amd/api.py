@@ -374,7 +374,12 @@ class MixedDegree:
     block, each writing its cells' local matrices into its slice of the CSR
     values; ``tune()`` picks every block's tile with fe_tune_cell_kernels and
     ``capture()`` records the calls of all blocks in one HIP graph, so that
-    ``numeric()`` is a single graph launch."""
+    ``numeric()`` is a single graph launch.  In the graph the blocks can run
+    on several streams (``groups``: lists of degrees, one stream each, a
+    fork and a join): the small blocks' kernels then share the compute
+    units with the large blocks' kernels, which leave registers and LDS free
+    (one wave per SIMD at P7 and P8); the blocks write disjoint slices of
+    the values."""
 
     def __init__(self, blocks, form: str = "mass", precision: str = "fp16", stream=None):
         self.stream = stream
@@ -409,19 +414,45 @@ class MixedDegree:
         return out
 
     def numeric_eager(self) -> torch.Tensor:
-        for b in self.blocks:
+        self._launch(self.blocks)
+        return self.values
+
+    def _launch(self, blocks) -> None:
+        for b in blocks:
             if b["mesh"].n_cells > 0:
                 fe_cell_kernels_tile(b["desc"], b["form_buf"], b["mesh"], b["values"], b["tile"],
                                      self.stream)
-        return self.values
 
-    def capture(self) -> None:
+    def capture(self, groups=((6, 7, 8), (1, 2, 3, 4, 5))) -> None:
+        """Record the blocks' calls in one graph: the blocks of groups[0] on
+        torch's current stream, each further group on a stream of its own
+        that forks from it and joins it again, each group's blocks in the
+        order of its degrees; degrees in no group run last on the current
+        stream, and one group (or an own stream of the assembly, which the
+        library must launch on) means one stream."""
         self.numeric_eager()                 # first launches outside the capture
         torch.cuda.synchronize()
+        placed = {d for grp in groups for d in grp}
+        parts = [[b for d in grp for b in self.blocks if b["degree"] == d] for grp in groups]
+        parts[0] += [b for b in self.blocks if b["degree"] not in placed]
+        parts = [p for p in parts if p]
+        fork = self.stream is None and len(parts) > 1
+        sides = [torch.cuda.Stream() for _ in parts[1:]] if fork else []
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            self.numeric_eager()
+            if fork:
+                main = torch.cuda.current_stream()
+                for s, p in zip(sides, parts[1:]):
+                    s.wait_stream(main)
+                    with torch.cuda.stream(s):
+                        self._launch(p)
+                self._launch(parts[0])
+                for s in sides:
+                    main.wait_stream(s)
+            else:
+                self.numeric_eager()
         self.graph = g
+        self._sides = sides
 
     def numeric(self) -> torch.Tensor:
         if self.graph is None:

@@ -122,12 +122,16 @@ def test_tiles_are_bitwise_identical_and_tuner_picks_one():
         say(f"  p{deg}: tile {tile}, ms {['%.4f' % t for t in times]}")
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("groups", [((1, 2, 3, 4, 5, 6, 7, 8),), ((6, 7, 8), (1, 2, 3, 4, 5)),
+                                    ((8,), (7, 6), (1, 2, 3, 4, 5))])
+def test_graph_replays_match_eager(groups):
+    # one stream, or the degree groups on two or three streams of the graph
+    # (forks and joins)
     blocks = small_blocks()
     md = _md(blocks, "fp16")
     md.tune(reps=1)
     eager = md.numeric_eager().clone()
-    md.capture()
+    md.capture(groups)
     for rep in range(3):
         md.values.fill_(float("nan"))         # eager work between replays
         torch.cuda.synchronize()
