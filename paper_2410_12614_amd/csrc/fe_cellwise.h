@@ -484,12 +484,6 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
         // boundary in global memory (whole float4s on both sides)
         float *blk = A + 16 * J * np;
         float *rs = v4 ? rb : rb + (int)(((uintptr_t)blk >> 2) & 3);
-        // the scale as a new value per row block (an empty asm), so that a
-        // tile's two scaled copies (mirror in row block I, direct in row
-        // block J) are formed where they are stored, not kept in VGPRs
-        // from the first to the second
-        float inv = cf.inv;
-        asm volatile("" : "+v"(inv));
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
         for (int ii = 0; ii < MT; ++ii) {
@@ -501,8 +495,8 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
           const int I = v4 ? ii : ii == 0 ? MT - 1 : ii - 1;
           if (I <= J) {
             // tile (I, J): lane holds A(16 I + 4 kb + r, 16 J + c) = A(16 J + c, 16 I + 4 kb + r)
-            const f32x4_t v = v4 ? acc[tile_index(I, J)] * inv
-                                 : agpr_tile_scaled(acc[tile_index(I, J)], inv);
+            const f32x4_t v = v4 ? acc[tile_index(I, J)] * cf.inv
+                                 : agpr_tile_scaled(acc[tile_index(I, J)], cf.inv);
             const int col = 16 * I + 4 * kb;
             if (v4) {
               if (col < np) *(float4 *)(rb + c * np + col) = float4{v[0], v[1], v[2], v[3]};
@@ -512,8 +506,8 @@ __global__ __launch_bounds__(NW * 64) void cellwise_kernel(CwArgs a) {
             }
           } else {
             // tile (J, I): lane holds A(16 J + 4 kb + r, 16 I + c)
-            const f32x4_t v = v4 ? acc[tile_index(J, I)] * inv
-                                 : agpr_tile_scaled(acc[tile_index(J, I)], inv);
+            const f32x4_t v = v4 ? acc[tile_index(J, I)] * cf.inv
+                                 : agpr_tile_scaled(acc[tile_index(J, I)], cf.inv);
             const int col = 16 * I + c;
             if (v4) {
               if (col < np)
