@@ -298,8 +298,11 @@ bool fused_eligible(const FormLayout &L) {
 bool cellwise_eligible(const FormLayout &L) {
   if (L.prec != FE_FP16_ACC32 || L.box || L.d != 3) return false;
   if (L.ndt == 3) return L.mt == 6 && L.n_phi % 4 == 0 && L.n_q_pad <= 512;
-  // (11 row tiles: rows packed at any n_phi)
-  return !L.has_coeff && (((L.mt == 4 || L.mt == 6 || L.mt == 8) && L.n_phi % 4 == 0) || L.mt == 11);
+  // (11 row tiles: rows packed at any n_phi up to 175, the most whose row
+  // block, staged up to three floats into the LDS buffer of 16 x 176 floats
+  // with the last tile column's overhang, fits it; P8 has 165)
+  return !L.has_coeff && (((L.mt == 4 || L.mt == 6 || L.mt == 8) && L.n_phi % 4 == 0) ||
+                          (L.mt == 11 && L.n_phi <= 175));
 }
 
 fe_status launch_info(const void *kern, int threads, size_t smem, LaunchInfo *out) {
