@@ -81,10 +81,14 @@ struct CwRec {
 // z_K(X_q) = sum_k z_{dof(K,k)} phi_k(X_q) for every cell, as a batched
 // product (n_q x n_phi) (n_phi x cells) on the FP32 matrix cores
 // (16 x 16 x 4): each wave takes 16 NG cells along N, the value table
-// phi_k(X_q) is the left operand (rows q).  Writes z [n_cells][n_q_pad]
-// (zero past n_q) and max_q |z_K(X_q)| per cell, and then, one lane per
-// cell, the cell's factors for the whole-cell kernel (FP64 geometry, the
-// scales of H; a degenerate cell raises the status flag).
+// phi_k(X_q) is the left operand (rows q).  The four waves of a workgroup
+// walk the same 16-point tiles of the table, which they stage in LDS
+// together (coalesced loads into registers, written after the current
+// tile's products; two LDS buffers, one barrier per tile).  Writes z
+// [n_cells][n_q_pad] (zero past n_q) and max_q |z_K(X_q)| per cell, and
+// then, one lane per cell, the cell's factors for the whole-cell kernel
+// (FP64 geometry, the scales of H; a degenerate cell raises the status
+// flag).
 template <int KS, int NG>
 __global__ __launch_bounds__(256) void k_coeff_points(const float *vtab, const int32_t *dofmap,
                                                       const double *coeff, int64_t n_cells,
@@ -92,10 +96,14 @@ __global__ __launch_bounds__(256) void k_coeff_points(const float *vtab, const i
                                                       const FormHeader *hdr, const double *coords,
                                                       int d, float *zpt, float *zmax, CwRec *rec,
                                                       int32_t *status) {
+  constexpr int TW = 4 * KS;                 // table row width in LDS (n_phi padded)
+  constexpr int TP = (16 * TW + 255) / 256;  // staged values per thread and tile
+  __shared__ float vt[2][16 * TW];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c = lane & 15, kb = lane >> 4;
   const int64_t cell0 = ((int64_t)blockIdx.x * 4 + wave) * 16 * NG;
-  if (cell0 >= n_cells) return;
+  // (a wave past the cells still stages its share and meets the barriers)
+  const bool active = cell0 < n_cells;
   // right operands: this lane's cell (column c) at the K entries 4 ks + kb
   float zk[NG][KS];
 #pragma unroll
@@ -116,22 +124,38 @@ __global__ __launch_bounds__(256) void k_coeff_points(const float *vtab, const i
   float zm[NG];
 #pragma unroll
   for (int g = 0; g < NG; ++g) zm[g] = 0.0f;
-  // left operands of q tile qt (row 16 qt + c, K entries 4 ks + kb), the
-  // next tile's loaded while the current one is contracted
-  auto load_a = [&](int qt, float (&av)[KS]) {
-    const int q = 16 * qt + c;
+  // table tile qt (rows 16 qt .. + 15, entries [row][k], zero past n_q and
+  // n_phi): this thread's values, then into LDS buffer b
+  auto load_t = [&](int qt, float (&pv)[TP]) {
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int k = 4 * ks + kb;
-      av[ks] = (q < n_q && k < n_phi) ? vtab[(size_t)q * n_phi + k] : 0.0f;
+    for (int p = 0; p < TP; ++p) {
+      const int e = p * 256 + (int)threadIdx.x;
+      const int r = e / TW, k = e - r * TW;
+      const int q = 16 * qt + r;
+      pv[p] = (e < 16 * TW && q < n_q && k < n_phi) ? vtab[(size_t)q * n_phi + k] : 0.0f;
+    }
+  };
+  auto put_t = [&](int b, const float (&pv)[TP]) {
+#pragma unroll
+    for (int p = 0; p < TP; ++p) {
+      const int e = p * 256 + (int)threadIdx.x;
+      if (e < 16 * TW) vt[b][e] = pv[p];
     }
   };
   const int nqt = n_q_pad / 16;
-  float av[KS];
-  load_a(0, av);
+  {
+    float pv[TP];
+    load_t(0, pv);
+    put_t(0, pv);
+  }
+  __syncthreads();
   for (int qt = 0; qt < nqt; ++qt) {
-    float an[KS];
-    if (qt + 1 < nqt) load_a(qt + 1, an);
+    float pn[TP];
+    if (qt + 1 < nqt) load_t(qt + 1, pn);
+    // left operands of tile qt: row 16 qt + c, K entries 4 ks + kb
+    float av[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) av[ks] = vt[qt & 1][c * TW + 4 * ks + kb];
     f32x4_t acc[NG];
 #pragma unroll
     for (int g = 0; g < NG; ++g) acc[g] = f32x4_t{0, 0, 0, 0};
@@ -150,10 +174,12 @@ __global__ __launch_bounds__(256) void k_coeff_points(const float *vtab, const i
 #pragma unroll
       for (int r = 0; r < 4; ++r) zm[g] = fmaxf(zm[g], fabsf(acc[g][r]));
     }
-    if (qt + 1 < nqt)
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) av[ks] = an[ks];
+    // the next tile into the other buffer (last read in tile qt - 1, which
+    // every wave finished before the barrier that closed it)
+    if (qt + 1 < nqt) put_t((qt + 1) & 1, pn);
+    __syncthreads();
   }
+  if (!active) return;
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
     float m = zm[g];
